@@ -1,0 +1,74 @@
+"""Pins of the oracle's D2Q5 potential solver, Eqs. (31)-(34) with anti-bounce-back at the
+electrodes: the textbook solutions of div(sigma grad phi) = 0 it must reproduce."""
+import numpy as np
+import pytest
+from scipy.integrate import cumulative_trapezoid
+
+from oracle.binding import Oracle
+from paper_2410_06657_amd import inputs
+
+
+def _uniform_case(nx, ny):
+    c = inputs.base_params(nx, ny)
+    c.update(shape=1, h0=-100.0, T_w=0.5, T_g=0.5)  # all gas, no freezing
+    return c
+
+
+def test_linear_profile_is_an_exact_fixed_point():
+    """Uniform sigma: the linear profile between the electrodes (walls half a link outside the
+    edge nodes) is a steady state of the sweeps, to round-off."""
+    c = _uniform_case(8, 16)
+    o = Oracle(c)
+    rc, k, r = o.solve_potential(-1.0, 500)
+    phi = o.field("phi")
+    j = np.arange(16)
+    np.testing.assert_allclose(phi, np.broadcast_to(((j + 0.5) / 16)[:, None], phi.shape), atol=2e-15)
+
+
+def test_layered_conductivity_matches_series_resistance():
+    """sigma(y) only: the current sigma dphi/dy is uniform, so phi(y) follows the integral of
+    1/sigma.  Second-order scheme on a smooth (tanh, W = 4) profile: within 2e-3."""
+    ny = 64
+    c = inputs.stefan_strip(4, ny, h0=24.0, Ste=0.0)
+    c.update(T_w=0.5, T_g=0.5, rho_s=1.0)
+    inputs.set_electric(c, R=5.0, S=1.0, Ca_E=0.0, R0=1.0)
+    c.update(poisson_tol=1e-13, poisson_max_sweeps=400000)
+    o = Oracle(c)
+    phi = o.field("phi")[:, 0]
+    psi = o.field("psi")[:, 0]
+    sig = psi * c["sig_l"] + (1 - psi) * c["sig_g"]
+    # integrate 1/sigma from the wall at y=-1/2 to y=ny-1/2 with node values (midpoint cells)
+    y = np.arange(ny)
+    inv = 1 / sig
+    cum = np.concatenate([[0.0], np.cumsum(inv)])  # cell-centred: node j spans [j-1/2, j+1/2]
+    exact = (cum[:-1] + 0.5 * inv) / cum[-1]
+    assert np.max(np.abs(phi - exact)) < 2e-3
+
+
+@pytest.mark.parametrize("R", [3.0, 0.5])
+def test_circular_inclusion_field(R):
+    """A cylinder of conductivity ratio R in a uniform field E0: the field inside is uniform
+    and E_in = 2 E0 / (1 + R) (2D textbook solution).  Diffuse interface W = 4, R0 = 12 in a
+    96 x 96 box: the error of the diffuse interface is first order in W/R0 and the image
+    error ~ (R0/L)^2 (measured 6.9% at R = 3 and shrinking with both), so the bound is 8%."""
+    n = 96
+    c = inputs.free_drop(n, n, 12.0, R=R, S=1.0, Ca_E=0.0)
+    c.update(poisson_tol=1e-11, poisson_max_sweeps=400000)
+    o = Oracle(c)
+    phi = o.field("phi")
+    yc, xc = int(c["yc"]), int(c["xc"])
+    Ein = (phi[yc + 3, xc] - phi[yc - 3, xc]) / 6  # |E| = dphi/dy (E = -grad phi points down)
+    E0 = 1.0 / n
+    assert Ein / E0 == pytest.approx(2 / (1 + R), rel=0.08)
+    assert (Ein < E0) == (R > 1)  # a better conductor screens the field, a worse one focuses it
+
+
+def test_stop_rule_and_cap():
+    c = inputs.cfg1(0)
+    c.update(nx=32, ny=16, R0=6.0, xc=16.0)
+    o = Oracle(c, init=False)
+    o.init()
+    rc, k, r = o.solve_potential(1e-30, 3)
+    assert rc == -2 and k == 3  # cap reached: not converged
+    rc, k, r = o.solve_potential(-1.0, 5)
+    assert rc == 0 and k == 5  # negative tolerance: fixed count
