@@ -1,0 +1,174 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) electrofreezing lattice Boltzmann library.
+ *
+ * The library advances the coupled phase-field lattice Boltzmann method of
+ * Huang, Li, Che, Chai, Wang, Shi, "Freezing dynamics of wetting droplet under a
+ * uniform electric field" (arXiv:2410.06657) on one GPU:
+ *   - f, D2Q9: conservative Allen-Cahn phase field psi with the freezing volume
+ *     source (Sec. 3.1, Eqs. (15)-(20));
+ *   - h, D2Q9: pressure and velocity with the mass source and the diffuse solid
+ *     force (Sec. 3.2, Eqs. (21)-(27));
+ *   - g, D2Q9: total (volumetric) enthalpy, temperature and solid fraction
+ *     (Sec. 3.3, Eqs. (28)-(30), inversion Eq. (7));
+ *   - l, D2Q5: electric potential of the leaky-dielectric model, swept to
+ *     convergence inside every time step (Sec. 3.4, Eqs. (31)-(34), Algorithm 1);
+ *   - the coupling terms: isotropic gradients and Laplacians (Eq. (36)), surface
+ *     tension (Eqs. (3)-(5)), electric force (Eq. (14)), property mixing (Eq. (1)).
+ *
+ * Grid and layout.  Nodes (i, j), 0 <= i < nx (periodic), 0 <= j < ny, at x = i,
+ * y = j.  Half-way walls at y = -1/2 (cooled substrate, lower electrode) and
+ * y = ny - 1/2 (upper electrode).  Host arrays exchanged through this ABI are
+ * FP64, row-major [j][i] for fields and [q][j][i] for populations (q in the
+ * order rest, E, N, W, S, NE, NW, SW, SE for D2Q9 and rest, E, N, W, S for D2Q5).
+ * Temperatures are measured from the melting point (T_m = 0).
+ *
+ * Memory ownership.  The caller allocates one device workspace of
+ * lbm_workspace_bytes() bytes and owns it and the stream; the library carves
+ * every device array out of that workspace and never allocates or frees device
+ * memory.  It owns the small host-side handle (and a few bytes of pinned host
+ * memory for flag read-back).  Host pointers passed in are borrowed for the
+ * duration of the call only.  A handle is used by one host thread at a time.
+ *
+ * Errors.  Every function returns LBM_OK (0) or a negative code; no C++
+ * exception crosses the ABI.  lbm_strerror() names a code; after LBM_EHIP the
+ * HIP error string of the last failing call is kept in the handle and returned
+ * by lbm_last_error().
+ */
+#ifndef LBM_ABI_INCLUDED
+#define LBM_ABI_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* bad argument or parameter value */
+#define LBM_ENOCONV (-2)    /* potential sweeps hit the cap before the stopping test */
+#define LBM_ENONFINITE (-3) /* NaN or Inf found by the diagnostics */
+#define LBM_EHIP (-4)       /* a HIP runtime call failed */
+#define LBM_ESTATE (-5)     /* call out of order (e.g. step before init) */
+#define LBM_ESPACE (-6)     /* workspace smaller than lbm_workspace_bytes() */
+
+/* Arithmetic and storage of the populations. */
+#define LBM_FP64 0
+
+/* Reading switches (bits of lbm_params.readings). */
+#define LBM_R_GRAD_S 1u /* F~ of Eq. (24) contains c_s^2 grad(S) (the printed "div S") */
+
+/* Case parameters, lattice units.  Properties of the three phases are mixed by
+   Eq. (1) with psi clamped to [0, 1]. */
+typedef struct lbm_params {
+    int nx, ny;
+    int precision;              /* LBM_FP64 */
+    double W, M, gamma;         /* interface width, mobility (Eq. (2a)), surface tension */
+    double rho_l, rho_g, rho_s; /* densities */
+    double mu_l, mu_g, mu_s;    /* dynamic viscosities */
+    double cp_l, cp_g, cp_s;    /* specific heat per unit mass */
+    double k_l, k_g, k_s;       /* thermal conductivities */
+    double latent;              /* latent heat per unit mass */
+    double T_w, T_g;            /* substrate temperature, initial temperature */
+    double eps_l, eps_g, eps_s; /* permittivities */
+    double sig_l, sig_g, sig_s; /* electric conductivities */
+    double phi_top, phi_bot;    /* electrode potentials */
+    double theta_deg;           /* contact angle at the substrate */
+    int shape;                  /* initial interface: 0 disc (R0, xc, yc), 1 layer of thickness h0 */
+    double R0, xc, yc, h0;
+    double poisson_tol;         /* relative sweep-to-sweep change that ends a solve; < 0: fixed count */
+    int poisson_max_sweeps;     /* cap per solve */
+    unsigned readings;          /* LBM_R_* bits */
+} lbm_params;
+
+/* Scalar fields for lbm_get_field / lbm_set_field. */
+enum {
+    LBM_PSI = 0, LBM_UX, LBM_UY, LBM_USX, LBM_USY, LBM_P, LBM_T, LBM_H,
+    LBM_FS, LBM_MDOT, LBM_PSIU_X, LBM_PSIU_Y, LBM_PHI, LBM_FL,
+    LBM_NFIELDS
+};
+/* Population sets for lbm_get_pop / lbm_set_pop. */
+enum { LBM_POP_F = 0, LBM_POP_H = 1, LBM_POP_G = 2, LBM_POP_L = 3 };
+
+/* Global output of Algorithm 1, all reductions in FP64. */
+typedef struct lbm_diag {
+    long long step;
+    double sum_psi, sum_f, sum_g; /* sums of psi and of the f and g populations */
+    double V_l, V_s;              /* sum of psi f_l (liquid volume) and of f_s */
+    double front_y;               /* f_l = 1/2 crossing on column nx/2, from the wall */
+    double height;                /* psi = 1/2 crossing on column nx/2, from the wall */
+    double max_u;                 /* max |u| */
+    double resid;                 /* relative change at the last potential sweep */
+    int sweeps;                   /* sweeps of the last potential solve */
+    int noconv;                   /* solves inside lbm_step that hit the cap */
+    double t_fre;                 /* freezing step: V_l first <= 1% of V_l0, interpolated; -1 if not yet */
+    double V_l0;                  /* V_l at initialisation */
+    int nonfinite;                /* 1 if psi, u, p, T or phi holds NaN/Inf */
+} lbm_diag;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device workspace needed by lbm_init for these parameters.
+   LBM_EINVAL on bad parameters (tau <= 1/2 cannot occur: every relaxation time
+   is 1/2 plus a positive transport coefficient, so positivity is what is checked). */
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Initialise (Algorithm 1, first block): psi from the tanh profile of the initial
+   shape, u = u* = p = 0, T = T_g in fully liquid drops, phi a linear ramp between
+   the electrodes, every population at its equilibrium (Eqs. (18), (22), (29), (32)),
+   then one potential solve (at least two sweeps: a first sweep of equilibrium
+   populations leaves a linear ramp unchanged).  `workspace` is a device pointer
+   to at least lbm_workspace_bytes() bytes, 256-byte aligned; `stream` is a
+   hipStream_t (NULL = the null stream).  Work is queued on the stream; the call
+   returns after the initial solve has converged (it reads the convergence flag). */
+int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream,
+             lbm_handle** out);
+
+/* n full time steps of Algorithm 1 in the order f (collide, stream, bounce-back,
+   wetting) -> psi, rho, F_s -> potential swept to convergence -> phi, F_e ->
+   h (collide, stream, bounce-back) -> u, p -> g (collide, stream, substrate at T_w)
+   -> T, f_l, f_s.  Kernels run on the handle's stream; the host reads the
+   potential's convergence flag once per batch of sweeps.  A solve that hits the
+   sweep cap leaves a valid state and is counted in lbm_diag.noconv. */
+int lbm_step(lbm_handle* h, int n);
+
+/* Sweep the potential (Eqs. (31)-(34)) with the current psi and f_s until the
+   relative change ||phi^k - phi^{k-1}||_2 / ||phi^k||_2 <= tol (tol < 0: exactly
+   max_sweeps sweeps).  Returns the sweep count and the last relative change;
+   LBM_ENOCONV if the cap was reached first (the state stays valid). */
+int lbm_solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps,
+                        double* resid);
+
+/* FP64 reductions of the current state into *out; synchronises the stream. */
+int lbm_diagnostics(lbm_handle* h, lbm_diag* out);
+
+/* Copy one field (nx*ny doubles) or one population set (nq*nx*ny doubles) between
+   the device state and a host array; synchronise the stream.  nq is 9 for f, h, g
+   and 4 for l: the D2Q5 rest link relaxes towards (w_0 - 1) phi but never enters
+   phi (Eq. (34) sums links 1-4 only) nor the other links' collision, so it is
+   not kept. */
+int lbm_get_field(lbm_handle* h, int field, double* dst);
+int lbm_set_field(lbm_handle* h, int field, const double* src);
+int lbm_get_pop(lbm_handle* h, int set, double* dst);
+int lbm_set_pop(lbm_handle* h, int set, const double* src);
+
+/* Sweep counts of every potential solve since lbm_init (index 0 = initial solve);
+   copies min(count, cap) entries, *count gets the total. */
+int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count);
+
+/* Measurement: launch exactly n potential sweeps (Eqs. (31)-(34), the step's inner
+   loop, in the launch configuration lbm_step uses, no stopping test) on the handle's
+   stream, bracketed by HIP events; *ms gets the elapsed GPU time.  The state
+   advances by n sweeps.  Synchronises the stream. */
+int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
+
+/* Release the handle (not the workspace, which the caller owns). */
+int lbm_destroy(lbm_handle* h);
+
+const char* lbm_strerror(int code);
+const char* lbm_last_error(const lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

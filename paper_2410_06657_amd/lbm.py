@@ -1,0 +1,216 @@
+"""Python binding of liblbm.so (the gfx950 HIP library): argument marshalling only.
+
+Every step of the method runs in the library's kernels; PyTorch only provides the device
+workspace and the stream.  There is no fallback: if the library is missing or no GPU is
+visible, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOCONV, LBM_ENONFINITE, LBM_EHIP, LBM_ESTATE, LBM_ESPACE = 0, -1, -2, -3, -4, -5, -6
+FIELDS = ["psi", "ux", "uy", "usx", "usy", "p", "T", "H", "fs", "mdot",
+          "psiu_x", "psiu_y", "phi", "fl"]
+POPS = {"f": (0, 9), "h": (1, 9), "g": (2, 9), "l": (3, 4)}
+PRECISIONS = {"fp64": 0}
+
+# every exported symbol of include/lbm.h
+SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
+           "lbm_diagnostics", "lbm_get_field", "lbm_set_field", "lbm_get_pop", "lbm_set_pop",
+           "lbm_sweep_log", "lbm_time_sweeps", "lbm_destroy", "lbm_strerror", "lbm_last_error"]
+
+
+class LbmParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("precision", C.c_int),
+        ("W", C.c_double), ("M", C.c_double), ("gamma", C.c_double),
+        ("rho_l", C.c_double), ("rho_g", C.c_double), ("rho_s", C.c_double),
+        ("mu_l", C.c_double), ("mu_g", C.c_double), ("mu_s", C.c_double),
+        ("cp_l", C.c_double), ("cp_g", C.c_double), ("cp_s", C.c_double),
+        ("k_l", C.c_double), ("k_g", C.c_double), ("k_s", C.c_double),
+        ("latent", C.c_double),
+        ("T_w", C.c_double), ("T_g", C.c_double),
+        ("eps_l", C.c_double), ("eps_g", C.c_double), ("eps_s", C.c_double),
+        ("sig_l", C.c_double), ("sig_g", C.c_double), ("sig_s", C.c_double),
+        ("phi_top", C.c_double), ("phi_bot", C.c_double),
+        ("theta_deg", C.c_double),
+        ("shape", C.c_int),
+        ("R0", C.c_double), ("xc", C.c_double), ("yc", C.c_double), ("h0", C.c_double),
+        ("poisson_tol", C.c_double), ("poisson_max_sweeps", C.c_int),
+        ("readings", C.c_uint),
+    ]
+
+
+class LbmDiag(C.Structure):
+    _fields_ = [
+        ("step", C.c_longlong),
+        ("sum_psi", C.c_double), ("sum_f", C.c_double), ("sum_g", C.c_double),
+        ("V_l", C.c_double), ("V_s", C.c_double),
+        ("front_y", C.c_double), ("height", C.c_double), ("max_u", C.c_double),
+        ("resid", C.c_double), ("sweeps", C.c_int), ("noconv", C.c_int),
+        ("t_fre", C.c_double), ("V_l0", C.c_double), ("nonfinite", C.c_int),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, what, code, detail=""):
+        self.code = code
+        msg = f"{what} failed: {code} ({lib().lbm_strerror(code).decode()})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so (built by __graft_entry__.build() or paper_2410_06657_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c "
+                               "'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+        L.lbm_workspace_bytes.argtypes = [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]
+        L.lbm_init.argtypes = [C.POINTER(LbmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_step.argtypes = [vp, C.c_int]
+        L.lbm_solve_potential.argtypes = [vp, C.c_double, C.c_int, ip, dp]
+        L.lbm_diagnostics.argtypes = [vp, C.POINTER(LbmDiag)]
+        L.lbm_get_field.argtypes = [vp, C.c_int, dp]
+        L.lbm_set_field.argtypes = [vp, C.c_int, dp]
+        L.lbm_get_pop.argtypes = [vp, C.c_int, dp]
+        L.lbm_set_pop.argtypes = [vp, C.c_int, dp]
+        L.lbm_sweep_log.argtypes = [vp, ip, C.c_int, ip]
+        L.lbm_time_sweeps.argtypes = [vp, C.c_int, C.POINTER(C.c_float)]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_strerror.argtypes = [C.c_int]
+        L.lbm_strerror.restype = C.c_char_p
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def make_params(case: dict, precision: str = "fp64") -> LbmParams:
+    p = LbmParams()
+    for name, ctype in LbmParams._fields_:
+        if name == "precision":
+            p.precision = PRECISIONS[precision]
+            continue
+        if name not in case:
+            raise KeyError(f"case is missing '{name}'")
+        v = case[name]
+        setattr(p, name, int(v) if ctype in (C.c_int, C.c_uint) else float(v))
+    return p
+
+
+def workspace_bytes(case: dict, precision: str = "fp64") -> int:
+    p = make_params(case, precision)
+    n = C.c_size_t()
+    rc = lib().lbm_workspace_bytes(C.byref(p), C.byref(n))
+    if rc != LBM_OK:
+        raise LbmError("lbm_workspace_bytes", rc)
+    return n.value
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """One case on one GPU.  The workspace is a torch uint8 tensor; the stream is torch's
+    current stream on `device` at construction."""
+
+    def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library has no CPU path")
+        self.case = dict(case)
+        self.nx, self.ny = int(case["nx"]), int(case["ny"])
+        self.device = torch.device(device)
+        self.params = make_params(case, precision)
+        nbytes = workspace_bytes(case, precision)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = lib().lbm_init(C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
+                            C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError("lbm_init", rc)
+        self._h = h
+
+    def _check(self, what, rc, ok=(LBM_OK,)):
+        if rc not in ok:
+            raise LbmError(what, rc, lib().lbm_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        self._check("lbm_step", lib().lbm_step(self._h, int(n)))
+
+    def solve_potential(self, tol: float, max_sweeps: int):
+        k = C.c_int()
+        r = C.c_double()
+        rc = lib().lbm_solve_potential(self._h, float(tol), int(max_sweeps), C.byref(k), C.byref(r))
+        self._check("lbm_solve_potential", rc, ok=(LBM_OK, LBM_ENOCONV))
+        return rc, k.value, r.value
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty((self.ny, self.nx), dtype=np.float64)
+        self._check("lbm_get_field", lib().lbm_get_field(self._h, FIELDS.index(name), _dp(out)))
+        return out
+
+    def set_field(self, name: str, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64).reshape(self.ny, self.nx)
+        self._check("lbm_set_field", lib().lbm_set_field(self._h, FIELDS.index(name), _dp(a)))
+
+    def pop(self, name: str) -> np.ndarray:
+        idx, nq = POPS[name]
+        out = np.empty((nq, self.ny, self.nx), dtype=np.float64)
+        self._check("lbm_get_pop", lib().lbm_get_pop(self._h, idx, _dp(out)))
+        return out
+
+    def set_pop(self, name: str, arr):
+        idx, nq = POPS[name]
+        a = np.ascontiguousarray(arr, dtype=np.float64).reshape(nq, self.ny, self.nx)
+        self._check("lbm_set_pop", lib().lbm_set_pop(self._h, idx, _dp(a)))
+
+    def diag(self) -> dict:
+        d = LbmDiag()
+        rc = lib().lbm_diagnostics(self._h, C.byref(d))
+        self._check("lbm_diagnostics", rc, ok=(LBM_OK, LBM_ENONFINITE))
+        return {k: getattr(d, k) for k, _ in LbmDiag._fields_}
+
+    def time_sweeps(self, n: int) -> float:
+        """GPU milliseconds of exactly n sweep launches (HIP events on the solver's stream)."""
+        ms = C.c_float()
+        self._check("lbm_time_sweeps", lib().lbm_time_sweeps(self._h, int(n), C.byref(ms)))
+        return ms.value
+
+    def sweep_log(self) -> np.ndarray:
+        cnt = C.c_int()
+        lib().lbm_sweep_log(self._h, None, 0, C.byref(cnt))
+        n = cnt.value
+        buf = (C.c_int * max(n, 1))()
+        lib().lbm_sweep_log(self._h, buf, n, C.byref(cnt))
+        return np.array(buf[:n], dtype=np.int64)
