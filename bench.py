@@ -18,7 +18,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coupled MLUPS + % HBM roofline; time-to-freeze, plain FP64 vs FP32/batched/warm"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-SWEEP_BYTES_FP64 = 88  # per node: 4 links + phi + 1/tau_l read, 4 links + phi written
+# algorithmic bytes per node (element size s): a potential sweep reads 4 links, phi and
+# 1/tau_l and writes 4 links and phi (11 s); a step outside the sweeps moves 27 + 27
+# populations and 13 + 13 fields (80 s)
+SWEEP_ELEMS, STEP_ELEMS = 11, 80
+ELEM = {"fp64": 8, "fp32": 4}
 
 
 def workload(name):
@@ -65,75 +69,104 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
             "step_s": step_s}
 
 
+def run_form(case, precision, steps, warmup, sweep_launches):
+    """Time `steps` coupled steps of one precision form, then the dominant kernel."""
+    import numpy as np
+    import torch
+
+    from paper_2410_06657_amd.lbm import Solver
+
+    n = case["nx"] * case["ny"]
+    t0 = time.perf_counter()
+    s = Solver(case, precision=precision)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    print(f"[bench] {precision}: init {init_s:.1f}s, initial solve {s.sweep_log()[0]} sweeps",
+          file=sys.stderr, flush=True)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    nlog = len(s.sweep_log())
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sweeps = s.sweep_log()[nlog:]
+    kmean = float(np.mean(sweeps))
+    ms_step = dt / steps * 1e3
+    d = s.diag()
+    print(f"[bench] {precision}: {steps} steps, {ms_step:.3f} ms/step, {kmean:.1f} sweeps/step",
+          file=sys.stderr, flush=True)
+    # dominant kernel: the blocked potential sweep, timed with HIP events on the solver's
+    # stream over `sweep_launches` full launches of m sweeps each
+    m = case.get("sweep_block") or 8
+    nsweeps = sweep_launches * m
+    ms = s.time_sweeps(nsweeps)
+    launch_s = ms * 1e-3 / sweep_launches
+    es = ELEM[precision]
+    per_launch = SWEEP_ELEMS * es * n * m
+    achieved = per_launch / launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>",
+                "avg_launch_us": round(launch_s * 1e6, 3), "sweeps_per_launch": m,
+                "algorithmic_bytes_per_launch": per_launch,
+                "compulsory_hbm_bytes_per_launch": SWEEP_ELEMS * es * n}
+    coupled_bytes = (STEP_ELEMS + SWEEP_ELEMS * kmean) * es * n
+    coupled_gbs = coupled_bytes / (ms_step * 1e-3) / 1e9
+    return {
+        "value": round(n * steps / dt / 1e6, 3), "ms_per_step": round(ms_step, 4),
+        "sweeps_per_step": round(kmean, 2),
+        "sweep_time_share": round(min(1.0, kmean / m * launch_s * 1e3 / ms_step), 4),
+        "coupled_algorithmic_GBs": round(coupled_gbs, 1),
+        "coupled_hbm_roofline_frac": round(coupled_gbs / HBM_PEAK_GBS, 4),
+        "init_s": round(init_s, 2), "roofline": roofline,
+        "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cfg2")
-    ap.add_argument("--sweep-launches", type=int, default=200,
-                    help="sweep launches timed with HIP events for the roofline")
+    ap.add_argument("--sweep-launches", type=int, default=100,
+                    help="blocked sweep launches timed with HIP events for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
+    ap.add_argument("--sweep-block", type=int, default=0,
+                    help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
               "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
-    from paper_2410_06657_amd.lbm import Solver
-
     case, desc = workload(args.workload)
+    case["sweep_block"] = args.sweep_block
     n = case["nx"] * case["ny"]
-    t0 = time.perf_counter()
-    s = Solver(case)
-    torch.cuda.synchronize()
-    init_s = time.perf_counter() - t0
-    print(f"[bench] init {init_s:.1f}s, initial solve {s.sweep_log()[0]} sweeps", file=sys.stderr, flush=True)
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-    nlog = len(s.sweep_log())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    sweeps = s.sweep_log()[nlog:]
-    kmean = float(np.mean(sweeps))
-    ms_step = dt / args.steps * 1e3
-    value = n * args.steps / dt / 1e6
-    d = s.diag()
-    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {kmean:.1f} sweeps/step",
-          file=sys.stderr, flush=True)
-
-    # dominant kernel: the potential sweep, timed live with HIP events on the solver's stream
-    ms = s.time_sweeps(args.sweep_launches)
-    avg_s = ms * 1e-3 / args.sweep_launches
-    per_launch = SWEEP_BYTES_FP64 * n
-    achieved = per_launch / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep", "avg_us": round(avg_s * 1e6, 3),
-                "algorithmic_bytes_per_launch": per_launch}
-
+    f64 = run_form(case, "fp64", args.steps, args.warmup, args.sweep_launches)
     line = {
-        "metric": METRIC, "value": round(value, 3), "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "metric": METRIC, "value": f64["value"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "nx": case["nx"], "ny": case["ny"], "precision": "fp64",
-                   "poisson_tol": case["poisson_tol"]},
-        "sweeps_per_step": round(kmean, 2),
-        "sweep_time_share": round(min(1.0, kmean * avg_s * 1e3 / ms_step), 4),
-        "init_s": round(init_s, 2),
-        "roofline": roofline,
-        "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"]},
+                   "poisson_tol": case["poisson_tol"], "sweeps_per_launch": case["sweep_block"] or 8},
+        "sweeps_per_step": f64["sweeps_per_step"],
+        "sweep_time_share": f64["sweep_time_share"],
+        "coupled_hbm_roofline_frac": f64["coupled_hbm_roofline_frac"],
+        "coupled_algorithmic_GBs": f64["coupled_algorithmic_GBs"],
+        "init_s": f64["init_s"],
+        "roofline": f64["roofline"],
+        "state": f64["state"],
     }
+    if not args.no_fp32:
+        f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches)
+        f32["speedup_vs_fp64"] = round(f32["value"] / f64["value"], 3)
+        line["forms"] = {"fp32": f32}
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(case, kmean)
+        cb = cpu_baseline(case, f64["sweeps_per_step"])
         cb.pop("step_s")
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)

@@ -52,8 +52,15 @@ extern "C" {
 #define LBM_ESTATE (-5)     /* call out of order (e.g. step before init) */
 #define LBM_ESPACE (-6)     /* workspace smaller than lbm_workspace_bytes() */
 
-/* Arithmetic and storage of the populations. */
+/* Arithmetic and storage (lbm_params.precision).  FP64: every population and field in
+   double.  FP32: populations, fields and arithmetic in float, with the enthalpy rest
+   link and H stored relative to the liquid's latent heat rho_s L and the D2Q5 links and
+   phi stored relative to the linear electrode ramp (their increments are below an FP32
+   ulp of the raw values); FP64 is kept for the potential residual, the liquid and solid
+   volume sums, the freezing-time detector and the front search.  The ABI always
+   exchanges raw FP64 values. */
 #define LBM_FP64 0
+#define LBM_FP32 1
 
 /* Reading switches (bits of lbm_params.readings). */
 #define LBM_R_GRAD_S 1u /* F~ of Eq. (24) contains c_s^2 grad(S) (the printed "div S") */
@@ -62,7 +69,7 @@ extern "C" {
    Eq. (1) with psi clamped to [0, 1]. */
 typedef struct lbm_params {
     int nx, ny;
-    int precision;              /* LBM_FP64 */
+    int precision;              /* LBM_FP64 or LBM_FP32 */
     double W, M, gamma;         /* interface width, mobility (Eq. (2a)), surface tension */
     double rho_l, rho_g, rho_s; /* densities */
     double mu_l, mu_g, mu_s;    /* dynamic viscosities */
@@ -79,6 +86,9 @@ typedef struct lbm_params {
     double poisson_tol;         /* relative sweep-to-sweep change that ends a solve; < 0: fixed count */
     int poisson_max_sweeps;     /* cap per solve */
     unsigned readings;          /* LBM_R_* bits */
+    int sweep_block;            /* potential sweeps per kernel launch: 1, 2, 4 or 8 (0: 8).
+                                   A launch keeps every sweep's residual, so the stopping
+                                   sweep is the same for any value. */
 } lbm_params;
 
 /* Scalar fields for lbm_get_field / lbm_set_field. */
@@ -164,6 +174,30 @@ int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
 
 /* Release the handle (not the workspace, which the caller owns). */
 int lbm_destroy(lbm_handle* h);
+
+/* ---- Batched form: many independent cases of different grid sizes ------------------
+   Every case is one run of the method above (Algorithm 1 with its own parameters and
+   state), but each stage is one kernel launch covering the tiles of all cases, the
+   stages outside the potential loop are replayed from HIP graphs (when the stream is not
+   the null stream), and the potential loops of all cases run in lockstep launches in
+   which cases that have converged exit at once.  All cases share `precision` and
+   `sweep_block`.  The caller owns one workspace of lbm_batch_workspace_bytes() bytes
+   (256-byte aligned) and the stream; the library allocates no device memory. */
+typedef struct lbm_batch lbm_batch;
+
+int lbm_batch_workspace_bytes(int ncases, const lbm_params* cases, size_t* bytes);
+/* Initialise every case as lbm_init does (initial potential solves in lockstep). */
+int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t bytes,
+                   void* stream, lbm_batch** out);
+/* n time steps of every case. */
+int lbm_batch_step(lbm_batch* b, int n);
+/* FP64 diagnostics of every case into per_case[0..ncases-1]; synchronises. */
+int lbm_batch_diagnostics(lbm_batch* b, lbm_diag* per_case);
+/* One field of case c as nx_c*ny_c FP64 values; synchronises. */
+int lbm_batch_get_field(lbm_batch* b, int c, int field, double* dst);
+/* Sweep counts of case c's potential solves since init (see lbm_sweep_log). */
+int lbm_batch_sweep_log(lbm_batch* b, int c, int* dst, int cap, int* count);
+int lbm_batch_destroy(lbm_batch* b);
 
 const char* lbm_strerror(int code);
 const char* lbm_last_error(const lbm_handle* h);

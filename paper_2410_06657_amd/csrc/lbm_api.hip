@@ -2,7 +2,9 @@
 //
 // The library carves every device array out of the caller's workspace, queues
 // kernels on the caller's stream and reads back only the few bytes of the control
-// block (potential-loop flags, reductions) through pinned host memory.
+// block (potential-loop flags, reductions) through pinned host memory.  Every stage
+// exists for R = double (FP64 form) and R = float (FP32 form); the handle holds the
+// state of the precision chosen at lbm_init.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,13 +24,16 @@ using lbm::State;
 struct lbm_handle {
     lbm_params prm;
     Dev dev;
-    State st;
+    State<double> sd;         // FP64 form
+    State<float> sf;          // FP32 form
+    int prec = LBM_FP64;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     int nb = 0;               // blocks of a node-parallel launch
     int sp = 0;               // which buffer of the double-buffered sets is current
-    int lcur = 0;             // which buffer holds the current potential (l, phi)
+    int lcur = 0;             // which of the three buffers holds the current potential (l, phi)
+    int swm = 8;              // sweeps per blocked launch
     long long step = 0;
     std::vector<int> log;     // sweep counts of every potential solve
     int last_sweeps = 0;
@@ -36,8 +41,14 @@ struct lbm_handle {
     int noconv = 0;
     int kprev = 0;            // sweeps of the previous solve (first batch size)
     Ctl* hctl = nullptr;      // pinned host mirror of the control block
+    Ctl* dctl = nullptr;      // device control block
+    double* partials = nullptr;
     std::string err;
+
+    template <typename R> State<R>& st();
 };
+template <> State<double>& lbm_handle::st<double>() { return sd; }
+template <> State<float>& lbm_handle::st<float>() { return sf; }
 
 namespace {
 
@@ -48,7 +59,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int validate(const lbm_params* p) {
     if (!p) return LBM_EINVAL;
     if (p->nx < 2 || p->ny < 3 || (int64_t)p->nx * p->ny > (int64_t)1 << 31) return LBM_EINVAL;
-    if (p->precision != LBM_FP64) return LBM_EINVAL;
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32) return LBM_EINVAL;
     if (!(p->W > 0) || !(p->M > 0) || !(p->gamma >= 0)) return LBM_EINVAL;
     if (!(p->rho_l > 0) || !(p->rho_g > 0) || !(p->rho_s > 0)) return LBM_EINVAL;
     if (!(p->mu_l > 0) || !(p->mu_g > 0) || !(p->mu_s > 0)) return LBM_EINVAL;
@@ -57,8 +68,13 @@ int validate(const lbm_params* p) {
     if (!(p->sig_l > 0) || !(p->sig_g > 0) || !(p->sig_s > 0)) return LBM_EINVAL;
     if (!(p->latent >= 0) || p->poisson_max_sweeps < 1) return LBM_EINVAL;
     if (p->shape != 0 && p->shape != 1) return LBM_EINVAL;
+    if (p->sweep_block != 0 && p->sweep_block != 1 && p->sweep_block != 2 && p->sweep_block != 4 &&
+        p->sweep_block != 8)
+        return LBM_EINVAL;
     return LBM_OK;
 }
+
+int sweep_m(const lbm_params* p) { return p->sweep_block ? p->sweep_block : 8; }
 
 Dev make_dev(const lbm_params* p) {
     Dev d{};
@@ -68,6 +84,9 @@ Dev make_dev(const lbm_params* p) {
     d.plane = (int64_t)d.pitch * p->ny;
     d.gx = (p->nx + lbm::TX - 1) / lbm::TX;
     d.gy = (p->ny + lbm::TY - 1) / lbm::TY;
+    int m = sweep_m(p);
+    d.tbx = (p->nx + (64 - 2 * m) - 1) / (64 - 2 * m);
+    d.tby = (p->ny + (lbm::SW_RY - 2 * m) - 1) / (lbm::SW_RY - 2 * m);
     double tauf = p->M / lbm::CS2 + 0.5;  // Sec. 3.1
     d.omf = 1.0 / tauf;
     d.facf = 1.0 - 0.5 / tauf;
@@ -96,34 +115,47 @@ Dev make_dev(const lbm_params* p) {
 struct Carver {
     char* base;
     size_t off = 0;
-    double* take(size_t ndouble) {
+    template <typename T>
+    T* take(size_t n) {
         off = round_up(off, ALIGN);
-        double* r = base ? reinterpret_cast<double*>(base + off) : nullptr;
-        off += ndouble * sizeof(double);
+        T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += n * sizeof(T);
         return r;
     }
 };
 
-size_t carve(const Dev& d, char* base, State* s, int nb) {
+template <typename R>
+size_t carve(const Dev& d, char* base, State<R>* s) {
+    int nb = d.gx * d.gy, nbt = d.tbx * d.tby;
     Carver c{base};
-    State t{};
+    State<R> t{};
     size_t P = (size_t)d.plane;
     for (int b = 0; b < 2; b++) {
-        t.f[b] = c.take(9 * P);
-        t.h[b] = c.take(9 * P);
-        t.g[b] = c.take(9 * P);
-        t.l[b] = c.take(4 * P);
-        t.psi[b] = c.take(P); t.ux[b] = c.take(P); t.uy[b] = c.take(P); t.p[b] = c.take(P);
-        t.H[b] = c.take(P); t.T[b] = c.take(P); t.fs[b] = c.take(P); t.md[b] = c.take(P);
-        t.phi[b] = c.take(P);
+        t.f[b] = c.take<R>(9 * P);
+        t.h[b] = c.take<R>(9 * P);
+        t.g[b] = c.take<R>(9 * P);
+        t.psi[b] = c.take<R>(P); t.ux[b] = c.take<R>(P); t.uy[b] = c.take<R>(P); t.p[b] = c.take<R>(P);
+        t.H[b] = c.take<R>(P); t.T[b] = c.take<R>(P); t.fs[b] = c.take<R>(P); t.md[b] = c.take<R>(P);
     }
-    double** singles[] = {&t.usx, &t.usy, &t.pux, &t.puy, &t.Ax, &t.Ay, &t.oml, &t.S, &t.Fx,
-                          &t.Fy, &t.rho, &t.Ftx, &t.Fty, &t.Gx, &t.Gy, &t.omh, &t.fl};
-    for (double** q : singles) *q = c.take(P);
-    t.partials = c.take((size_t)lbm::part_total(nb));
-    t.ctl = reinterpret_cast<Ctl*>(c.take((sizeof(Ctl) + 7) / 8));
+    for (int b = 0; b < 3; b++) {
+        t.l[b] = c.take<R>(4 * P);
+        t.phi[b] = c.take<R>(P);
+    }
+    // the deviation bases exist only in the FP32 form
+    const bool based = std::is_same<R, float>::value;
+    t.lb = based ? c.take<R>(4 * P) : nullptr;
+    t.hb = based ? c.take<R>(P) : nullptr;
+    R** singles[] = {&t.usx, &t.usy, &t.pux, &t.puy, &t.Ax, &t.Ay, &t.oml, &t.S, &t.Fx,
+                     &t.Fy, &t.rho, &t.Ftx, &t.Fty, &t.Gx, &t.Gy, &t.omh, &t.fl};
+    for (R** q : singles) *q = c.take<R>(P);
+    t.partials = c.take<double>((size_t)lbm::part_total(nb, nbt));
+    t.ctl = c.take<Ctl>(1);
     if (s) *s = t;
     return round_up(c.off, ALIGN);
+}
+
+size_t carve_bytes(const lbm_params* p, const Dev& d) {
+    return p->precision == LBM_FP32 ? carve<float>(d, nullptr, nullptr) : carve<double>(d, nullptr, nullptr);
 }
 
 #define HIPCHK(h, x)                                      \
@@ -140,33 +172,115 @@ size_t carve(const Dev& d, char* base, State* s, int nb) {
 __global__ void k_ctl_zero(Ctl* c) { *c = Ctl{}; }
 
 int fetch_ctl(lbm_handle* h) {
-    HIPCHK(h, hipMemcpyAsync(h->hctl, h->st.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->hctl, h->dctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
 
-// Potential loop: sweep launches go out in batches.  Block 0 of launch k tests sweep
-// k - 1; once a test ends the loop every later launch exits at once, so the sweep count
-// is exact while the host reads the flag once per batch.  Launch max_sweeps + 1 only
-// tests the last sweep.
+template <typename R>
+void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
+    int nbt = h->dev.tbx * h->dev.tby;
+    State<R>& s = h->st<R>();
+    switch (h->swm) {
+        case 1: lbm::k_sweep_tb<1, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 2: lbm::k_sweep_tb<2, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 4: lbm::k_sweep_tb<4, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
+        default: lbm::k_sweep_tb<8, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
+    }
+}
+
+template <typename R>
+void launch_test(lbm_handle* h, const lbm::SweepLaunch& a) {
+    State<R>& s = h->st<R>();
+    switch (h->swm) {
+        case 1: lbm::k_sweep_test<1, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 2: lbm::k_sweep_test<2, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 4: lbm::k_sweep_test<4, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
+        default: lbm::k_sweep_test<8, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
+    }
+}
+
+// Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; block 0 of
+// each launch tests every sweep of the previous launch, and each batch of launches ends
+// with a one-block test of its last launch, after which the host reads the flag.  The
+// first batch covers the previous solve's count less one launch, later batches double
+// from one launch.  Launches queued after a test ended the loop exit at once.  If the
+// final sweep is not the last of its launch, that launch's sweeps up to it are
+// recomputed from its input (three buffers keep that input intact past the launches
+// that follow it in the batch, which all exit at once).
+template <typename R>
 int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid) {
-    lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->st.ctl, tol, min_sweeps, max_sweeps);
+    if (std::is_same<R, float>::value)
+        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
+    lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
     LAUNCHCHK(h);
-    int next = 1;
-    int batch = std::max(2, h->kprev * 3 / 4 + 1);
+    std::vector<lbm::SweepLaunch> plan;
+    int next = 1;       // next sweep index
+    int buf = h->lcur;  // buffer holding the state before sweep `next`
+    int nlaunch = std::max(1, (h->kprev - h->swm) / h->swm);
+    int grow = 1;
+    const bool rebasing = std::is_same<R, float>::value;
     for (;;) {
-        int n = std::min(batch, max_sweeps + 2 - next);
-        for (int k = next; k < next + n; k++)
-            lbm::k_sweep<<<h->nb, NT, 0, h->stream>>>(h->dev, h->st, k, h->lcur);
+        for (int c = 0; c < nlaunch && next <= max_sweeps; c++) {
+            // FP32 batches end on rebase points, which sit at the same sweep counts for
+            // every sweeps-per-launch choice
+            if (rebasing && c > 0 && (next - 1) % lbm::REBASE_SWEEPS == 0) break;
+            lbm::SweepLaunch a{};
+            int t = (int)plan.size();
+            a.nsw = std::min(h->swm, max_sweeps + 1 - next);
+            a.src = buf;
+            a.dst = (buf + 1) % 3;
+            a.k0 = next;
+            a.slot = t & 1;
+            a.launch = t;
+            if (t > 0) {
+                a.prev_k0 = plan[t - 1].k0;
+                a.prev_nsw = plan[t - 1].nsw;
+                a.prev_slot = plan[t - 1].slot;
+            }
+            launch_sweep<R>(h, a);
+            plan.push_back(a);
+            next += a.nsw;
+            buf = a.dst;
+        }
+        lbm::SweepLaunch tst{};
+        const lbm::SweepLaunch& last = plan.back();
+        tst.prev_k0 = last.k0;
+        tst.prev_nsw = last.nsw;
+        tst.prev_slot = last.slot;
+        tst.launch = (int)plan.size();
+        launch_test<R>(h, tst);
         LAUNCHCHK(h);
-        next += n;
         int rc = fetch_ctl(h);
         if (rc) return rc;
-        if (h->hctl->done || next > max_sweeps + 1) break;
-        batch = std::min(std::max(batch * 2, 8), 2048);
+        if (h->hctl->done || next > max_sweeps) break;
+        // FP32: keep the stored links small during long solves
+        if (rebasing && (next - 1) % lbm::REBASE_SWEEPS == 0)
+            lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), buf);
+        nlaunch = grow;
+        grow = std::min(grow * 2, 256);
+    }
+    if (!h->hctl->done) {
+        h->err = "potential loop ended without a decision";
+        return LBM_EHIP;
     }
     int k = h->hctl->count;
-    h->lcur = (h->lcur + k) & 1;
+    const lbm::SweepLaunch& f = plan[h->hctl->fix_launch];
+    int final_buf = f.dst;
+    if (h->hctl->fix_n != f.nsw) {
+        lbm::SweepLaunch a{};
+        a.src = f.src;
+        a.dst = (f.src + 2) % 3;
+        a.nsw = h->hctl->fix_n;
+        a.k0 = f.k0;
+        a.slot = (int)plan.size() & 1;
+        a.launch = (int)plan.size();
+        a.force = 1;
+        launch_sweep<R>(h, a);
+        LAUNCHCHK(h);
+        final_buf = a.dst;
+    }
+    h->lcur = final_buf;
     h->kprev = k;
     h->last_sweeps = k;
     h->last_resid = h->hctl->resid;
@@ -177,33 +291,105 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     return LBM_OK;
 }
 
+template <typename R>
 int one_step(lbm_handle* h) {
     const Dev& d = h->dev;
     int sp = h->sp;
     hipStream_t st = h->stream;
-    lbm::k_f_prep<<<h->nb, NT, 0, st>>>(d, h->st, sp);
-    lbm::k_f_stream<<<h->nb, NT, 0, st>>>(d, h->st, sp);
+    State<R>& s = h->st<R>();
+    lbm::k_f_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp);
+    lbm::k_f_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
     LAUNCHCHK(h);
-    int rc = run_sweeps(h, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, nullptr, nullptr);
+    int rc = run_sweeps<R>(h, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, nullptr, nullptr);
     if (rc == LBM_ENOCONV)
         h->noconv++;
     else if (rc)
         return rc;
-    lbm::k_h_prep1<<<h->nb, NT, 0, st>>>(d, h->st, sp, h->lcur);
-    lbm::k_h_prep2<<<h->nb, NT, 0, st>>>(d, h->st, sp);
-    lbm::k_h_stream<<<h->nb, NT, 0, st>>>(d, h->st, sp);
-    lbm::k_g_stream<<<h->nb, NT, 0, st>>>(d, h->st, sp);
-    lbm::k_vl_finalize<<<1, NT, 0, st>>>(d, h->st, 0);
+    lbm::k_h_prep1<R><<<h->nb, NT, 0, st>>>(d, s, sp, h->lcur);
+    lbm::k_h_prep2<R><<<h->nb, NT, 0, st>>>(d, s, sp);
+    lbm::k_h_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
+    lbm::k_g_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
+    lbm::k_vl_finalize<<<1, NT, 0, st>>>(d, h->partials, h->dctl, 0);
     LAUNCHCHK(h);
     h->sp ^= 1;
     h->step++;
     return LBM_OK;
 }
 
-// Device plane of a field in the current state.
-double* field_ptr(lbm_handle* h, int field) {
-    State& s = h->st;
+template <typename R>
+int init_state(lbm_handle* h) {
+    const Dev& d = h->dev;
+    State<R>& s = h->st<R>();
+    k_ctl_zero<<<1, 1, 0, h->stream>>>(h->dctl);
+    lbm::k_init<R><<<h->nb, NT, 0, h->stream>>>(d, s);
+    lbm::k_oml<R><<<h->nb, NT, 0, h->stream>>>(d, s, 0);
+    LAUNCHCHK(h);
+    // first solve from equilibrium populations: the stopping test counts from sweep 2
+    int rc = run_sweeps<R>(h, h->prm.poisson_tol, 2, h->prm.poisson_max_sweeps, nullptr, nullptr);
+    if (rc && rc != LBM_ENOCONV) return rc;
+    lbm::k_vl0<R><<<h->nb, NT, 0, h->stream>>>(d, s);
+    lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->partials, h->dctl, 1);
+    LAUNCHCHK(h);
+    return fetch_ctl(h);
+}
+
+template <typename R>
+int solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps, double* resid) {
+    // tau_l follows the current psi and f_s (as the step does after the f stage)
+    lbm::k_oml<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp);
+    LAUNCHCHK(h);
+    return run_sweeps<R>(h, tol, 1, max_sweeps, sweeps, resid);
+}
+
+template <typename R>
+int diagnostics(lbm_handle* h) {
+    lbm::k_diag<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, h->lcur);
+    lbm::k_diag_finalize<R><<<1, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp);
+    LAUNCHCHK(h);
+    return fetch_ctl(h);
+}
+
+template <typename R>
+int time_sweeps(lbm_handle* h, int n, float* ms) {
+    hipEvent_t a, b;
+    HIPCHK(h, hipEventCreate(&a));
+    HIPCHK(h, hipEventCreate(&b));
+    if (std::is_same<R, float>::value)
+        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
+    lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, -1.0, 1, n);
+    HIPCHK(h, hipEventRecord(a, h->stream));
+    int buf = h->lcur;
+    for (int k = 1, t = 0; k <= n; t++) {
+        lbm::SweepLaunch s{};
+        s.nsw = std::min(h->swm, n + 1 - k);
+        s.src = buf;
+        s.dst = (buf + 1) % 3;
+        s.k0 = k;
+        s.slot = t & 1;
+        s.launch = t;
+        launch_sweep<R>(h, s);
+        buf = s.dst;
+        k += s.nsw;
+    }
+    HIPCHK(h, hipEventRecord(b, h->stream));
+    LAUNCHCHK(h);
+    HIPCHK(h, hipEventSynchronize(b));
+    HIPCHK(h, hipEventElapsedTime(ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    h->lcur = buf;
+    return fetch_ctl(h);
+}
+
+// Device plane(s) of a field or population set in the current state, with the offset
+// kind that converts stored values to the raw FP64 values of the ABI.
+enum Offset { OFF_NONE, OFF_G, OFF_BASE };  // enthalpy base; potential link bases
+
+template <typename R>
+R* field_ptr(lbm_handle* h, int field, Offset* off) {
+    State<R>& s = h->st<R>();
     int sp = h->sp;
+    *off = OFF_NONE;
     switch (field) {
         case LBM_PSI: return s.psi[sp];
         case LBM_UX: return s.ux[sp];
@@ -212,7 +398,7 @@ double* field_ptr(lbm_handle* h, int field) {
         case LBM_USY: return s.usy;
         case LBM_P: return s.p[sp];
         case LBM_T: return s.T[sp];
-        case LBM_H: return s.H[sp];
+        case LBM_H: *off = h->prec == LBM_FP32 ? OFF_G : OFF_NONE; return s.H[sp];
         case LBM_FS: return s.fs[sp];
         case LBM_MDOT: return s.md[sp];
         case LBM_PSIU_X: return s.pux;
@@ -223,15 +409,77 @@ double* field_ptr(lbm_handle* h, int field) {
     }
 }
 
-double* pop_ptr(lbm_handle* h, int set, int* nq) {
-    State& s = h->st;
+template <typename R>
+R* pop_ptr(lbm_handle* h, int set, int* nq, Offset* off) {
+    State<R>& s = h->st<R>();
+    *off = OFF_NONE;
     switch (set) {
         case LBM_POP_F: *nq = 9; return s.f[h->sp];
         case LBM_POP_H: *nq = 9; return s.h[h->sp];
-        case LBM_POP_G: *nq = 9; return s.g[h->sp];
-        case LBM_POP_L: *nq = 4; return s.l[h->lcur];
+        case LBM_POP_G: *nq = 9; *off = h->prec == LBM_FP32 ? OFF_G : OFF_NONE; return s.g[h->sp];
+        case LBM_POP_L: *nq = 4; *off = h->prec == LBM_FP32 ? OFF_BASE : OFF_NONE; return s.l[h->lcur];
         default: return nullptr;
     }
+}
+
+// Offset added to stored values of plane q to give raw values (base: per node).
+template <typename R>
+int copy_planes(lbm_handle* h, R* dev, double* host, int planes, bool to_host, Offset off) {
+    const Dev& d = h->dev;
+    size_t w = (size_t)d.nx * sizeof(R);
+    size_t dp = (size_t)d.pitch * sizeof(R);
+    size_t rows = (size_t)d.ny * planes;
+    size_t per = (size_t)d.nx * d.ny;
+    std::vector<R> stage(per * planes);
+    // OFF_G: one enthalpy base plane (applies to H and to the rest link of g);
+    // OFF_BASE: one base plane per potential link
+    std::vector<R> base;
+    size_t bplanes = off == OFF_BASE ? (size_t)planes : 1;
+    R* bp = off == OFF_BASE ? h->st<R>().lb : h->st<R>().hb;
+    if (off == OFF_G || (off == OFF_BASE && to_host)) {
+        base.resize(per * bplanes);
+        HIPCHK(h, hipMemcpy2DAsync(base.data(), w, bp, dp, w, (size_t)d.ny * bplanes, hipMemcpyDeviceToHost,
+                                   h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    auto offset = [&](size_t k) -> double {
+        if (off == OFF_G) return (planes == 1 || k < per) ? (double)base[k % per] : 0.0;
+        if (off == OFF_BASE) return (double)base[k];
+        return 0.0;
+    };
+    if (to_host) {
+        HIPCHK(h, hipMemcpy2DAsync(stage.data(), w, dev, dp, w, rows, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (size_t k = 0; k < per * planes; k++) host[k] = (double)stage[k] + offset(k);
+    } else {
+        if (off == OFF_BASE) {
+            // a written link becomes the pair (fl(v), fl(v - fl(v)))
+            base.resize(per * bplanes);
+            for (size_t k = 0; k < per * planes; k++) base[k] = (R)host[k];
+            HIPCHK(h, hipMemcpy2DAsync(bp, dp, base.data(), w, w, rows, hipMemcpyHostToDevice, h->stream));
+        }
+        for (size_t k = 0; k < per * planes; k++) stage[k] = (R)(host[k] - offset(k));
+        HIPCHK(h, hipMemcpy2DAsync(dev, dp, stage.data(), w, w, rows, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    return LBM_OK;
+}
+
+template <typename R>
+int get_set_field(lbm_handle* h, int field, double* buf, bool get) {
+    Offset off;
+    R* p = field_ptr<R>(h, field, &off);
+    if (!p || !buf) return LBM_EINVAL;
+    return copy_planes<R>(h, p, buf, 1, get, off);
+}
+
+template <typename R>
+int get_set_pop(lbm_handle* h, int set, double* buf, bool get) {
+    int nq = 0;
+    Offset off;
+    R* p = pop_ptr<R>(h, set, &nq, &off);
+    if (!p || !buf) return LBM_EINVAL;
+    return copy_planes<R>(h, p, buf, nq, get, off);
 }
 
 }  // namespace
@@ -243,7 +491,7 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
     if (rc) return rc;
     if (!bytes) return LBM_EINVAL;
     Dev d = make_dev(p);
-    *bytes = carve(d, nullptr, nullptr, d.gx * d.gy);
+    *bytes = carve_bytes(p, d);
     return LBM_OK;
 }
 
@@ -252,41 +500,36 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
     if (rc) return rc;
     if (!workspace || !out || ((uintptr_t)workspace % ALIGN) != 0) return LBM_EINVAL;
     Dev d = make_dev(p);
-    int nb = d.gx * d.gy;
-    size_t need = carve(d, nullptr, nullptr, nb);
+    size_t need = carve_bytes(p, d);
     if (bytes < need) return LBM_ESPACE;
     lbm_handle* h = new (std::nothrow) lbm_handle();
     if (!h) return LBM_EINVAL;
     h->prm = *p;
     h->dev = d;
-    h->nb = nb;
+    h->prec = p->precision;
+    h->nb = d.gx * d.gy;
     h->stream = (hipStream_t)stream;
     h->ws = (char*)workspace;
     h->ws_bytes = bytes;
-    carve(d, h->ws, &h->st, nb);
+    h->swm = sweep_m(p);
+    if (h->prec == LBM_FP32) {
+        carve<float>(d, h->ws, &h->sf);
+        h->dctl = h->sf.ctl;
+        h->partials = h->sf.partials;
+    } else {
+        carve<double>(d, h->ws, &h->sd);
+        h->dctl = h->sd.ctl;
+        h->partials = h->sd.partials;
+    }
     if (hipHostMalloc((void**)&h->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
         delete h;
         return LBM_EHIP;
     }
     std::memset(h->hctl, 0, sizeof(Ctl));
-    k_ctl_zero<<<1, 1, 0, h->stream>>>(h->st.ctl);
-    lbm::k_init<<<nb, NT, 0, h->stream>>>(d, h->st);
-    lbm::k_oml<<<nb, NT, 0, h->stream>>>(d, h->st, 0);
-    if (hipGetLastError() != hipSuccess) {
-        lbm_destroy(h);
-        return LBM_EHIP;
-    }
-    // first solve from equilibrium populations: the stopping test counts from sweep 2
-    rc = run_sweeps(h, p->poisson_tol, 2, p->poisson_max_sweeps, nullptr, nullptr);
-    if (rc && rc != LBM_ENOCONV) {
+    rc = h->prec == LBM_FP32 ? init_state<float>(h) : init_state<double>(h);
+    if (rc) {
         lbm_destroy(h);
         return rc;
-    }
-    lbm::k_vl0<<<nb, NT, 0, h->stream>>>(d, h->st);
-    lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->st, 1);
-    if (hipGetLastError() != hipSuccess || fetch_ctl(h) != LBM_OK) {
-        lbm_destroy(h);
-        return LBM_EHIP;
     }
     *out = h;
     return LBM_OK;
@@ -296,7 +539,7 @@ int lbm_step(lbm_handle* h, int n) {
     if (!h) return LBM_ESTATE;
     if (n < 0) return LBM_EINVAL;
     for (int k = 0; k < n; k++) {
-        int rc = one_step(h);
+        int rc = h->prec == LBM_FP32 ? one_step<float>(h) : one_step<double>(h);
         if (rc) return rc;
     }
     return LBM_OK;
@@ -305,19 +548,14 @@ int lbm_step(lbm_handle* h, int n) {
 int lbm_solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps, double* resid) {
     if (!h) return LBM_ESTATE;
     if (max_sweeps < 1) return LBM_EINVAL;
-    // tau_l follows the current psi and f_s (as the step does after the f stage)
-    lbm::k_oml<<<h->nb, NT, 0, h->stream>>>(h->dev, h->st, h->sp);
-    LAUNCHCHK(h);
-    return run_sweeps(h, tol, 1, max_sweeps, sweeps, resid);
+    return h->prec == LBM_FP32 ? solve_potential<float>(h, tol, max_sweeps, sweeps, resid)
+                               : solve_potential<double>(h, tol, max_sweeps, sweeps, resid);
 }
 
 int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
     if (!h) return LBM_ESTATE;
     if (!out) return LBM_EINVAL;
-    lbm::k_diag<<<h->nb, NT, 0, h->stream>>>(h->dev, h->st, h->sp, h->lcur);
-    lbm::k_diag_finalize<<<1, NT, 0, h->stream>>>(h->dev, h->st, h->sp);
-    LAUNCHCHK(h);
-    int rc = fetch_ctl(h);
+    int rc = h->prec == LBM_FP32 ? diagnostics<float>(h) : diagnostics<double>(h);
     if (rc) return rc;
     const Ctl& c = *h->hctl;
     std::memset(out, 0, sizeof *out);
@@ -339,47 +577,28 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
     return c.nonfinite ? LBM_ENONFINITE : LBM_OK;
 }
 
-static int copy_planes(lbm_handle* h, double* dev, void* host, int planes, bool to_host) {
-    const Dev& d = h->dev;
-    size_t w = (size_t)d.nx * sizeof(double);
-    size_t dp = (size_t)d.pitch * sizeof(double);
-    size_t rows = (size_t)d.ny * planes;
-    if (to_host)
-        HIPCHK(h, hipMemcpy2DAsync(host, w, dev, dp, w, rows, hipMemcpyDeviceToHost, h->stream));
-    else
-        HIPCHK(h, hipMemcpy2DAsync(dev, dp, host, w, w, rows, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    return LBM_OK;
-}
-
 int lbm_get_field(lbm_handle* h, int field, double* dst) {
     if (!h) return LBM_ESTATE;
-    double* p = field_ptr(h, field);
-    if (!p || !dst) return LBM_EINVAL;
-    return copy_planes(h, p, dst, 1, true);
+    return h->prec == LBM_FP32 ? get_set_field<float>(h, field, dst, true)
+                               : get_set_field<double>(h, field, dst, true);
 }
 
 int lbm_set_field(lbm_handle* h, int field, const double* src) {
     if (!h) return LBM_ESTATE;
-    double* p = field_ptr(h, field);
-    if (!p || !src) return LBM_EINVAL;
-    return copy_planes(h, p, const_cast<double*>(src), 1, false);
+    double* s = const_cast<double*>(src);
+    return h->prec == LBM_FP32 ? get_set_field<float>(h, field, s, false)
+                               : get_set_field<double>(h, field, s, false);
 }
 
 int lbm_get_pop(lbm_handle* h, int set, double* dst) {
     if (!h) return LBM_ESTATE;
-    int nq = 0;
-    double* p = pop_ptr(h, set, &nq);
-    if (!p || !dst) return LBM_EINVAL;
-    return copy_planes(h, p, dst, nq, true);
+    return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, dst, true) : get_set_pop<double>(h, set, dst, true);
 }
 
 int lbm_set_pop(lbm_handle* h, int set, const double* src) {
     if (!h) return LBM_ESTATE;
-    int nq = 0;
-    double* p = pop_ptr(h, set, &nq);
-    if (!p || !src) return LBM_EINVAL;
-    return copy_planes(h, p, const_cast<double*>(src), nq, false);
+    double* s = const_cast<double*>(src);
+    return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, s, false) : get_set_pop<double>(h, set, s, false);
 }
 
 int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count) {
@@ -394,20 +613,7 @@ int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count) {
 int lbm_time_sweeps(lbm_handle* h, int n, float* ms) {
     if (!h) return LBM_ESTATE;
     if (n < 1 || !ms) return LBM_EINVAL;
-    hipEvent_t a, b;
-    HIPCHK(h, hipEventCreate(&a));
-    HIPCHK(h, hipEventCreate(&b));
-    lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->st.ctl, -1.0, 1, n);
-    HIPCHK(h, hipEventRecord(a, h->stream));
-    for (int k = 1; k <= n; k++) lbm::k_sweep<<<h->nb, NT, 0, h->stream>>>(h->dev, h->st, k, h->lcur);
-    HIPCHK(h, hipEventRecord(b, h->stream));
-    LAUNCHCHK(h);
-    HIPCHK(h, hipEventSynchronize(b));
-    HIPCHK(h, hipEventElapsedTime(ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    h->lcur = (h->lcur + n) & 1;
-    return fetch_ctl(h);
+    return h->prec == LBM_FP32 ? time_sweeps<float>(h, n, ms) : time_sweeps<double>(h, n, ms);
 }
 
 int lbm_destroy(lbm_handle* h) {
@@ -432,5 +638,438 @@ const char* lbm_strerror(int code) {
 }
 
 const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form.
+
+struct lbm_batch {
+    int ncases = 0;
+    int prec = LBM_FP64;
+    int swm = 8;
+    hipStream_t stream = nullptr;
+    std::vector<lbm_params> prm;
+    std::vector<Dev> dev;
+    std::vector<lbm::BatchCase<double>> cd;
+    std::vector<lbm::BatchCase<float>> cf;
+    void* table = nullptr;               // device BatchCase<R>[ncases]
+    int* first_node = nullptr;           // device: first node-grid block of each case
+    int* first_sw = nullptr;             // device: first sweep-grid block of each case
+    int* lcur_d = nullptr;               // device: current potential buffer of each case
+    int* lcur0_d = nullptr;              // device: buffer at the start of the running solve
+    double* tol_d = nullptr;
+    int* maxsw_d = nullptr;
+    lbm::SweepLaunch* fix_d = nullptr;
+    Ctl* ctl_d = nullptr;                // ncases control blocks
+    Ctl* ctl_h = nullptr;                // pinned mirror
+    int node_blocks = 0, sweep_blocks = 0;
+    std::vector<int> lcur, kprev;
+    std::vector<std::vector<int>> log;
+    int sp = 0;
+    long long step = 0;
+    bool graphs = false;
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [stage A/B][sp]
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    std::string err;
+};
+
+namespace {
+
+struct BatchLayout {
+    std::vector<size_t> off;   // byte offset of each case's state
+    size_t table, first_node, first_sw, lcur, lcur0, tol, maxsw, fix, ctl, total;
+};
+
+int batch_validate(int ncases, const lbm_params* cases) {
+    if (ncases < 1 || !cases) return LBM_EINVAL;
+    for (int c = 0; c < ncases; c++) {
+        int rc = validate(&cases[c]);
+        if (rc) return rc;
+        if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]))
+            return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+BatchLayout batch_layout(int ncases, const lbm_params* cases) {
+    BatchLayout L;
+    size_t off = 0;
+    bool f32 = cases[0].precision == LBM_FP32;
+    for (int c = 0; c < ncases; c++) {
+        L.off.push_back(off);
+        Dev d = make_dev(&cases[c]);
+        off = round_up(off + (f32 ? carve<float>(d, nullptr, nullptr) : carve<double>(d, nullptr, nullptr)), ALIGN);
+    }
+    size_t cs = f32 ? sizeof(lbm::BatchCase<float>) : sizeof(lbm::BatchCase<double>);
+    auto take = [&](size_t bytes) { size_t r = off; off = round_up(off + bytes, ALIGN); return r; };
+    L.table = take(cs * ncases);
+    L.first_node = take(sizeof(int) * ncases);
+    L.first_sw = take(sizeof(int) * ncases);
+    L.lcur = take(sizeof(int) * ncases);
+    L.lcur0 = take(sizeof(int) * ncases);
+    L.tol = take(sizeof(double) * ncases);
+    L.maxsw = take(sizeof(int) * ncases);
+    L.fix = take(sizeof(lbm::SweepLaunch) * ncases);
+    L.ctl = take(sizeof(Ctl) * ncases);
+    L.total = off;
+    return L;
+}
+
+#define BHIP(b, x)                                                       \
+    do {                                                                 \
+        hipError_t e_ = (x);                                             \
+        if (e_ != hipSuccess) {                                          \
+            (b)->err = std::string(#x) + ": " + hipGetErrorString(e_);   \
+            return LBM_EHIP;                                             \
+        }                                                                \
+    } while (0)
+
+template <typename R> std::vector<lbm::BatchCase<R>>& bcases(lbm_batch* b);
+template <> std::vector<lbm::BatchCase<double>>& bcases<double>(lbm_batch* b) { return b->cd; }
+template <> std::vector<lbm::BatchCase<float>>& bcases<float>(lbm_batch* b) { return b->cf; }
+
+template <typename R>
+const lbm::BatchCase<R>* btable(lbm_batch* b) { return (const lbm::BatchCase<R>*)b->table; }
+
+template <int M, typename R>
+void batch_launch_sweep(lbm_batch* b, int t) {
+    lbm::kb_sweep<M, R><<<b->sweep_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_sw, b->ncases, b->lcur0_d, t);
+}
+
+template <typename R>
+void batch_sweep(lbm_batch* b, int t) {
+    switch (b->swm) {
+        case 1: batch_launch_sweep<1, R>(b, t); break;
+        case 2: batch_launch_sweep<2, R>(b, t); break;
+        case 4: batch_launch_sweep<4, R>(b, t); break;
+        default: batch_launch_sweep<8, R>(b, t); break;
+    }
+}
+
+template <typename R>
+void batch_test(lbm_batch* b, int t) {
+    auto tb = btable<R>(b);
+    switch (b->swm) {
+        case 1: lbm::kb_sweep_test<1, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        case 2: lbm::kb_sweep_test<2, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        case 4: lbm::kb_sweep_test<4, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        default: lbm::kb_sweep_test<8, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+    }
+}
+
+template <typename R>
+void batch_fix(lbm_batch* b) {
+    auto tb = btable<R>(b);
+    switch (b->swm) {
+        case 1: lbm::kb_sweep_fix<1, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
+        case 2: lbm::kb_sweep_fix<2, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
+        case 4: lbm::kb_sweep_fix<4, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
+        default: lbm::kb_sweep_fix<8, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
+    }
+}
+
+// Lockstep potential loops of all cases.  Launch t performs sweeps t*M+1.. of every case
+// that is still running (and, in block 0 of each case, tests its launch t-1); a batch of
+// launches ends with a one-block-per-case test of its last launch, then the host reads
+// all control blocks.  Finished cases whose final sweep was not the last of its launch
+// are recomputed together in one launch.
+template <typename R>
+int batch_sweeps(lbm_batch* b, int min_sweeps) {
+    int nc = b->ncases;
+    if (std::is_same<R, float>::value)
+        lbm::kb_rebase<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc, b->sp, b->lcur_d);
+    BHIP(b, hipMemcpyAsync(b->lcur0_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    lbm::kb_ctl_reset<R><<<(nc + 63) / 64, 64, 0, b->stream>>>(btable<R>(b), nc, b->tol_d, min_sweeps, b->maxsw_d);
+    BHIP(b, hipGetLastError());
+    int kmin = *std::min_element(b->kprev.begin(), b->kprev.end());
+    int maxmax = 0;
+    for (auto& p : b->prm) maxmax = std::max(maxmax, p.poisson_max_sweeps);
+    int tmax = (maxmax + b->swm - 1) / b->swm;  // launches that reach every case's cap
+    int nlaunch = std::max(1, (kmin - b->swm) / b->swm);
+    int grow = 1, t = 0;
+    const bool rebasing = std::is_same<R, float>::value;
+    const int reb = lbm::REBASE_SWEEPS / b->swm;  // launches between FP32 rebase points
+    for (;;) {
+        for (int c = 0; c < nlaunch && t < tmax; c++, t++) {
+            if (rebasing && c > 0 && t % reb == 0) break;
+            batch_sweep<R>(b, t);
+        }
+        batch_test<R>(b, t - 1);
+        BHIP(b, hipGetLastError());
+        BHIP(b, hipMemcpyAsync(b->ctl_h, b->ctl_d, sizeof(Ctl) * nc, hipMemcpyDeviceToHost, b->stream));
+        BHIP(b, hipStreamSynchronize(b->stream));
+        bool all = true;
+        for (int c = 0; c < nc; c++) all = all && b->ctl_h[c].done;
+        if (all) break;
+        if (t >= tmax) {
+            b->err = "potential loops ended without a decision";
+            return LBM_EHIP;
+        }
+        if (rebasing && t % reb == 0)
+            lbm::kb_rebase_running<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc,
+                                                                            b->lcur0_d, t);
+        nlaunch = grow;
+        grow = std::min(grow * 2, 256);
+    }
+    std::vector<lbm::SweepLaunch> fix(nc);
+    bool any = false;
+    for (int c = 0; c < nc; c++) {
+        const Ctl& ct = b->ctl_h[c];
+        int f = ct.fix_launch;
+        int src = (b->lcur[c] + f) % 3;
+        int nsw_f = std::min(b->swm, b->prm[c].poisson_max_sweeps + 1 - (f * b->swm + 1));
+        int final_buf = (src + 1) % 3;
+        fix[c] = lbm::SweepLaunch{};
+        if (ct.fix_n != nsw_f) {
+            fix[c].src = src;
+            fix[c].dst = (src + 2) % 3;
+            fix[c].nsw = ct.fix_n;
+            fix[c].k0 = f * b->swm + 1;
+            fix[c].force = 1;
+            final_buf = fix[c].dst;
+            any = true;
+        }
+        b->lcur[c] = final_buf;
+        b->kprev[c] = ct.count;
+        b->log[c].push_back(ct.count);
+    }
+    if (any) {
+        BHIP(b, hipMemcpyAsync(b->fix_d, fix.data(), sizeof(lbm::SweepLaunch) * nc, hipMemcpyHostToDevice, b->stream));
+        batch_fix<R>(b);
+        BHIP(b, hipGetLastError());
+    }
+    BHIP(b, hipMemcpyAsync(b->lcur_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+// The stages before (A) and after (B) the potential loop, for buffer parity sp.
+template <typename R>
+void batch_stage(lbm_batch* b, int which, int sp) {
+    auto tb = btable<R>(b);
+    int nc = b->ncases;
+    if (which == 0) {
+        lbm::kb_f_prep<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_f_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+    } else {
+        lbm::kb_h_prep1<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_h_prep2<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_h_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_g_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 0);
+    }
+}
+
+template <typename R>
+int batch_run_stage(lbm_batch* b, int which) {
+    if (b->graphs) {
+        BHIP(b, hipGraphLaunch(b->gexec[which][b->sp], b->stream));
+    } else {
+        batch_stage<R>(b, which, b->sp);
+        BHIP(b, hipGetLastError());
+    }
+    return LBM_OK;
+}
+
+template <typename R>
+int batch_capture(lbm_batch* b) {
+    for (int which = 0; which < 2; which++)
+        for (int sp = 0; sp < 2; sp++) {
+            BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            batch_stage<R>(b, which, sp);
+            BHIP(b, hipStreamEndCapture(b->stream, &b->graph[which][sp]));
+            BHIP(b, hipGraphInstantiate(&b->gexec[which][sp], b->graph[which][sp], nullptr, nullptr, 0));
+        }
+    b->graphs = true;
+    return LBM_OK;
+}
+
+template <typename R>
+int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
+    int nc = b->ncases;
+    auto& cases = bcases<R>(b);
+    cases.resize(nc);
+    std::vector<int> fn(nc), fs(nc);
+    std::vector<double> tol(nc);
+    std::vector<int> maxsw(nc);
+    Ctl* ctl = (Ctl*)(ws + L.ctl);
+    for (int c = 0; c < nc; c++) {
+        cases[c].d = b->dev[c];
+        carve<R>(b->dev[c], ws + L.off[c], &cases[c].s);
+        cases[c].s.ctl = ctl + c;
+        fn[c] = b->node_blocks;
+        fs[c] = b->sweep_blocks;
+        b->node_blocks += b->dev[c].gx * b->dev[c].gy;
+        b->sweep_blocks += b->dev[c].tbx * b->dev[c].tby;
+        tol[c] = b->prm[c].poisson_tol;
+        maxsw[c] = b->prm[c].poisson_max_sweeps;
+    }
+    BHIP(b, hipMemcpyAsync(b->table, cases.data(), sizeof(lbm::BatchCase<R>) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->first_node, fn.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->first_sw, fs.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->tol_d, tol.data(), sizeof(double) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->maxsw_d, maxsw.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->lcur_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    for (int c = 0; c < nc; c++) k_ctl_zero<<<1, 1, 0, b->stream>>>(ctl + c);
+    auto tb = btable<R>(b);
+    lbm::kb_init<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
+    lbm::kb_oml<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
+    BHIP(b, hipGetLastError());
+    int rc = batch_sweeps<R>(b, 2);
+    if (rc) return rc;
+    lbm::kb_vl0<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
+    lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 1);
+    BHIP(b, hipGetLastError());
+    BHIP(b, hipStreamSynchronize(b->stream));
+    if (b->stream) return batch_capture<R>(b);
+    return LBM_OK;
+}
+
+template <typename R>
+int batch_step_impl(lbm_batch* b) {
+    int rc = batch_run_stage<R>(b, 0);
+    if (rc) return rc;
+    rc = batch_sweeps<R>(b, 1);
+    if (rc) return rc;
+    rc = batch_run_stage<R>(b, 1);
+    if (rc) return rc;
+    b->sp ^= 1;
+    b->step++;
+    return LBM_OK;
+}
+
+// Diagnostics and field reads reuse the single-case kernels on one case at a time.
+template <typename R>
+int batch_case_handle(lbm_batch* b, int c, lbm_handle* h) {
+    h->prm = b->prm[c];
+    h->dev = b->dev[c];
+    h->prec = b->prec;
+    h->st<R>() = bcases<R>(b)[c].s;
+    h->stream = b->stream;
+    h->nb = b->dev[c].gx * b->dev[c].gy;
+    h->sp = b->sp;
+    h->lcur = b->lcur[c];
+    h->swm = b->swm;
+    h->dctl = bcases<R>(b)[c].s.ctl;
+    h->partials = bcases<R>(b)[c].s.partials;
+    h->step = b->step;
+    h->hctl = b->ctl_h + c;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_workspace_bytes(int ncases, const lbm_params* cases, size_t* bytes) {
+    int rc = batch_validate(ncases, cases);
+    if (rc) return rc;
+    if (!bytes) return LBM_EINVAL;
+    *bytes = batch_layout(ncases, cases).total;
+    return LBM_OK;
+}
+
+int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t bytes, void* stream,
+                   lbm_batch** out) {
+    int rc = batch_validate(ncases, cases);
+    if (rc) return rc;
+    if (!workspace || !out || ((uintptr_t)workspace % ALIGN) != 0) return LBM_EINVAL;
+    BatchLayout L = batch_layout(ncases, cases);
+    if (bytes < L.total) return LBM_ESPACE;
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_EINVAL;
+    char* ws = (char*)workspace;
+    b->ncases = ncases;
+    b->prec = cases[0].precision;
+    b->swm = sweep_m(&cases[0]);
+    b->stream = (hipStream_t)stream;
+    b->prm.assign(cases, cases + ncases);
+    for (int c = 0; c < ncases; c++) b->dev.push_back(make_dev(&cases[c]));
+    b->table = ws + L.table;
+    b->first_node = (int*)(ws + L.first_node);
+    b->first_sw = (int*)(ws + L.first_sw);
+    b->lcur_d = (int*)(ws + L.lcur);
+    b->lcur0_d = (int*)(ws + L.lcur0);
+    b->tol_d = (double*)(ws + L.tol);
+    b->maxsw_d = (int*)(ws + L.maxsw);
+    b->fix_d = (lbm::SweepLaunch*)(ws + L.fix);
+    b->ctl_d = (Ctl*)(ws + L.ctl);
+    b->lcur.assign(ncases, 0);
+    b->kprev.assign(ncases, 0);
+    b->log.assign(ncases, {});
+    if (hipHostMalloc((void**)&b->ctl_h, sizeof(Ctl) * ncases, hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return LBM_EHIP;
+    }
+    rc = b->prec == LBM_FP32 ? batch_init_impl<float>(b, ws, L) : batch_init_impl<double>(b, ws, L);
+    if (rc) {
+        lbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int n) {
+    if (!b) return LBM_ESTATE;
+    if (n < 0) return LBM_EINVAL;
+    for (int k = 0; k < n; k++) {
+        int rc = b->prec == LBM_FP32 ? batch_step_impl<float>(b) : batch_step_impl<double>(b);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_diagnostics(lbm_batch* b, lbm_diag* per_case) {
+    if (!b) return LBM_ESTATE;
+    if (!per_case) return LBM_EINVAL;
+    int worst = LBM_OK;
+    for (int c = 0; c < b->ncases; c++) {
+        lbm_handle h;
+        if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+        h.log = b->log[c];
+        h.last_sweeps = b->log[c].empty() ? 0 : b->log[c].back();
+        h.last_resid = b->ctl_h[c].resid;
+        int rc = lbm_diagnostics(&h, &per_case[c]);
+        h.hctl = nullptr;  // owned by the batch
+        if (rc == LBM_ENONFINITE) worst = rc;
+        else if (rc) return rc;
+    }
+    return worst;
+}
+
+int lbm_batch_get_field(lbm_batch* b, int c, int field, double* dst) {
+    if (!b) return LBM_ESTATE;
+    if (c < 0 || c >= b->ncases) return LBM_EINVAL;
+    lbm_handle h;
+    if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+    int rc = lbm_get_field(&h, field, dst);
+    h.hctl = nullptr;
+    return rc;
+}
+
+int lbm_batch_sweep_log(lbm_batch* b, int c, int* dst, int cap, int* count) {
+    if (!b) return LBM_ESTATE;
+    if (c < 0 || c >= b->ncases) return LBM_EINVAL;
+    int n = (int)b->log[c].size();
+    if (dst)
+        for (int k = 0; k < n && k < cap; k++) dst[k] = b->log[c][k];
+    if (count) *count = n;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_OK;
+    (void)hipStreamSynchronize(b->stream);
+    for (int w = 0; w < 2; w++)
+        for (int s = 0; s < 2; s++) {
+            if (b->gexec[w][s]) (void)hipGraphExecDestroy(b->gexec[w][s]);
+            if (b->graph[w][s]) (void)hipGraphDestroy(b->graph[w][s]);
+        }
+    if (b->ctl_h) (void)hipHostFree(b->ctl_h);
+    delete b;
+    return LBM_OK;
+}
 
 }  // extern "C"

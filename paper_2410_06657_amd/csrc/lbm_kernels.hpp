@@ -8,12 +8,27 @@
 // which neighbouring threads share through the L1/L2 caches).  Each stage reads one
 // buffer and writes the other, so the kernels of a stage never race.
 //
+// Every kernel is a template on the real type R of storage and arithmetic: R = double
+// (FP64 form) or R = float (FP32 form).  Reductions (potential residual, liquid volume,
+// diagnostics) are FP64 in both.  In the FP32 form two population sets are stored as
+// deviations from a per-node base, because their increments fall below an FP32 ulp of
+// the raw values: the rest link of g and H minus h_b = psi rho_s L (the node's latent
+// content, moved to the new psi every step; the rest link never streams, so this is
+// exact), and each D2Q5 link as a pair (b_i, l_i) of an FP32 base and an FP32 remainder
+// whose sum is the link.  The pair is renormalised (b_i <- b_i + l_i by an error-free
+// two-sum) at the start of every potential solve and between batches of sweeps, so the
+// sweeps work on remainders that hold only the change since then; the constant base terms
+// of a launch are evaluated in FP64.  The FP64 form keeps no base: its arithmetic is the
+// raw scheme.
+//
 // Blocks are 256 threads (4 waves of 64) covering a 64 x 4 tile.  The 1-D grid is
 // remapped so that each of the 8 XCDs (which receive workgroups round-robin) works
 // on one contiguous band of tiles: neighbouring tiles share that XCD's L2.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace lbm {
 
@@ -33,6 +48,7 @@ struct Dev {
     int nx, ny, pitch;
     int64_t plane;                  // elements per field plane = pitch * ny
     int gx, gy;                     // tiles in x and y
+    int tbx, tby;                   // tiles of the blocked potential sweep in x and y
     double omf, facf;               // 1/tau_f and 1 - 1/(2 tau_f)
     double beta, kappa, wet, W;     // Eq. (5) and the wetting slope (4/W) cos(theta)
     double rho_s, rho_l, rho_g, mu_s, mu_l, mu_g;
@@ -50,6 +66,7 @@ struct Dev {
 // next sweep's block 0, or a one-block finalize kernel) adds them in block order.
 struct Ctl {
     int done, count, conv, pad0;     // potential loop: finished, sweeps, converged
+    int fix_launch, fix_n;           // launch holding the final sweep, and its sweeps up to it
     int min_sweeps, max_sweeps;
     double tol, resid;
     double V_l0, V_prev, t_fre;      // freezing-time detector
@@ -60,17 +77,26 @@ struct Ctl {
 };
 
 // Offsets into the partial-sum array (nb = blocks of a node-parallel launch).
-__host__ __device__ constexpr int64_t part_sweep(int nb, int slot) { return (int64_t)2 * nb * slot; }
-__host__ __device__ constexpr int64_t part_vl(int nb) { return (int64_t)4 * nb; }
-__host__ __device__ constexpr int64_t part_diag(int nb) { return (int64_t)5 * nb; }
-__host__ __device__ constexpr int64_t part_total(int nb) { return (int64_t)12 * nb; }
+constexpr int SW_MAXM = 8;
+// FP32 potential base moves every REBASE_SWEEPS sweeps of a long solve (multiple of SW_MAXM)
+constexpr int REBASE_SWEEPS = 256;  // most sweeps one blocked launch performs
+__host__ __device__ constexpr int64_t part_vl(int nb) { return 0; }
+__host__ __device__ constexpr int64_t part_diag(int nb) { return (int64_t)nb; }
+__host__ __device__ constexpr int64_t part_sweep(int nb, int nbt, int slot) {
+    return (int64_t)8 * nb + (int64_t)slot * SW_MAXM * 2 * nbt;
+}
+__host__ __device__ constexpr int64_t part_total(int nb, int nbt) {
+    return (int64_t)8 * nb + (int64_t)2 * SW_MAXM * 2 * nbt;
+}
 
-__device__ __forceinline__ double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
+template <typename R>
+__device__ __forceinline__ R clamp01(R x) { return x < R(0) ? R(0) : (x > R(1) ? R(1) : x); }
 
 // Eq. (1) with psi clamped to [0, 1].
-__device__ __forceinline__ double mix(double s, double l, double g, double psi, double fs) {
-    double pc = clamp01(psi);
-    return fs * s + (1.0 - fs) * pc * l + (1.0 - fs) * (1.0 - pc) * g;
+template <typename R>
+__device__ __forceinline__ R mix(double s, double l, double g, R psi, R fs) {
+    R pc = clamp01(psi);
+    return fs * R(s) + (R(1) - fs) * pc * R(l) + (R(1) - fs) * (R(1) - pc) * R(g);
 }
 
 __device__ __forceinline__ int wrapx(int i, int nx) { return i < 0 ? i + nx : (i >= nx ? i - nx : i); }
@@ -79,50 +105,56 @@ __device__ __forceinline__ int64_t at(const Dev& d, int i, int j) { return (int6
 
 // Field value with a ghost rule for rows -1 and ny (x already wrapped).
 enum Ghost { GMIRROR = 0, GWET = 1, GPHI = 2 };
-template <int G>
-__device__ __forceinline__ double ghosted(const double* __restrict__ f, const Dev& d, int i, int j) {
+template <int G, typename R>
+__device__ __forceinline__ R ghosted(const R* __restrict__ f, const Dev& d, int i, int j) {
     if (j < 0) {
-        double b = f[i];
-        if (G == GWET) return b + d.wet * b * (1.0 - b);
-        if (G == GPHI) return 2.0 * d.phi_bot - b;
+        R b = f[i];
+        if (G == GWET) return b + R(d.wet) * b * (R(1) - b);
+        if (G == GPHI) return R(2.0 * d.phi_bot) - b;
         return b;
     }
     if (j >= d.ny) {
-        double t = f[at(d, i, d.ny - 1)];
-        if (G == GPHI) return 2.0 * d.phi_top - t;
+        R t = f[at(d, i, d.ny - 1)];
+        if (G == GPHI) return R(2.0 * d.phi_top) - t;
         return t;  // mirror; psi meets the top wall at 90 degrees
     }
     return f[at(d, i, j)];
 }
 
 // 3x3 neighbourhood v[dy+1][dx+1] around (i, j).
-template <int G>
-__device__ __forceinline__ void load3(const double* __restrict__ f, const Dev& d, int i, int j, double v[3][3]) {
+template <int G, typename R>
+__device__ __forceinline__ void load3(const R* __restrict__ f, const Dev& d, int i, int j, R v[3][3]) {
     int im = wrapx(i - 1, d.nx), ip = wrapx(i + 1, d.nx);
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++) {
-        v[dy + 1][0] = ghosted<G>(f, d, im, j + dy);
-        v[dy + 1][1] = ghosted<G>(f, d, i, j + dy);
-        v[dy + 1][2] = ghosted<G>(f, d, ip, j + dy);
+        v[dy + 1][0] = ghosted<G, R>(f, d, im, j + dy);
+        v[dy + 1][1] = ghosted<G, R>(f, d, i, j + dy);
+        v[dy + 1][2] = ghosted<G, R>(f, d, ip, j + dy);
     }
 }
 
 // Eq. (36a) and (36b) on a 3x3 neighbourhood.
-__device__ __forceinline__ void grad_lap(const double v[3][3], double& gx, double& gy, double& lap) {
-    gx = 3.0 * (WA * (v[1][2] - v[1][0]) + WD * (v[2][2] - v[2][0] - v[0][0] + v[0][2]));
-    gy = 3.0 * (WA * (v[2][1] - v[0][1]) + WD * (v[2][2] + v[2][0] - v[0][0] - v[0][2]));
-    double c = v[1][1];
-    lap = 6.0 * (WA * (v[1][2] + v[1][0] + v[2][1] + v[0][1] - 4.0 * c) +
-                 WD * (v[2][2] + v[2][0] + v[0][0] + v[0][2] - 4.0 * c));
+template <typename R>
+__device__ __forceinline__ void grad_lap(const R v[3][3], R& gx, R& gy, R& lap) {
+    const R wa = R(WA), wd = R(WD);
+    gx = R(3) * (wa * (v[1][2] - v[1][0]) + wd * (v[2][2] - v[2][0] - v[0][0] + v[0][2]));
+    gy = R(3) * (wa * (v[2][1] - v[0][1]) + wd * (v[2][2] + v[2][0] - v[0][0] - v[0][2]));
+    R c = v[1][1];
+    lap = R(6) * (wa * (v[1][2] + v[1][0] + v[2][1] + v[0][1] - R(4) * c) +
+                  wd * (v[2][2] + v[2][0] + v[0][0] + v[0][2] - R(4) * c));
 }
 
-// Tile of this block, XCD-aware.
-__device__ __forceinline__ void node_of(const Dev& d, int& i, int& j) {
-    int nb = d.gx * d.gy;
-    int b = blockIdx.x;
+// XCD-aware block order: consecutive workgroup ids go to the 8 XCDs round-robin, so
+// block b of a grid of nb blocks works on tile (b mod 8) * nb/8 + b/8, giving each XCD
+// one contiguous band of tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
     int per = nb >> 3;
-    int lb = (per << 3) == nb ? (b & 7) * per + (b >> 3) : b;
-    int bx = lb % d.gx, by = lb / d.gx;
+    return (per << 3) == nb ? (b & 7) * per + (b >> 3) : b;
+}
+
+// Node of this thread in tile `t` of the node grid.
+__device__ __forceinline__ void node_of(const Dev& d, int t, int& i, int& j) {
+    int bx = t % d.gx, by = t / d.gx;
     i = bx * TX + (threadIdx.x & (TX - 1));
     j = by * TY + (threadIdx.x / TX);
 }
@@ -157,91 +189,101 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // Collision of one population at its source node.
 
 // Phase field, Eqs. (15), (18), (19): A = d/dt(psi u) + c_s^2 lambda n.
-__device__ __forceinline__ double coll_f(int q, double fq, double psi, double ux, double uy,
-                                         double Ax, double Ay, double md, const Dev& d) {
-    double cu = QX[q] * ux + QY[q] * uy;
-    double feq = QW[q] * psi * (1.0 + 3.0 * cu);
-    double F = QW[q] * (3.0 * (QX[q] * Ax + QY[q] * Ay) + psi * md);
-    return fq - d.omf * (fq - feq) + d.facf * F;
+template <typename R>
+__device__ __forceinline__ R coll_f(int q, R fq, R psi, R ux, R uy, R Ax, R Ay, R md, const Dev& d) {
+    R cu = R(QX[q]) * ux + R(QY[q]) * uy;
+    R feq = R(QW[q]) * psi * (R(1) + R(3) * cu);
+    R F = R(QW[q]) * (R(3) * (R(QX[q]) * Ax + R(QY[q]) * Ay) + psi * md);
+    return fq - R(d.omf) * (fq - feq) + R(d.facf) * F;
 }
 
 // Flow, Eqs. (21)-(24).  (Ftx, Fty) = F~, (Gx, Gy) = F + rho f_solid.
+template <typename R>
 struct HIn {
-    double p, rho, ux, uy, S, Ftx, Fty, Gx, Gy, om;
+    R p, rho, ux, uy, S, Ftx, Fty, Gx, Gy, om;
 };
-__device__ __forceinline__ double coll_h(int q, double hq, const HIn& a) {
-    double cu = QX[q] * a.ux + QY[q] * a.uy;
-    double uu = a.ux * a.ux + a.uy * a.uy;
-    double s = QW[q] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-    double heq = (q == 0 ? (QW[q] - 1.0) : QW[q]) * 3.0 * a.p + a.rho * s;
-    double cF = QX[q] * a.Ftx + QY[q] * a.Fty;
-    double uF = a.ux * a.Ftx + a.uy * a.Fty;
-    double cG = QX[q] * a.Gx + QY[q] * a.Gy;
-    double R = QW[q] * (a.S + 3.0 * cG + 9.0 * (cu * cF - CS2 * uF));
-    return hq - a.om * (hq - heq) + (1.0 - 0.5 * a.om) * R;
+template <typename R>
+__device__ __forceinline__ R coll_h(int q, R hq, const HIn<R>& a) {
+    R cu = R(QX[q]) * a.ux + R(QY[q]) * a.uy;
+    R uu = a.ux * a.ux + a.uy * a.uy;
+    R s = R(QW[q]) * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    R heq = R(q == 0 ? (QW[q] - 1.0) : QW[q]) * R(3) * a.p + a.rho * s;
+    R cF = R(QX[q]) * a.Ftx + R(QY[q]) * a.Fty;
+    R uF = a.ux * a.Ftx + a.uy * a.Fty;
+    R cG = R(QX[q]) * a.Gx + R(QY[q]) * a.Gy;
+    R Rq = R(QW[q]) * (a.S + R(3) * cG + R(9) * (cu * cF - R(CS2) * uF));
+    return hq - a.om * (hq - heq) + (R(1) - R(0.5) * a.om) * Rq;
 }
 
-// Enthalpy, Eqs. (28)-(29) with the source weighted by omega_i.
+// Enthalpy, Eqs. (28)-(29) with the source weighted by omega_i.  H is the stored H - G.
+template <typename R>
 struct GIn {
-    double H, T, C, ux, uy, om, Q;
+    R H, T, C, ux, uy, om, Q;
 };
-__device__ __forceinline__ double coll_g(int q, double gq, const GIn& a, double Cref) {
-    double uu = a.ux * a.ux + a.uy * a.uy;
-    double geq;
+template <typename R>
+__device__ __forceinline__ R coll_g(int q, R gq, const GIn<R>& a, R Cref) {
+    R uu = a.ux * a.ux + a.uy * a.uy;
+    R geq;
     if (q == 0) {
-        geq = a.H - Cref * a.T + W0 * (Cref * a.T - 1.5 * a.C * a.T * uu);
+        geq = a.H - Cref * a.T + R(W0) * (Cref * a.T - R(1.5) * a.C * a.T * uu);
     } else {
-        double cu = QX[q] * a.ux + QY[q] * a.uy;
-        geq = QW[q] * (Cref * a.T + a.C * a.T * (3.0 * cu + 4.5 * (cu * cu - CS2 * uu)));
+        R cu = R(QX[q]) * a.ux + R(QY[q]) * a.uy;
+        geq = R(QW[q]) * (Cref * a.T + a.C * a.T * (R(3) * cu + R(4.5) * (cu * cu - R(CS2) * uu)));
     }
-    return gq - a.om * (gq - geq) + (1.0 - 0.5 * a.om) * QW[q] * a.Q;
+    return gq - a.om * (gq - geq) + (R(1) - R(0.5) * a.om) * R(QW[q]) * a.Q;
 }
 
-// Eq. (7) on the volumetric enthalpy, T_s = T_l = 0, latent heat psi * Lvol.
-__device__ __forceinline__ void invert(const Dev& d, double H, double psi, double& T, double& fl) {
-    double pc = clamp01(psi);
-    double Leff = pc * d.Lvol;
-    if (H < 0.0) {
-        fl = 0.0;
-        T = H / mix(d.C_s, d.C_l, d.C_g, pc, pc);
-    } else if (H <= Leff) {
-        fl = Leff > 0.0 ? H / Leff : 1.0;
-        T = 0.0;
+// Eq. (7) on the volumetric enthalpy, T_s = T_l = 0, latent heat psi * Lvol.  Hs is the
+// stored enthalpy H - G with G the node's base (0 in FP64).
+template <typename R>
+__device__ __forceinline__ void invert(const Dev& d, R Hs, R G, R psi, R& T, R& fl) {
+    R pc = clamp01(psi);
+    R Leff = pc * R(d.Lvol);
+    if (Hs < -G) {
+        fl = R(0);
+        T = (Hs + G) / mix<R>(d.C_s, d.C_l, d.C_g, pc, pc);
+    } else if (Hs <= Leff - G) {
+        fl = Leff > R(0) ? (Hs + G) / Leff : R(1);
+        T = R(0);
     } else {
-        fl = 1.0;
-        T = (H - Leff) / mix(d.C_s, d.C_l, d.C_g, pc, 0.0);
+        fl = R(1);
+        T = (Hs + (G - Leff)) / mix<R>(d.C_s, d.C_l, d.C_g, pc, R(0));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Pointers of one stage.
 
+template <typename R>
 struct State {
-    double* f[2];
-    double* h[2];
-    double* g[2];
-    double* l[2];      // D2Q5 moving links E, N, W, S (the rest population never feeds phi)
-    double* psi[2];
-    double* ux[2];
-    double* uy[2];
-    double* p[2];
-    double* H[2];
-    double* T[2];
-    double* fs[2];
-    double* md[2];
-    double* phi[2];
-    double *usx, *usy, *pux, *puy, *Ax, *Ay, *oml, *S, *Fx, *Fy;
-    double *rho, *Ftx, *Fty, *Gx, *Gy, *omh, *fl;
-    double* partials;  // per-block reduction partials
+    R* f[2];
+    R* h[2];
+    R* g[2];
+    R* l[3];      // D2Q5 moving links E, N, W, S (the rest population never feeds phi)
+    R* psi[2];
+    R* ux[2];
+    R* uy[2];
+    R* p[2];
+    R* H[2];
+    R* T[2];
+    R* fs[2];
+    R* md[2];
+    R* phi[3];         // raw phi
+    R* lb;             // 4 base planes of the FP32 potential links (unused in FP64)
+    R* hb;             // enthalpy base of the FP32 rest link and H (unused in FP64)
+    R *usx, *usy, *pux, *puy, *Ax, *Ay, *oml, *S, *Fx, *Fy;
+    R *rho, *Ftx, *Fty, *Gx, *Gy, *omh, *fl;
+    double* partials;  // per-block FP64 reduction partials
     Ctl* ctl;
 };
 
 // ---------------------------------------------------------------------------
 // Initialisation (Algorithm 1, first block): fields, equilibria in buffer 0.
 
-__global__ void __launch_bounds__(NT) k_init(Dev d, State s) {
+template <typename R>
+__device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
     double v;
@@ -253,202 +295,418 @@ __global__ void __launch_bounds__(NT) k_init(Dev d, State s) {
         double dy = j - d.yc;
         v = 0.5 * (1.0 + tanh(2.0 * (d.R0 - sqrt(dx * dx + dy * dy)) / d.W));
     }
-    double pc = clamp01(v);
-    double Hn = mix(d.C_s, d.C_l, d.C_g, v, 0.0) * d.T_g + pc * d.Lvol;
-    double T, fl;
-    invert(d, Hn, v, T, fl);
-    double fs = pc * (1.0 - fl);
+    R psi = R(v);
+    R pc = clamp01(psi);
+    constexpr bool based = std::is_same<R, float>::value;
+    R hb = based ? pc * R(d.Lvol) : R(0);
+    R Hn = mix<R>(d.C_s, d.C_l, d.C_g, psi, R(0)) * R(d.T_g) + (pc * R(d.Lvol) - hb);
+    if (based) s.hb[n] = hb;
+    R T, fl;
+    invert<R>(d, Hn, hb, psi, T, fl);
+    R fs = pc * (R(1) - fl);
     double phi0 = d.phi_bot + (d.phi_top - d.phi_bot) * (j + 0.5) / d.ny;
-    s.psi[0][n] = v;
+    s.psi[0][n] = psi;
     s.ux[0][n] = 0; s.uy[0][n] = 0; s.usx[n] = 0; s.usy[n] = 0; s.p[0][n] = 0;
     s.H[0][n] = Hn; s.T[0][n] = T; s.fs[0][n] = fs; s.md[0][n] = 0; s.fl[n] = fl;
     s.pux[n] = 0; s.puy[n] = 0;
-    double rho = mix(d.rho_s, d.rho_l, d.rho_g, v, fs);
-    double C = mix(d.C_s, d.C_l, d.C_g, v, fs);
-    HIn hin{0, rho, 0, 0, 0, 0, 0, 0, 0, 1.0};
-    GIn gin{Hn, T, C, 0, 0, 1.0, 0};
+    R rho = mix<R>(d.rho_s, d.rho_l, d.rho_g, psi, fs);
+    R C = mix<R>(d.C_s, d.C_l, d.C_g, psi, fs);
+    HIn<R> hin{0, rho, 0, 0, 0, 0, 0, 0, 0, R(1)};
+    GIn<R> gin{Hn, T, C, 0, 0, R(1), 0};
 #pragma unroll
     for (int q = 0; q < 9; q++) {
-        s.f[0][q * d.plane + n] = QW[q] * v;
-        s.h[0][q * d.plane + n] = coll_h(q, 0.0, hin);  // omega = 1 returns h_eq
-        s.g[0][q * d.plane + n] = coll_g(q, 0.0, gin, d.Cref);
+        s.f[0][q * d.plane + n] = R(QW[q]) * psi;
+        s.h[0][q * d.plane + n] = coll_h<R>(q, R(0), hin);  // omega = 1 returns h_eq
+        s.g[0][q * d.plane + n] = coll_g<R>(q, R(0), gin, R(d.Cref));
     }
-    double l = LWA * phi0;
+    double leq = LWA * phi0;
+    R lbase = based ? R(leq) : R(0);
+    R l = R(leq - (double)lbase);  // FP32: the remainder of the base (FP64: the link)
 #pragma unroll
-    for (int q = 0; q < 4; q++) s.l[0][q * d.plane + n] = l;
-    s.phi[0][n] = (l + l + l + l) / (1.0 - LW0);
+    for (int q = 0; q < 4; q++) {
+        s.l[0][q * d.plane + n] = l;
+        if (based) s.lb[q * d.plane + n] = lbase;
+    }
+    s.phi[0][n] = based ? R(phi0) : (l + l + l + l) * R(1.0 / (1.0 - LW0));
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_init(Dev d, State<R> s) {
+    b_init<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
 // Stage 1a: A = d/dt(psi u) + c_s^2 lambda n at every node (Eqs. (19), (35)),
 // then remember psi^n u^n for the next step.
-__global__ void __launch_bounds__(NT) k_f_prep(Dev d, State s, int sp) {
+template <typename R>
+__device__ __forceinline__ void b_f_prep(const Dev& d, const State<R>& s, int sp, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    const double* psi = s.psi[sp];
-    double v[3][3];
-    load3<GWET>(psi, d, i, j, v);
-    double gx, gy, lap;
-    grad_lap(v, gx, gy, lap);
-    double mag = sqrt(gx * gx + gy * gy);
-    double nx = 0.0, ny = 0.0;
-    if (mag > 1e-12) {
+    const R* psi = s.psi[sp];
+    R v[3][3];
+    load3<GWET, R>(psi, d, i, j, v);
+    R gx, gy, lap;
+    grad_lap<R>(v, gx, gy, lap);
+    R mag = sqrt(gx * gx + gy * gy);
+    R nx = R(0), ny = R(0);
+    if (mag > R(1e-12)) {
         nx = gx / mag;
         ny = gy / mag;
     }
-    double ps = v[1][1];
-    double lam = 4.0 * ps * (1.0 - ps) / d.W;
-    double ux = s.ux[sp][n], uy = s.uy[sp][n];
-    double px = ps * ux, py = ps * uy;
-    s.Ax[n] = (px - s.pux[n]) + CS2 * lam * nx;
-    s.Ay[n] = (py - s.puy[n]) + CS2 * lam * ny;
+    R ps = v[1][1];
+    R lam = R(4) * ps * (R(1) - ps) / R(d.W);
+    R ux = s.ux[sp][n], uy = s.uy[sp][n];
+    R px = ps * ux, py = ps * uy;
+    s.Ax[n] = (px - s.pux[n]) + R(CS2) * lam * nx;
+    s.Ay[n] = (py - s.puy[n]) + R(CS2) * lam * ny;
     s.pux[n] = px;
     s.puy[n] = py;
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_f_prep(Dev d, State<R> s, int sp) {
+    b_f_prep<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Stage 1b: f pulled and collided at its source, half-way bounce-back at the
 // walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.
-__global__ void __launch_bounds__(NT) k_f_stream(Dev d, State s, int sp) {
+template <typename R>
+__device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int sp, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    const double* fsrc = s.f[sp];
-    double* fdst = s.f[sp ^ 1];
-    const double* psi = s.psi[sp];
-    const double* ux = s.ux[sp];
-    const double* uy = s.uy[sp];
-    const double* md = s.md[sp];
-    double sum = 0.0;
+    const R* fsrc = s.f[sp];
+    R* fdst = s.f[sp ^ 1];
+    const R* psi = s.psi[sp];
+    const R* ux = s.ux[sp];
+    const R* uy = s.uy[sp];
+    const R* md = s.md[sp];
+    R sum = R(0);
 #pragma unroll
     for (int q = 0; q < 9; q++) {
         int jj = j - QY[q];
-        double val;
+        R val;
         if (jj < 0 || jj >= d.ny) {
             int o = QOPP[q];
-            val = coll_f(o, fsrc[o * d.plane + n], psi[n], ux[n], uy[n], s.Ax[n], s.Ay[n], md[n], d);
+            val = coll_f<R>(o, fsrc[o * d.plane + n], psi[n], ux[n], uy[n], s.Ax[n], s.Ay[n], md[n], d);
         } else {
             int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            val = coll_f(q, fsrc[q * d.plane + m], psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m], d);
+            val = coll_f<R>(q, fsrc[q * d.plane + m], psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m], d);
         }
         fdst[q * d.plane + n] = val;
         sum += val;
     }
-    double pn = sum / (1.0 - 0.5 * md[n]);
+    R pn = sum / (R(1) - R(0.5) * md[n]);
     s.psi[sp ^ 1][n] = pn;
-    double sig = mix(d.sig_s, d.sig_l, d.sig_g, pn, s.fs[sp][n]);
-    s.oml[n] = 1.0 / (sig / CS2 + 0.5);
+    R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, pn, s.fs[sp][n]);
+    s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_f_stream(Dev d, State<R> s, int sp) {
+    b_f_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // 1/tau_l = 1/(sigma/c_s^2 + 1/2) from the current psi and f_s (Sec. 3.4).
-__global__ void __launch_bounds__(NT) k_oml(Dev d, State s, int sp) {
+template <typename R>
+__device__ __forceinline__ void b_oml(const Dev& d, const State<R>& s, int sp, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    double sig = mix(d.sig_s, d.sig_l, d.sig_g, s.psi[sp][n], s.fs[sp][n]);
-    s.oml[n] = 1.0 / (sig / CS2 + 0.5);
+    R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, s.psi[sp][n], s.fs[sp][n]);
+    s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_oml(Dev d, State<R> s, int sp) {
+    b_oml<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
-// Convergence test of sweep j, run by one block: adds the block partials of that
-// sweep in block order and updates the loop state (thread 0).
-__device__ __forceinline__ void sweep_check(const Dev& d, const State& s, int j, double* sh) {
-    int nb = d.gx * d.gy;
-    const double* pv = s.partials + part_sweep(nb, j & 1);
-    double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += NT) {
-        a += pv[2 * k];
-        b += pv[2 * k + 1];
-    }
-    a = block_sum(a, sh);
-    b = block_sum(b, sh);
-    if (threadIdx.x == 0) {
-        Ctl* c = s.ctl;
-        double r = a == 0.0 ? 0.0 : (b > 0.0 ? sqrt(a) / sqrt(b) : INFINITY);
+// Blocked potential sweeps (Eqs. (31)-(34)).
+//
+// One launch advances the D2Q5 links by up to M sweeps.  A 256-thread block owns a
+// region of 64 columns x SW_RY rows; wave w holds rows [w*SW_NPT, (w+1)*SW_NPT) of the
+// region, one column per lane, in registers.  Per sweep each node collides its four
+// moving links towards w_i phi with its own 1/tau_l, then pulls: the E/W links come from
+// the neighbouring lanes (wave-wide lane shifts), the N/S links from the rows above and
+// below in the same lane, and only the rows at wave boundaries pass through LDS.  Walls:
+// half-way anti-bounce-back at the electrodes; x is periodic (region columns wrap).
+// After m sweeps the outer m columns/rows of the region are stale, so a block writes only
+// its inner (64 - 2M) x (SW_RY - 2M) nodes.  For every sweep the block stores FP64 partial
+// sums of |phi^k - phi^{k-1}|^2 and |phi^k|^2 over the nodes it writes; block 0 of the next
+// launch adds them in block order and ends the loop at the first sweep that passes the
+// test (the host then recomputes that launch's sweeps up to it if it was not the last).
+constexpr int SW_NPT = 8;
+constexpr int SW_RY = 4 * SW_NPT;
+constexpr double INV_1MW0 = 1.0 / (1.0 - LW0);  // phi = (l_1 + l_2 + l_3 + l_4) / (1 - w_0), Eq. (34)
+
+struct SweepLaunch {
+    int src, dst;               // potential buffers (0..2)
+    int nsw;                    // sweeps in this launch (0: only test the previous launch)
+    int k0;                     // index of its first sweep within the solve (from 1)
+    int slot;                   // partial-sum slot of this launch
+    int prev_k0, prev_nsw, prev_slot;  // previous launch to test (prev_nsw = 0: none)
+    int launch;                 // index of this launch within the solve
+    int force;                  // run even if the loop has ended (recomputation)
+};
+
+template <int M, typename R>
+__device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh) {
+    int nbt = d.tbx * d.tby, nb = d.gx * d.gy;
+    const double* pv = s.partials + part_sweep(nb, nbt, a.prev_slot);
+    double acc[2 * M];
+#pragma unroll
+    for (int m = 0; m < 2 * M; m++) acc[m] = 0.0;
+    for (int b = threadIdx.x; b < nbt; b += NT)
+#pragma unroll
+        for (int m = 0; m < M; m++)
+            if (m < a.prev_nsw) {
+                acc[2 * m] += pv[((int64_t)m * nbt + b) * 2];
+                acc[2 * m + 1] += pv[((int64_t)m * nbt + b) * 2 + 1];
+            }
+#pragma unroll
+    for (int m = 0; m < 2 * M; m++) acc[m] = block_sum(acc[m], sh);
+    if (threadIdx.x != 0) return;
+    Ctl* c = s.ctl;
+    for (int m = 0; m < a.prev_nsw && m < M; m++) {
+        double da = acc[2 * m], pa = acc[2 * m + 1];
+        double r = da == 0.0 ? 0.0 : (pa > 0.0 ? sqrt(da) / sqrt(pa) : INFINITY);
+        int j = a.prev_k0 + m;
         c->resid = r;
         c->count = j;
         int conv = c->tol >= 0.0 && j >= c->min_sweeps && r <= c->tol;
-        c->conv = conv;
-        if (conv || j >= c->max_sweeps) c->done = 1;
+        if (conv || j >= c->max_sweeps) {
+            c->conv = conv;
+            c->done = 1;
+            c->fix_launch = a.launch - 1;
+            c->fix_n = m + 1;
+            break;
+        }
     }
 }
 
-// Potential sweep k of a solve (Eqs. (31)-(34)): D2Q5 links pulled and collided at their
-// source, half-way anti-bounce-back at the electrodes, the new phi, and per-block FP64
-// partial sums of |phi^k - phi^{k-1}|^2 and |phi^k|^2.  Block 0 also tests sweep k-1,
-// whose partials the previous launch stored; when that sweep converged, this launch's
-// output (written to the other buffer) is discarded and the state after sweep k-1 stands.
-// Launch k = max_sweeps + 1 only tests the last sweep.  `lcur` is the buffer holding the
-// state before sweep 1.
-__global__ void __launch_bounds__(NT) k_sweep(Dev d, State s, int k, int lcur) {
+template <int M, typename R>
+__device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& a, int tile) {
+    // every product is rounded on its own, so the result does not depend on how the
+    // compiler unrolls the M sweeps (bitwise equal for every M)
+#pragma clang fp contract(off)
+    __shared__ R bup[2][4][64], bdn[2][4][64];
     __shared__ double sh[NT / 64];
     const Ctl* c = s.ctl;
-    if (c->done) return;
-    if (k > c->max_sweeps) {
-        if (blockIdx.x == 0) sweep_check(d, s, k - 1, sh);
-        return;
-    }
-    int src = (lcur + k - 1) & 1;
-    const double* lsrc = s.l[src];
-    double* ldst = s.l[src ^ 1];
-    const double* phs = s.phi[src];
-    double* phd = s.phi[src ^ 1];
-    int i, j;
-    node_of(d, i, j);
-    double d2 = 0.0, p2 = 0.0;
-    if (i < d.nx && j < d.ny) {
-        int64_t n = at(d, i, j);
+    if (c->done && !a.force) return;
+    if (a.nsw > 0) {
+        constexpr int OX = 64 - 2 * M, OY = SW_RY - 2 * M;
+        const R inv = R(INV_1MW0), lw = R(LWA);
+        int nbt = d.tbx * d.tby;
+        int bx = tile % d.tbx, by = tile / d.tbx;
+        int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        int x0 = bx * OX - M, y0 = by * OY - M + w * SW_NPT;
+        int graw = x0 + lane;
+        int gi = graw % d.nx;
+        if (gi < 0) gi += d.nx;
+        const bool ownx = lane >= M && lane < M + OX && graw < d.nx;
+        const R* ls = s.l[a.src];
         const int64_t P = d.plane;
-        int64_t nw = at(d, wrapx(i - 1, d.nx), j), ne = at(d, wrapx(i + 1, d.nx), j);
-        // E-moving link from the west neighbour, W-moving from the east neighbour
-        double l1 = lsrc[0 * P + nw];
-        l1 = l1 - s.oml[nw] * (l1 - LWA * phs[nw]);
-        double l3 = lsrc[2 * P + ne];
-        l3 = l3 - s.oml[ne] * (l3 - LWA * phs[ne]);
-        double l2, l4;
-        if (j > 0) {
-            int64_t m = n - d.pitch;
-            l2 = lsrc[1 * P + m];
-            l2 = l2 - s.oml[m] * (l2 - LWA * phs[m]);
-        } else {
-            double o = lsrc[3 * P + n];
-            o = o - s.oml[n] * (o - LWA * phs[n]);
-            l2 = -o + 2.0 * LWA * d.phi_bot;
+        constexpr bool based = std::is_same<R, float>::value;
+        R L1[SW_NPT], L2[SW_NPT], L3[SW_NPT], L4[SW_NPT], OM[SW_NPT], PB[SW_NPT];
+#pragma unroll
+        for (int k = 0; k < SW_NPT; k++) {
+            int gj = y0 + k;
+            if (gj >= 0 && gj < d.ny) {
+                int64_t n = at(d, gi, gj);
+                L1[k] = ls[n];
+                L2[k] = ls[P + n];
+                L3[k] = ls[2 * P + n];
+                L4[k] = ls[3 * P + n];
+                OM[k] = s.oml[n];
+            } else {
+                L1[k] = L2[k] = L3[k] = L4[k] = OM[k] = R(0);
+            }
+            PB[k] = R(0);
         }
-        if (j < d.ny - 1) {
-            int64_t m = n + d.pitch;
-            l4 = lsrc[3 * P + m];
-            l4 = l4 - s.oml[m] * (l4 - LWA * phs[m]);
-        } else {
-            double o = lsrc[1 * P + n];
-            o = o - s.oml[n] * (o - LWA * phs[n]);
-            l4 = -o + 2.0 * LWA * d.phi_top;
+        double accd[M], accp[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) accd[m] = accp[m] = 0.0;
+        // FP32 pair storage: with link = b + l and phi_B the base's moment, the collided
+        // link is A(l) + C with A the collision of the remainders on their own moment and
+        // C = b - omega (b - w phi_B) constant within the launch.  A remainder pulled from
+        // node y therefore gains D = C(y) - b(x); at the electrodes the anti-bounce-back
+        // remainder is D - A with D = 2 w phi_wall - C_opp(x) - b(x).  D is formed in FP64
+        // and rounded once (it is a small difference of nearly equal bases).
+        R D1[SW_NPT], D2[SW_NPT], D3[SW_NPT], D4[SW_NPT];
+        if constexpr (based) {
+            __shared__ double cup[4][64], cdn[4][64];
+            double C2[SW_NPT], C4[SW_NPT];
+            R B2[SW_NPT], B4[SW_NPT];
+#pragma unroll
+            for (int k = 0; k < SW_NPT; k++) {
+                int gj = y0 + k;
+                R b1 = R(0), b2 = R(0), b3 = R(0), b4 = R(0);
+                if (gj >= 0 && gj < d.ny) {
+                    int64_t n = at(d, gi, gj);
+                    b1 = s.lb[n];
+                    b2 = s.lb[P + n];
+                    b3 = s.lb[2 * P + n];
+                    b4 = s.lb[3 * P + n];
+                }
+                double pb = (((double)b1 + (double)b2) + ((double)b3 + (double)b4)) * INV_1MW0;
+                double om = (double)OM[k];
+                double e = LWA * pb;
+                double c1 = (double)b1 - om * ((double)b1 - e);
+                double c3 = (double)b3 - om * ((double)b3 - e);
+                C2[k] = (double)b2 - om * ((double)b2 - e);
+                C4[k] = (double)b4 - om * ((double)b4 - e);
+                D1[k] = R(__shfl_up(c1, 1, 64) - (double)b1);
+                D3[k] = R(__shfl_down(c3, 1, 64) - (double)b3);
+                B2[k] = b2;
+                B4[k] = b4;
+                PB[k] = R(pb);
+            }
+            cup[w][lane] = C2[SW_NPT - 1];
+            cdn[w][lane] = C4[0];
+            __syncthreads();
+            double cbelow = w > 0 ? cup[w - 1][lane] : 0.0;
+            double cabove = w < 3 ? cdn[w + 1][lane] : 0.0;
+#pragma unroll
+            for (int k = 0; k < SW_NPT; k++) {
+                int gj = y0 + k;
+                double c2n = k > 0 ? C2[k - 1] : cbelow;
+                double c4n = k < SW_NPT - 1 ? C4[k + 1] : cabove;
+                if (gj == 0) c2n = 2.0 * LWA * d.phi_bot - C4[k];
+                if (gj == d.ny - 1) c4n = 2.0 * LWA * d.phi_top - C2[k];
+                D2[k] = R(c2n - (double)B2[k]);
+                D4[k] = R(c4n - (double)B4[k]);
+            }
         }
-        ldst[0 * P + n] = l1;
-        ldst[1 * P + n] = l2;
-        ldst[2 * P + n] = l3;
-        ldst[3 * P + n] = l4;
-        double ph = (l1 + l2 + l3 + l4) / (1.0 - LW0);
-        phd[n] = ph;
-        double dd = ph - phs[n];
-        d2 = dd * dd;
-        p2 = ph * ph;
+        const R wbot0 = R(2.0 * LWA * d.phi_bot), wtop0 = R(2.0 * LWA * d.phi_top);
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (m >= a.nsw) break;
+            R A1[SW_NPT], A2[SW_NPT], A3[SW_NPT], A4[SW_NPT], PH[SW_NPT];
+#pragma unroll
+            for (int k = 0; k < SW_NPT; k++) {
+                R ph = (L1[k] + L2[k] + L3[k] + L4[k]) * inv;
+                PH[k] = ph;
+                R e = lw * ph;
+                A1[k] = L1[k] - OM[k] * (L1[k] - e);
+                A2[k] = L2[k] - OM[k] * (L2[k] - e);
+                A3[k] = L3[k] - OM[k] * (L3[k] - e);
+                A4[k] = L4[k] - OM[k] * (L4[k] - e);
+            }
+            int par = m & 1;
+            bup[par][w][lane] = A2[SW_NPT - 1];
+            bdn[par][w][lane] = A4[0];
+            __syncthreads();
+            R below = w > 0 ? bup[par][w - 1][lane] : R(0);
+            R above = w < 3 ? bdn[par][w + 1][lane] : R(0);
+#pragma unroll
+            for (int k = 0; k < SW_NPT; k++) {
+                int gj = y0 + k;
+                R n1 = __shfl_up(A1[k], 1, 64);
+                R n3 = __shfl_down(A3[k], 1, 64);
+                R n2 = k > 0 ? A2[k - 1] : below;
+                R n4 = k < SW_NPT - 1 ? A4[k + 1] : above;
+                if constexpr (based) {
+                    n1 = n1 + D1[k];
+                    n3 = n3 + D3[k];
+                    n2 = gj == 0 ? D2[k] - A4[k] : n2 + D2[k];
+                    n4 = gj == d.ny - 1 ? D4[k] - A2[k] : n4 + D4[k];
+                } else {
+                    if (gj == 0) n2 = wbot0 - A4[k];
+                    if (gj == d.ny - 1) n4 = wtop0 - A2[k];
+                }
+                L1[k] = n1;
+                L2[k] = n2;
+                L3[k] = n3;
+                L4[k] = n4;
+                int r = w * SW_NPT + k;
+                if (ownx && r >= M && r < M + OY && gj >= 0 && gj < d.ny) {
+                    R ph = (n1 + n2 + n3 + n4) * inv;
+                    double dd = (double)(ph - PH[k]);
+                    double pr = based ? (double)ph + (double)PB[k] : (double)ph;
+                    accd[m] += dd * dd;
+                    accp[m] += pr * pr;
+                }
+            }
+        }
+        R* ld = s.l[a.dst];
+        R* pd = s.phi[a.dst];
+#pragma unroll
+        for (int k = 0; k < SW_NPT; k++) {
+            int gj = y0 + k;
+            int r = w * SW_NPT + k;
+            if (ownx && r >= M && r < M + OY && gj >= 0 && gj < d.ny) {
+                int64_t n = at(d, gi, gj);
+                ld[n] = L1[k];
+                ld[P + n] = L2[k];
+                ld[2 * P + n] = L3[k];
+                ld[3 * P + n] = L4[k];
+                pd[n] = based ? PB[k] + (L1[k] + L2[k] + L3[k] + L4[k]) * inv
+                              : (L1[k] + L2[k] + L3[k] + L4[k]) * inv;
+            }
+        }
+        double* pw = s.partials + part_sweep(d.gx * d.gy, nbt, a.slot);
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (m >= a.nsw) break;
+            double bd = block_sum(accd[m], sh);
+            double bp = block_sum(accp[m], sh);
+            if (threadIdx.x == 0) {
+                pw[((int64_t)m * nbt + tile) * 2] = bd;
+                pw[((int64_t)m * nbt + tile) * 2 + 1] = bp;
+            }
+        }
     }
-    double bd = block_sum(d2, sh);
-    double bp = block_sum(p2, sh);
-    int nb = d.gx * d.gy;
-    if (threadIdx.x == 0) {
-        double* pw = s.partials + part_sweep(nb, k & 1);
-        pw[2 * blockIdx.x] = bd;
-        pw[2 * blockIdx.x + 1] = bp;
+    if (tile == 0 && a.prev_nsw > 0) {
+        __syncthreads();
+        sweep_test<M, R>(d, s, a, sh);
     }
-    if (blockIdx.x == 0 && k >= 2) sweep_check(d, s, k - 1, sh);
+}
+
+template <int M, typename R>
+__global__ void __launch_bounds__(NT) k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
+    b_sweep_tb<M, R>(d, s, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// FP32 form: renormalise every link pair (b, l) by Knuth's two-sum, b' = fl(b + l) and
+// l' = (b + l) - b' exactly, so the represented links do not change and the remainders
+// the sweeps work on restart near zero.
+template <typename R>
+__device__ __forceinline__ void b_rebase(const Dev& d, const State<R>& s, int lcur, int tile) {
+#pragma clang fp contract(off)
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    int64_t n = at(d, i, j);
+    const int64_t P = d.plane;
+    R* l = s.l[lcur];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        R b = s.lb[q * P + n], r = l[q * P + n];
+        R hi = b + r;
+        R bv = hi - b;
+        R lo = (b - (hi - bv)) + (r - bv);
+        s.lb[q * P + n] = hi;
+        l[q * P + n] = lo;
+    }
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_rebase(Dev d, State<R> s, int lcur) {
+    b_rebase<R>(d, s, lcur, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// One block: the convergence test of the last launch of a batch (same rule as above).
+template <int M, typename R>
+__global__ void __launch_bounds__(NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a) {
+    __shared__ double sh[NT / 64];
+    if (s.ctl->done) return;
+    sweep_test<M, R>(d, s, a, sh);
 }
 
 __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) {
+    c->fix_launch = 0;
+    c->fix_n = 0;
     c->done = 0;
     c->count = 0;
     c->conv = 0;
@@ -461,199 +719,232 @@ __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) 
 // ---------------------------------------------------------------------------
 // Stage 3a: surface tension (Eqs. (3)-(5)) and electric force (Eq. (14)) with
 // psi^{n+1}; S = rho mdot + u . grad(rho) (Eq. (24)).
-__global__ void __launch_bounds__(NT) k_h_prep1(Dev d, State s, int sp, int lcur) {
+template <typename R>
+__device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    const double* psi = s.psi[sp ^ 1];
-    const double* fs = s.fs[sp];
-    const double* phi = s.phi[lcur];
-    double vp[3][3], vf[3][3], vph[3][3], ve[3][3], vr[3][3];
-    load3<GWET>(psi, d, i, j, vp);
-    load3<GMIRROR>(fs, d, i, j, vf);
-    load3<GPHI>(phi, d, i, j, vph);
+    const R* psi = s.psi[sp ^ 1];
+    const R* fs = s.fs[sp];
+    const R* phi = s.phi[lcur];
+    R vp[3][3], vf[3][3], vph[3][3], ve[3][3], vr[3][3];
+    load3<GWET, R>(psi, d, i, j, vp);
+    load3<GMIRROR, R>(fs, d, i, j, vf);
+    load3<GPHI, R>(phi, d, i, j, vph);
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
         for (int b = 0; b < 3; b++) {
-            ve[a][b] = mix(d.eps_s, d.eps_l, d.eps_g, vp[a][b], vf[a][b]);
-            vr[a][b] = mix(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
+            ve[a][b] = mix<R>(d.eps_s, d.eps_l, d.eps_g, vp[a][b], vf[a][b]);
+            vr[a][b] = mix<R>(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
         }
-    double gx, gy, lap;
-    grad_lap(vp, gx, gy, lap);
-    double ps = vp[1][1];
-    double mu = 4.0 * d.beta * ps * (ps - 1.0) * (ps - 0.5) - d.kappa * lap;
-    double Fx = mu * gx, Fy = mu * gy;
-    double gpx, gpy, lphi, gex, gey, dum;
-    grad_lap(vph, gpx, gpy, lphi);
-    grad_lap(ve, gex, gey, dum);
-    double eps = ve[1][1];
-    double Ex = -gpx, Ey = -gpy;
-    double qv = -(gex * gpx + gey * gpy + eps * lphi);
-    double E2 = Ex * Ex + Ey * Ey;
-    Fx += qv * Ex - 0.5 * E2 * gex;
-    Fy += qv * Ey - 0.5 * E2 * gey;
+    R gx, gy, lap;
+    grad_lap<R>(vp, gx, gy, lap);
+    R ps = vp[1][1];
+    R mu = R(4) * R(d.beta) * ps * (ps - R(1)) * (ps - R(0.5)) - R(d.kappa) * lap;
+    R Fx = mu * gx, Fy = mu * gy;
+    R gpx, gpy, lphi, gex, gey, dum;
+    grad_lap<R>(vph, gpx, gpy, lphi);
+    grad_lap<R>(ve, gex, gey, dum);
+    R eps = ve[1][1];
+    R Ex = -gpx, Ey = -gpy;
+    R qv = -(gex * gpx + gey * gpy + eps * lphi);
+    R E2 = Ex * Ex + Ey * Ey;
+    Fx += qv * Ex - R(0.5) * E2 * gex;
+    Fy += qv * Ey - R(0.5) * E2 * gey;
     s.Fx[n] = Fx;
     s.Fy[n] = Fy;
-    double grx, gry;
-    grad_lap(vr, grx, gry, dum);
+    R grx, gry;
+    grad_lap<R>(vr, grx, gry, dum);
     s.S[n] = vr[1][1] * s.md[sp][n] + s.ux[sp][n] * grx + s.uy[sp][n] * gry;
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_h_prep1(Dev d, State<R> s, int sp, int lcur) {
+    b_h_prep1<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Stage 3b: collision inputs of h: rho, F~, F + rho f_solid, 1/tau_h.
-__global__ void __launch_bounds__(NT) k_h_prep2(Dev d, State s, int sp) {
+template <typename R>
+__device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int sp, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    const double* psi = s.psi[sp ^ 1];
-    const double* fs = s.fs[sp];
-    double vp[3][3], vf[3][3], vr[3][3], vpr[3][3];
-    load3<GWET>(psi, d, i, j, vp);
-    load3<GMIRROR>(fs, d, i, j, vf);
+    const R* psi = s.psi[sp ^ 1];
+    const R* fs = s.fs[sp];
+    R vp[3][3], vf[3][3], vr[3][3], vpr[3][3];
+    load3<GWET, R>(psi, d, i, j, vp);
+    load3<GMIRROR, R>(fs, d, i, j, vf);
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int b = 0; b < 3; b++) vr[a][b] = mix(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
-    load3<GMIRROR>(s.p[sp], d, i, j, vpr);
-    double grx, gry, gpx, gpy, gsx = 0.0, gsy = 0.0, dum;
-    grad_lap(vr, grx, gry, dum);
-    grad_lap(vpr, gpx, gpy, dum);
+        for (int b = 0; b < 3; b++) vr[a][b] = mix<R>(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
+    load3<GMIRROR, R>(s.p[sp], d, i, j, vpr);
+    R grx, gry, gpx, gpy, gsx = R(0), gsy = R(0), dum;
+    grad_lap<R>(vr, grx, gry, dum);
+    grad_lap<R>(vpr, gpx, gpy, dum);
     if (d.readings & 1u) {
-        double vs[3][3];
-        load3<GMIRROR>(s.S, d, i, j, vs);
-        grad_lap(vs, gsx, gsy, dum);
+        R vs[3][3];
+        load3<GMIRROR, R>(s.S, d, i, j, vs);
+        grad_lap<R>(vs, gsx, gsy, dum);
     }
-    double rho = vr[1][1];
-    double fsn = vf[1][1];
-    double Fx = s.Fx[n], Fy = s.Fy[n];
+    R rho = vr[1][1];
+    R fsn = vf[1][1];
+    R Fx = s.Fx[n], Fy = s.Fy[n];
     s.rho[n] = rho;
-    s.Ftx[n] = Fx - gpx + CS2 * grx + CS2 * gsx;
-    s.Fty[n] = Fy - gpy + CS2 * gry + CS2 * gsy;
-    s.Gx[n] = Fx + rho * (fsn * (0.0 - s.usx[n]));
-    s.Gy[n] = Fy + rho * (fsn * (0.0 - s.usy[n]));
-    double mu = mix(d.mu_s, d.mu_l, d.mu_g, vp[1][1], fsn);
-    s.omh[n] = 1.0 / (mu / (rho * CS2) + 0.5);
+    s.Ftx[n] = Fx - gpx + R(CS2) * grx + R(CS2) * gsx;
+    s.Fty[n] = Fy - gpy + R(CS2) * gry + R(CS2) * gsy;
+    s.Gx[n] = Fx + rho * (fsn * (R(0) - s.usx[n]));
+    s.Gy[n] = Fy + rho * (fsn * (R(0) - s.usy[n]));
+    R mu = mix<R>(d.mu_s, d.mu_l, d.mu_g, vp[1][1], fsn);
+    s.omh[n] = R(1) / (mu / (rho * R(CS2)) + R(0.5));
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_h_prep2(Dev d, State<R> s, int sp) {
+    b_h_prep2<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-__device__ __forceinline__ HIn h_inputs(const State& s, int sp, int64_t m) {
-    return HIn{s.p[sp][m], s.rho[m], s.ux[sp][m], s.uy[sp][m], s.S[m],
-               s.Ftx[m], s.Fty[m], s.Gx[m], s.Gy[m], s.omh[m]};
+template <typename R>
+__device__ __forceinline__ HIn<R> h_inputs(const State<R>& s, int sp, int64_t m) {
+    return HIn<R>{s.p[sp][m], s.rho[m], s.ux[sp][m], s.uy[sp][m], s.S[m],
+                  s.Ftx[m], s.Fty[m], s.Gx[m], s.Gy[m], s.omh[m]};
 }
 
 // Stage 3c: h pulled and collided at its source, bounce-back at the walls;
 // u* (Eq. (25)), u (Eq. (26) with u_s = 0), p (Eq. (27)).
-__global__ void __launch_bounds__(NT) k_h_stream(Dev d, State s, int sp) {
+template <typename R>
+__device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int sp, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    const double* hsrc = s.h[sp];
-    double* hdst = s.h[sp ^ 1];
-    HIn self = h_inputs(s, sp, n);
-    double sx = 0.0, sy = 0.0, s0 = 0.0;
+    const R* hsrc = s.h[sp];
+    R* hdst = s.h[sp ^ 1];
+    HIn<R> self = h_inputs<R>(s, sp, n);
+    R sx = R(0), sy = R(0), s0 = R(0);
 #pragma unroll
     for (int q = 0; q < 9; q++) {
         int jj = j - QY[q];
-        double val;
+        R val;
         if (jj < 0 || jj >= d.ny) {
             int o = QOPP[q];
-            val = coll_h(o, hsrc[o * d.plane + n], self);
+            val = coll_h<R>(o, hsrc[o * d.plane + n], self);
         } else {
             int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            val = coll_h(q, hsrc[q * d.plane + m], h_inputs(s, sp, m));
+            val = coll_h<R>(q, hsrc[q * d.plane + m], h_inputs<R>(s, sp, m));
         }
         hdst[q * d.plane + n] = val;
-        sx += QX[q] * val;
-        sy += QY[q] * val;
+        sx += R(QX[q]) * val;
+        sy += R(QY[q]) * val;
         if (q) s0 += val;
     }
-    double rho = self.rho;
-    double fsn = s.fs[sp][n];
-    double ax = (sx + 0.5 * s.Fx[n]) / rho;
-    double ay = (sy + 0.5 * s.Fy[n]) / rho;
+    R rho = self.rho;
+    R fsn = s.fs[sp][n];
+    R ax = (sx + R(0.5) * s.Fx[n]) / rho;
+    R ay = (sy + R(0.5) * s.Fy[n]) / rho;
     s.usx[n] = ax;
     s.usy[n] = ay;
-    double ux = ax + 0.5 * fsn * (0.0 - ax);
-    double uy = ay + 0.5 * fsn * (0.0 - ay);
+    R ux = ax + R(0.5) * fsn * (R(0) - ax);
+    R uy = ay + R(0.5) * fsn * (R(0) - ay);
     s.ux[sp ^ 1][n] = ux;
     s.uy[sp ^ 1][n] = uy;
-    double uF = self.ux * self.Ftx + self.uy * self.Fty;
-    double R0 = W0 * (self.S - 3.0 * uF);
-    double uu = ux * ux + uy * uy;
-    double s0u = W0 * (-1.5 * uu);
-    s.p[sp ^ 1][n] = CS2 / (1.0 - W0) * (s0 + 0.5 * self.S + (1.0 / self.om) * R0 + rho * s0u);
+    R uF = self.ux * self.Ftx + self.uy * self.Fty;
+    R R0 = R(W0) * (self.S - R(3) * uF);
+    R uu = ux * ux + uy * uy;
+    R s0u = R(W0) * (R(-1.5) * uu);
+    s.p[sp ^ 1][n] = R(CS2 / (1.0 - W0)) * (s0 + R(0.5) * self.S + (R(1) / self.om) * R0 + rho * s0u);
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_h_stream(Dev d, State<R> s, int sp) {
+    b_h_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-__device__ __forceinline__ GIn g_inputs(const Dev& d, const State& s, int sp, int64_t m) {
-    double ps = s.psi[sp ^ 1][m];
-    double fsn = s.fs[sp][m];
-    double C = mix(d.C_s, d.C_l, d.C_g, ps, fsn);
-    double k = mix(d.k_s, d.k_l, d.k_g, ps, fsn);
-    double T = s.T[sp][m];
-    return GIn{s.H[sp][m], T, C, s.ux[sp ^ 1][m], s.uy[sp ^ 1][m],
-               1.0 / (k / (d.Cref * CS2) + 0.5), C * T * s.md[sp][m]};
+template <typename R>
+__device__ __forceinline__ GIn<R> g_inputs(const Dev& d, const State<R>& s, int sp, int64_t m) {
+    R ps = s.psi[sp ^ 1][m];
+    R fsn = s.fs[sp][m];
+    R C = mix<R>(d.C_s, d.C_l, d.C_g, ps, fsn);
+    R k = mix<R>(d.k_s, d.k_l, d.k_g, ps, fsn);
+    R T = s.T[sp][m];
+    return GIn<R>{s.H[sp][m], T, C, s.ux[sp ^ 1][m], s.uy[sp ^ 1][m],
+                  R(1) / (k / (R(d.Cref) * R(CS2)) + R(0.5)), C * T * s.md[sp][m]};
 }
 
 // Stage 4: g pulled and collided at its source; substrate anti-bounce-back at T_w,
 // adiabatic top; H^{n+1} = sum g + Q/2 (Eq. (30)); Eq. (7) gives T, f_l; new f_s
-// and mdot.  The FP64 liquid volume feeds the on-device freezing-time detector.
-__global__ void __launch_bounds__(NT) k_g_stream(Dev d, State s, int sp) {
+// and mdot.  Per-block FP64 liquid volume for the freezing-time detector.
+template <typename R>
+__device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int sp, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     double vl = 0.0;
     if (i < d.nx && j < d.ny) {
         int64_t n = at(d, i, j);
-        const double* gsrc = s.g[sp];
-        double* gdst = s.g[sp ^ 1];
-        GIn self = g_inputs(d, s, sp, n);
-        double sum = 0.0;
+        const R* gsrc = s.g[sp];
+        R* gdst = s.g[sp ^ 1];
+        const R Cref = R(d.Cref);
+        GIn<R> self = g_inputs<R>(d, s, sp, n);
+        R sum = R(0), g0 = R(0);
 #pragma unroll
         for (int q = 0; q < 9; q++) {
             int jj = j - QY[q];
             int o = QOPP[q];
-            double val;
+            R val;
             if (jj < 0) {
-                val = -coll_g(o, gsrc[o * d.plane + n], self, d.Cref) + 2.0 * QW[q] * d.Cref * d.T_w;
+                val = -coll_g<R>(o, gsrc[o * d.plane + n], self, Cref) + R(2.0 * QW[q] * d.Cref * d.T_w);
             } else if (jj >= d.ny) {
-                val = coll_g(o, gsrc[o * d.plane + n], self, d.Cref);
+                val = coll_g<R>(o, gsrc[o * d.plane + n], self, Cref);
             } else {
                 int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-                val = coll_g(q, gsrc[q * d.plane + m], g_inputs(d, s, sp, m), d.Cref);
+                val = coll_g<R>(q, gsrc[q * d.plane + m], g_inputs<R>(d, s, sp, m), Cref);
             }
+            if (q == 0) g0 = val;
             gdst[q * d.plane + n] = val;
             sum += val;
         }
-        double Hn = sum + 0.5 * self.Q;
-        double ps = s.psi[sp ^ 1][n];
-        double T, fl;
-        invert(d, Hn, ps, T, fl);
-        double fsn = clamp01(ps) * (1.0 - fl);
+        R Hn = sum + R(0.5) * self.Q;
+        R ps = s.psi[sp ^ 1][n];
+        constexpr bool based = std::is_same<R, float>::value;
+        R hb = based ? s.hb[n] : R(0);
+        R T, fl;
+        invert<R>(d, Hn, hb, ps, T, fl);
+        if (based) {
+            // move the base to the new psi: rest link and H re-expressed exactly
+            R hn = clamp01(ps) * R(d.Lvol);
+            R shift = hb - hn;
+            gdst[n] = g0 + shift;
+            Hn = Hn + shift;
+            s.hb[n] = hn;
+        }
+        R fsn = clamp01(ps) * (R(1) - fl);
         s.H[sp ^ 1][n] = Hn;
         s.T[sp ^ 1][n] = T;
         s.fl[n] = fl;
-        s.md[sp ^ 1][n] = d.shrink * (fsn - s.fs[sp][n]);
+        s.md[sp ^ 1][n] = R(d.shrink) * (fsn - s.fs[sp][n]);
         s.fs[sp ^ 1][n] = fsn;
-        vl = clamp01(ps) * fl;
+        vl = (double)(clamp01(ps) * fl);
     }
     __shared__ double sh[NT / 64];
     double bv = block_sum(vl, sh);
-    if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + blockIdx.x] = bv;
+    if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + tile] = bv;
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_g_stream(Dev d, State<R> s, int sp) {
+    b_g_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // One block: liquid volume of the new state (block partials in order).  mode 1 records
 // V_l0 after initialisation; mode 0 advances the step counter and runs the freezing-time
 // detector: t_fre is the first step with V_l <= 1% of V_l0, interpolated linearly.
-__global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, State s, int mode) {
+__global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, const double* partials, Ctl* c, int mode) {
     __shared__ double sh[NT / 64];
     int nb = d.gx * d.gy;
-    const double* pv = s.partials + part_vl(nb);
+    const double* pv = partials + part_vl(nb);
     double a = 0.0;
     for (int k = threadIdx.x; k < nb; k += NT) a += pv[k];
     a = block_sum(a, sh);
     if (threadIdx.x != 0) return;
-    Ctl* c = s.ctl;
     if (mode == 1) {
         c->V_l0 = a;
         c->V_prev = a;
@@ -672,26 +963,32 @@ __global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, State s, int mode) {
 }
 
 // Per-block liquid volume of the initial state (finalized by k_vl_finalize, mode 1).
-__global__ void __launch_bounds__(NT) k_vl0(Dev d, State s) {
+template <typename R>
+__device__ __forceinline__ void b_vl0(const Dev& d, const State<R>& s, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     double vl = 0.0;
     if (i < d.nx && j < d.ny) {
         int64_t n = at(d, i, j);
-        vl = clamp01(s.psi[0][n]) * s.fl[n];
+        vl = (double)(clamp01(s.psi[0][n]) * s.fl[n]);
     }
     __shared__ double sh[NT / 64];
     double bv = block_sum(vl, sh);
-    if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + blockIdx.x] = bv;
+    if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + tile] = bv;
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_vl0(Dev d, State<R> s) {
+    b_vl0<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
 // Diagnostics: per-block FP64 sums, max |u| and a non-finite count; k_diag_finalize
 // adds them in block order and scans the centre column for the droplet height
 // (psi = 1/2) and the freezing front (f_l = 1/2).
-__global__ void __launch_bounds__(NT) k_diag(Dev d, State s, int sp, int lcur) {
+template <typename R>
+__device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     int i, j;
-    node_of(d, i, j);
+    node_of(d, tile, i, j);
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (i < d.nx && j < d.ny) {
         int64_t n = at(d, i, j);
@@ -701,15 +998,15 @@ __global__ void __launch_bounds__(NT) k_diag(Dev d, State s, int sp, int lcur) {
         v[0] = ps;
         double sf = 0.0, sg = 0.0;
         for (int q = 0; q < 9; q++) {
-            sf += s.f[sp][q * d.plane + n];
-            sg += s.g[sp][q * d.plane + n];
+            sf += (double)s.f[sp][q * d.plane + n];
+            sg += (double)s.g[sp][q * d.plane + n];
         }
         v[1] = sf;
-        v[2] = sg;
-        v[3] = clamp01(ps) * fl;
+        v[2] = std::is_same<R, float>::value ? sg + (double)s.hb[n] : sg;
+        v[3] = (double)clamp01(s.psi[sp][n]) * fl;
         v[4] = s.fs[sp][n];
         v[5] = sqrt(ux * ux + uy * uy);
-        double chk = ps + ux + uy + s.p[sp][n] + s.T[sp][n] + s.phi[lcur][n];
+        double chk = ps + ux + uy + (double)s.p[sp][n] + (double)s.T[sp][n] + (double)s.phi[lcur][n];
         v[6] = isfinite(chk) ? 0.0 : 1.0;
     }
     __shared__ double sh[NT / 64];
@@ -718,12 +1015,17 @@ __global__ void __launch_bounds__(NT) k_diag(Dev d, State s, int sp, int lcur) {
     r[5] = block_max(v[5], sh);
     r[6] = block_sum(v[6], sh);
     if (threadIdx.x == 0) {
-        double* pw = s.partials + part_diag(d.gx * d.gy) + 7 * (int64_t)blockIdx.x;
+        double* pw = s.partials + part_diag(d.gx * d.gy) + 7 * (int64_t)tile;
         for (int k = 0; k < 7; k++) pw[k] = r[k];
     }
 }
+template <typename R>
+__global__ void __launch_bounds__(NT) k_diag(Dev d, State<R> s, int sp, int lcur) {
+    b_diag<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
+}
 
-__global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State s, int sp) {
+template <typename R>
+__global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State<R> s, int sp) {
     __shared__ double sh[NT / 64];
     int nb = d.gx * d.gy;
     const double* pv = s.partials + part_diag(nb);
@@ -741,7 +1043,7 @@ __global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State s, int sp) {
     Ctl* c = s.ctl;
     for (int m = 0; m < 6; m++) c->dsum[m] = out[m];
     c->nonfinite = out[6] > 0.0;
-    const double* psi = s.psi[sp];
+    const R* psi = s.psi[sp];
     int ic = d.nx / 2;
     double height = 0.0;
     for (int jj = d.ny - 1; jj >= 0; jj--) {
@@ -757,9 +1059,9 @@ __global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State s, int sp) {
         }
     }
     double front = 0.0;
-    if (psi[at(d, ic, 0)] >= 0.5) {
+    if (psi[at(d, ic, 0)] >= R(0.5)) {
         front = height;
-        for (int jj = 0; jj < d.ny && psi[at(d, ic, jj)] >= 0.5; jj++) {
+        for (int jj = 0; jj < d.ny && psi[at(d, ic, jj)] >= R(0.5); jj++) {
             double a0 = s.fl[at(d, ic, jj)];
             if (a0 >= 0.5) {
                 if (jj == 0) {
@@ -776,22 +1078,165 @@ __global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State s, int sp) {
     c->front = front;
 }
 
-// Pitched plane <-> dense FP64 array copies for get/set (device side).
-__global__ void k_pack(Dev d, const double* __restrict__ src, double* __restrict__ dst, int planes) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t per = (int64_t)d.nx * d.ny;
-    if (k >= per * planes) return;
-    int64_t q = k / per, r = k % per;
-    int j = (int)(r / d.nx), i = (int)(r % d.nx);
-    dst[k] = src[q * d.plane + at(d, i, j)];
+// ---------------------------------------------------------------------------
+// Batched form: many cases of different grid sizes advanced together.  Each case keeps
+// its own constants, state and control block; a table in device memory lists them with
+// the first block of each case in the node grid and in the blocked-sweep grid.  One
+// launch per stage covers every case: block b (XCD-ordered) finds its case by binary
+// search and runs the same body as the single-case kernel on that case's tile b - first.
+
+template <typename R>
+struct BatchCase {
+    Dev d;
+    State<R> s;
+};
+
+__device__ __forceinline__ int find_case(const int* __restrict__ first, int ncases, int b) {
+    int lo = 0, hi = ncases - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
-__global__ void k_unpack(Dev d, const double* __restrict__ src, double* __restrict__ dst, int planes) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t per = (int64_t)d.nx * d.ny;
-    if (k >= per * planes) return;
-    int64_t q = k / per, r = k % per;
-    int j = (int)(r / d.nx), i = (int)(r % d.nx);
-    dst[q * d.plane + at(d, i, j)] = src[k];
+
+#define LBM_BATCHED(name, body, ...)                                                        \
+    template <typename R>                                                                   \
+    __global__ void __launch_bounds__(NT) name(const BatchCase<R>* __restrict__ cases,      \
+                                               const int* __restrict__ first, int ncases,  \
+                                               int sp, const int* __restrict__ lcur) {     \
+        int b = xcd_tile(blockIdx.x, gridDim.x);                                            \
+        int c = find_case(first, ncases, b);                                                \
+        const BatchCase<R>& bc = cases[c];                                                  \
+        body<R>(bc.d, bc.s, ##__VA_ARGS__, b - first[c]);                                   \
+    }
+
+LBM_BATCHED(kb_init, b_init)
+LBM_BATCHED(kb_oml, b_oml, sp)
+LBM_BATCHED(kb_f_prep, b_f_prep, sp)
+LBM_BATCHED(kb_f_stream, b_f_stream, sp)
+LBM_BATCHED(kb_rebase, b_rebase, lcur[c])
+LBM_BATCHED(kb_h_prep1, b_h_prep1, sp, lcur[c])
+LBM_BATCHED(kb_h_prep2, b_h_prep2, sp)
+LBM_BATCHED(kb_h_stream, b_h_stream, sp)
+LBM_BATCHED(kb_g_stream, b_g_stream, sp)
+LBM_BATCHED(kb_vl0, b_vl0)
+#undef LBM_BATCHED
+
+// FP32 rebase of the cases whose potential loop is still running after launch t - 1 (their
+// state is in buffer (lcur0 + t) mod 3).
+template <typename R>
+__global__ void __launch_bounds__(NT) kb_rebase_running(const BatchCase<R>* __restrict__ cases,
+                                                        const int* __restrict__ first, int ncases,
+                                                        const int* __restrict__ lcur0, int t) {
+    int b = xcd_tile(blockIdx.x, gridDim.x);
+    int c = find_case(first, ncases, b);
+    const BatchCase<R>& bc = cases[c];
+    if (bc.s.ctl->done) return;
+    b_rebase<R>(bc.d, bc.s, (lcur0[c] + t) % 3, b - first[c]);
+}
+
+// Launch t of a lockstep potential loop for one case: sweeps t*M+1 .. of that case, from
+// the buffer the case's solve started in; the previous launch is the one to test.
+template <int M>
+__device__ __forceinline__ SweepLaunch lockstep_launch(const Ctl* c, int lcur0, int t) {
+    SweepLaunch a{};
+    a.k0 = t * M + 1;
+    a.nsw = min(M, c->max_sweeps + 1 - a.k0);
+    if (a.nsw < 0) a.nsw = 0;
+    a.src = (lcur0 + t) % 3;
+    a.dst = (a.src + 1) % 3;
+    a.slot = t & 1;
+    a.launch = t;
+    if (t > 0) {
+        a.prev_k0 = (t - 1) * M + 1;
+        a.prev_nsw = min(M, c->max_sweeps + 1 - a.prev_k0);
+        a.prev_slot = (t - 1) & 1;
+    }
+    return a;
+}
+
+template <int M, typename R>
+__global__ void __launch_bounds__(NT) kb_sweep(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
+                                               int ncases, const int* __restrict__ lcur0, int t) {
+    int b = xcd_tile(blockIdx.x, gridDim.x);
+    int c = find_case(first, ncases, b);
+    const BatchCase<R>& bc = cases[c];
+    SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t);
+    if (a.nsw == 0) return;
+    b_sweep_tb<M, R>(bc.d, bc.s, a, b - first[c]);
+}
+
+// Recomputation of each finished case's last launch up to its final sweep (fix[c].nsw = 0:
+// nothing to redo for that case).
+template <int M, typename R>
+__global__ void __launch_bounds__(NT) kb_sweep_fix(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
+                                                   int ncases, const SweepLaunch* __restrict__ fix) {
+    int b = xcd_tile(blockIdx.x, gridDim.x);
+    int c = find_case(first, ncases, b);
+    SweepLaunch a = fix[c];
+    if (a.nsw == 0) return;
+    const BatchCase<R>& bc = cases[c];
+    b_sweep_tb<M, R>(bc.d, bc.s, a, b - first[c]);
+}
+
+// One block per case: test the case's launch t (the last of a batch).
+template <int M, typename R>
+__global__ void __launch_bounds__(NT) kb_sweep_test(const BatchCase<R>* __restrict__ cases, const int* __restrict__ lcur0,
+                                                    int t) {
+    __shared__ double sh[NT / 64];
+    const BatchCase<R>& bc = cases[blockIdx.x];
+    if (bc.s.ctl->done) return;
+    SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x], t + 1);
+    if (a.prev_nsw <= 0) return;
+    sweep_test<M, R>(bc.d, bc.s, a, sh);
+}
+
+template <typename R>
+__global__ void kb_ctl_reset(const BatchCase<R>* __restrict__ cases, int ncases, const double* tol, int min_sweeps,
+                             const int* max_sweeps) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncases) return;
+    Ctl* ct = cases[c].s.ctl;
+    ct->fix_launch = 0;
+    ct->fix_n = 0;
+    ct->done = 0;
+    ct->count = 0;
+    ct->conv = 0;
+    ct->resid = 0.0;
+    ct->tol = tol[c];
+    ct->min_sweeps = min_sweeps;
+    ct->max_sweeps = max_sweeps[c];
+}
+
+// One block per case: the liquid volume of the case's new state (see k_vl_finalize).
+template <typename R>
+__global__ void __launch_bounds__(NT) kb_vl_finalize(const BatchCase<R>* __restrict__ cases, int mode) {
+    __shared__ double sh[NT / 64];
+    const BatchCase<R>& bc = cases[blockIdx.x];
+    const Dev& d = bc.d;
+    Ctl* c = bc.s.ctl;
+    int nb = d.gx * d.gy;
+    const double* pv = bc.s.partials + part_vl(nb);
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += NT) a += pv[k];
+    a = block_sum(a, sh);
+    if (threadIdx.x != 0) return;
+    if (mode == 1) {
+        c->V_l0 = a;
+        c->V_prev = a;
+        c->t_fre = -1.0;
+        c->step = 0;
+        return;
+    }
+    long long st = c->step + 1;
+    c->step = st;
+    double thr = 0.01 * c->V_l0;
+    if (c->t_fre < 0.0 && c->V_l0 > 0.0 && a <= thr) {
+        double dv = c->V_prev - a;
+        c->t_fre = (double)(st - 1) + (dv > 0.0 ? (c->V_prev - thr) / dv : 1.0);
+    }
+    c->V_prev = a;
 }
 
 }  // namespace lbm

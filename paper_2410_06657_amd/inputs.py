@@ -167,6 +167,30 @@ def cfg3_strip(ny: int = 4096, h0: float | None = None, Ste: float = 0.1,
     return stefan_strip(4, ny, h0 if h0 is not None else ny - 8, Ste, rho_ratio_sl)
 
 
+def cfg4(seed: int = 4, ncases: int = 96) -> list:
+    """The batched sweep: ncases sessile drops with N_y ~ U{128, 144, ..., 768}, N_x = 2 N_y,
+    R0 = 0.3125 N_y, Ca_E ~ U[0, 0.4], theta ~ U[45, 135] deg, R ~ logU[0.3, 5],
+    S ~ logU[0.5, 3], Ste = 0.1, FP32.  Case c uses uniforms 5c .. 5c+4 of SplitMix64(seed)
+    and seeds its centre jitter with 1000 seed + c."""
+    cases = []
+    s = seed & MASK64
+    draws = []
+    for _ in range(5 * ncases):
+        s, out = splitmix64(s)
+        draws.append((out >> 11) * (1.0 / (1 << 53)))
+    for c in range(ncases):
+        u = draws[5 * c:5 * c + 5]
+        ny = 128 + 16 * min(int(u[0] * 41), 40)
+        nx = 2 * ny
+        Ca = 0.4 * u[1]
+        theta = 45.0 + 90.0 * u[2]
+        R = math.exp(math.log(0.3) + u[3] * (math.log(5.0) - math.log(0.3)))
+        S = math.exp(math.log(0.5) + u[4] * (math.log(3.0) - math.log(0.5)))
+        case = sessile_drop(nx, ny, 0.3125 * ny, theta, R, S, Ca, 0.1, seed=1000 * seed + c)
+        cases.append(case)
+    return cases
+
+
 def scaled(case: dict, nx: int, ny: int) -> dict:
     """The same droplet problem on another grid: lengths scale with ny."""
     f = ny / case["ny"]

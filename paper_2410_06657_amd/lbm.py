@@ -18,12 +18,14 @@ LBM_OK, LBM_EINVAL, LBM_ENOCONV, LBM_ENONFINITE, LBM_EHIP, LBM_ESTATE, LBM_ESPAC
 FIELDS = ["psi", "ux", "uy", "usx", "usy", "p", "T", "H", "fs", "mdot",
           "psiu_x", "psiu_y", "phi", "fl"]
 POPS = {"f": (0, 9), "h": (1, 9), "g": (2, 9), "l": (3, 4)}
-PRECISIONS = {"fp64": 0}
+PRECISIONS = {"fp64": 0, "fp32": 1}
 
 # every exported symbol of include/lbm.h
 SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_diagnostics", "lbm_get_field", "lbm_set_field", "lbm_get_pop", "lbm_set_pop",
-           "lbm_sweep_log", "lbm_time_sweeps", "lbm_destroy", "lbm_strerror", "lbm_last_error"]
+           "lbm_sweep_log", "lbm_time_sweeps", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+           "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_diagnostics",
+           "lbm_batch_get_field", "lbm_batch_sweep_log", "lbm_batch_destroy"]
 
 
 class LbmParams(C.Structure):
@@ -44,7 +46,11 @@ class LbmParams(C.Structure):
         ("R0", C.c_double), ("xc", C.c_double), ("yc", C.c_double), ("h0", C.c_double),
         ("poisson_tol", C.c_double), ("poisson_max_sweeps", C.c_int),
         ("readings", C.c_uint),
+        ("sweep_block", C.c_int),
     ]
+
+
+LAUNCH_DEFAULTS = {"sweep_block": 0}
 
 
 class LbmDiag(C.Structure):
@@ -95,6 +101,13 @@ def lib():
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = C.c_char_p
+        L.lbm_batch_workspace_bytes.argtypes = [C.c_int, C.POINTER(LbmParams), C.POINTER(C.c_size_t)]
+        L.lbm_batch_init.argtypes = [C.c_int, C.POINTER(LbmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_batch_step.argtypes = [vp, C.c_int]
+        L.lbm_batch_diagnostics.argtypes = [vp, C.POINTER(LbmDiag)]
+        L.lbm_batch_get_field.argtypes = [vp, C.c_int, C.c_int, dp]
+        L.lbm_batch_sweep_log.argtypes = [vp, C.c_int, ip, C.c_int, ip]
+        L.lbm_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -105,9 +118,9 @@ def make_params(case: dict, precision: str = "fp64") -> LbmParams:
         if name == "precision":
             p.precision = PRECISIONS[precision]
             continue
-        if name not in case:
+        if name not in case and name not in LAUNCH_DEFAULTS:
             raise KeyError(f"case is missing '{name}'")
-        v = case[name]
+        v = case.get(name, LAUNCH_DEFAULTS.get(name))
         setattr(p, name, int(v) if ctype in (C.c_int, C.c_uint) else float(v))
     return p
 
@@ -213,4 +226,74 @@ class Solver:
         n = cnt.value
         buf = (C.c_int * max(n, 1))()
         lib().lbm_sweep_log(self._h, buf, n, C.byref(cnt))
+        return np.array(buf[:n], dtype=np.int64)
+
+
+class Batch:
+    """Many cases advanced together (one launch per stage for all of them).  The stream is a
+    dedicated torch stream (default priority) so that the fixed stages can be replayed
+    from HIP graphs."""
+
+    def __init__(self, cases: list, precision: str = "fp32", device: str = "cuda:0"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library has no CPU path")
+        self.cases = [dict(c) for c in cases]
+        self.n = len(cases)
+        arr = (LbmParams * self.n)(*[make_params(c, precision) for c in cases])
+        self._params = arr
+        nbytes = C.c_size_t()
+        rc = lib().lbm_batch_workspace_bytes(self.n, arr, C.byref(nbytes))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_workspace_bytes", rc)
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.Stream(self.device)
+        torch.cuda.synchronize(self.device)
+        h = C.c_void_p()
+        rc = lib().lbm_batch_init(self.n, arr, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_init", rc)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        rc = lib().lbm_batch_step(self._h, int(n))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_step", rc)
+
+    def diag(self) -> list:
+        arr = (LbmDiag * self.n)()
+        rc = lib().lbm_batch_diagnostics(self._h, arr)
+        if rc not in (LBM_OK, LBM_ENONFINITE):
+            raise LbmError("lbm_batch_diagnostics", rc)
+        return [{k: getattr(d, k) for k, _ in LbmDiag._fields_} for d in arr]
+
+    def field(self, c: int, name: str) -> np.ndarray:
+        case = self.cases[c]
+        out = np.empty((int(case["ny"]), int(case["nx"])), dtype=np.float64)
+        rc = lib().lbm_batch_get_field(self._h, int(c), FIELDS.index(name), _dp(out))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_get_field", rc)
+        return out
+
+    def sweep_log(self, c: int) -> np.ndarray:
+        cnt = C.c_int()
+        lib().lbm_batch_sweep_log(self._h, int(c), None, 0, C.byref(cnt))
+        n = cnt.value
+        buf = (C.c_int * max(n, 1))()
+        lib().lbm_batch_sweep_log(self._h, int(c), buf, n, C.byref(cnt))
         return np.array(buf[:n], dtype=np.int64)

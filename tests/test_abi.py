@@ -40,8 +40,11 @@ def test_workspace_size_and_validation(liblbm):
     from paper_2410_06657_amd import inputs
     c = inputs.cfg1(0)
     n = liblbm.workspace_bytes(c)
-    # 62 population planes + 35 field planes of 128 x 64 doubles, plus a small tail
-    assert 97 * 128 * 64 * 8 <= n < 98 * 128 * 64 * 8 + 65536
+    # 66 population planes + 36 field planes of 128 x 64 doubles, plus a small tail
+    assert 102 * 128 * 64 * 8 <= n < 102 * 128 * 64 * 8 + 65536
+    # FP32: the same planes in floats plus the bases (4 potential-link planes, 1 enthalpy)
+    n32 = liblbm.workspace_bytes(c, "fp32")
+    assert 107 * 128 * 64 * 4 <= n32 < 107 * 128 * 64 * 4 + 65536
     big = liblbm.workspace_bytes(inputs.cfg3())
     assert big > 6e9
     for bad in (dict(c, nx=1), dict(c, ny=2), dict(c, M=0.0), dict(c, sig_l=-1.0),
