@@ -124,6 +124,34 @@ def run_form(case, precision, steps, warmup, sweep_launches):
     }
 
 
+def counters_probe(case, launches=20):
+    """Short run for hardware-counter passes (rocprofv3 --pmc): a plain copy kernel of known
+    size (the calibration of the byte counters), then `launches` blocked sweep launches per
+    precision on the workload's grid.  The initial potential solve is capped at 16 sweeps so
+    the run stays short; a launch's memory traffic does not depend on convergence."""
+    import torch
+
+    from paper_2410_06657_amd.lbm import Solver
+
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[counters] copy kernel: 3 x {nbytes} bytes read and written", file=sys.stderr, flush=True)
+    del src, dst
+    c = dict(case, poisson_max_sweeps=16, poisson_tol=-1.0)
+    m = c.get("sweep_block") or 8
+    for precision in ("fp64", "fp32"):
+        s = Solver(c, precision=precision)
+        s.time_sweeps(launches * m)
+        torch.cuda.synchronize()
+        print(f"[counters] {precision}: {launches} launches of {m} sweeps on {c['nx']}x{c['ny']}",
+              file=sys.stderr, flush=True)
+        del s
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +164,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--sweep-block", type=int, default=0,
                     help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for rocprofv3 --pmc passes (copy calibration + sweep launches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
@@ -144,6 +174,9 @@ def main():
 
     case, desc = workload(args.workload)
     case["sweep_block"] = args.sweep_block
+    if args.counters:
+        counters_probe(case)
+        return
     n = case["nx"] * case["ny"]
     f64 = run_form(case, "fp64", args.steps, args.warmup, args.sweep_launches)
     line = {

@@ -89,6 +89,9 @@ typedef struct lbm_params {
     int sweep_block;            /* potential sweeps per kernel launch: 1, 2, 4 or 8 (0: 8).
                                    A launch keeps every sweep's residual, so the stopping
                                    sweep is the same for any value. */
+    int sweep_waves;            /* 64-lane waves per sweep workgroup, 4 or 8 (0: 4): the
+                                   region a workgroup sweeps is 64 x (8 * sweep_waves) nodes.
+                                   Results do not depend on it (nor on sweep_block). */
 } lbm_params;
 
 /* Scalar fields for lbm_get_field / lbm_set_field. */
@@ -167,10 +170,30 @@ int lbm_set_pop(lbm_handle* h, int set, const double* src);
 int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count);
 
 /* Measurement: launch exactly n potential sweeps (Eqs. (31)-(34), the step's inner
-   loop, in the launch configuration lbm_step uses, no stopping test) on the handle's
-   stream, bracketed by HIP events; *ms gets the elapsed GPU time.  The state
-   advances by n sweeps.  Synchronises the stream. */
+   loop, in the launch configuration lbm_step uses: the first workgroup of each launch
+   also evaluates the previous launch's residuals, but the loop never stops early) on
+   the handle's stream, bracketed by HIP events; *ms gets the elapsed GPU time.  The
+   state advances by n sweeps.  Synchronises the stream. */
 int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
+
+/* Autotuner of the potential-sweep launch shape (sweeps per launch x waves per
+   workgroup) for one grid size and precision; the shape changes no result, only speed.
+   Every candidate in {2, 4, 8} x {4, 8} is initialised on a temporary workspace that
+   the library allocates and frees (hipMalloc/hipFree), then `launches` launches of it are
+   timed twice on `stream` (the faster pass counts).  Results are cached per (nx, ny,
+   precision) for the life of the process; flags & LBM_TUNE_FORCE re-times.  Other
+   fields of *p only shape the timed state.  Synchronises the stream. */
+#define LBM_TUNE_FORCE 1
+#define LBM_TUNE_MAXCAND 8
+typedef struct {
+    int sweep_block, sweep_waves;          /* the fastest shape */
+    int cached;                            /* 1: taken from the cache */
+    int ncand;
+    int cand_block[LBM_TUNE_MAXCAND];
+    int cand_waves[LBM_TUNE_MAXCAND];
+    float us_per_sweep[LBM_TUNE_MAXCAND];  /* measured time per sweep */
+} lbm_tune;
+int lbm_autotune(const lbm_params* p, void* stream, int launches, int flags, lbm_tune* out);
 
 /* Release the handle (not the workspace, which the caller owns). */
 int lbm_destroy(lbm_handle* h);

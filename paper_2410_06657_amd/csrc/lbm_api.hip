@@ -10,7 +10,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lbm.h"
@@ -34,6 +37,7 @@ struct lbm_handle {
     int sp = 0;               // which buffer of the double-buffered sets is current
     int lcur = 0;             // which of the three buffers holds the current potential (l, phi)
     int swm = 8;              // sweeps per blocked launch
+    int swv = 4;              // waves per sweep workgroup
     long long step = 0;
     std::vector<int> log;     // sweep counts of every potential solve
     int last_sweeps = 0;
@@ -71,10 +75,28 @@ int validate(const lbm_params* p) {
     if (p->sweep_block != 0 && p->sweep_block != 1 && p->sweep_block != 2 && p->sweep_block != 4 &&
         p->sweep_block != 8)
         return LBM_EINVAL;
+    if (p->sweep_waves != 0 && p->sweep_waves != 4 && p->sweep_waves != 8) return LBM_EINVAL;
     return LBM_OK;
 }
 
 int sweep_m(const lbm_params* p) { return p->sweep_block ? p->sweep_block : 8; }
+int sweep_w(const lbm_params* p) { return p->sweep_waves ? p->sweep_waves : 4; }
+
+// Calls f(M, WV) with the sweep shape as compile-time constants.
+template <int M, typename F>
+void with_waves(int wv, F&& f) {
+    if (wv == 8) f(std::integral_constant<int, M>{}, std::integral_constant<int, 8>{});
+    else f(std::integral_constant<int, M>{}, std::integral_constant<int, 4>{});
+}
+template <typename F>
+void with_shape(int m, int wv, F&& f) {
+    switch (m) {
+        case 1: with_waves<1>(wv, f); break;
+        case 2: with_waves<2>(wv, f); break;
+        case 4: with_waves<4>(wv, f); break;
+        default: with_waves<8>(wv, f); break;
+    }
+}
 
 Dev make_dev(const lbm_params* p) {
     Dev d{};
@@ -86,7 +108,8 @@ Dev make_dev(const lbm_params* p) {
     d.gy = (p->ny + lbm::TY - 1) / lbm::TY;
     int m = sweep_m(p);
     d.tbx = (p->nx + (64 - 2 * m) - 1) / (64 - 2 * m);
-    d.tby = (p->ny + (lbm::SW_RY - 2 * m) - 1) / (lbm::SW_RY - 2 * m);
+    int ry = lbm::SW_NPT * sweep_w(p);
+    d.tby = (p->ny + (ry - 2 * m) - 1) / (ry - 2 * m);
     double tauf = p->M / lbm::CS2 + 0.5;  // Sec. 3.1
     d.omf = 1.0 / tauf;
     d.facf = 1.0 - 0.5 / tauf;
@@ -177,16 +200,13 @@ int fetch_ctl(lbm_handle* h) {
     return LBM_OK;
 }
 
-template <typename R>
+template <typename R, int Tag = 0>
 void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
     int nbt = h->dev.tbx * h->dev.tby;
     State<R>& s = h->st<R>();
-    switch (h->swm) {
-        case 1: lbm::k_sweep_tb<1, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
-        case 2: lbm::k_sweep_tb<2, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
-        case 4: lbm::k_sweep_tb<4, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
-        default: lbm::k_sweep_tb<8, R><<<nbt, NT, 0, h->stream>>>(h->dev, s, a); break;
-    }
+    with_shape(h->swm, h->swv, [&](auto M, auto WV) {
+        lbm::k_sweep_tb<M, R, WV, Tag><<<nbt, 64 * WV, 0, h->stream>>>(h->dev, s, a);
+    });
 }
 
 template <typename R>
@@ -217,7 +237,9 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     std::vector<lbm::SweepLaunch> plan;
     int next = 1;       // next sweep index
     int buf = h->lcur;  // buffer holding the state before sweep `next`
-    int nlaunch = std::max(1, (h->kprev - h->swm) / h->swm);
+    // first batch: the previous solve's count less one launch, at most 256 launches (after
+    // a solve that stopped at its cap the count says little about the next one)
+    int nlaunch = std::min(256, std::max(1, (h->kprev - h->swm) / h->swm));
     int grow = 1;
     const bool rebasing = std::is_same<R, float>::value;
     for (;;) {
@@ -359,7 +381,9 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
     lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, -1.0, 1, n);
     HIPCHK(h, hipEventRecord(a, h->stream));
     int buf = h->lcur;
+    lbm::SweepLaunch prev{};
     for (int k = 1, t = 0; k <= n; t++) {
+        // as in a solve: block 0 also tests the previous launch (never converging here)
         lbm::SweepLaunch s{};
         s.nsw = std::min(h->swm, n + 1 - k);
         s.src = buf;
@@ -367,7 +391,13 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
         s.k0 = k;
         s.slot = t & 1;
         s.launch = t;
-        launch_sweep<R>(h, s);
+        if (t > 0) {
+            s.prev_k0 = prev.k0;
+            s.prev_nsw = prev.nsw;
+            s.prev_slot = prev.slot;
+        }
+        launch_sweep<R, 1>(h, s);
+        prev = s;
         buf = s.dst;
         k += s.nsw;
     }
@@ -512,6 +542,7 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
     h->ws = (char*)workspace;
     h->ws_bytes = bytes;
     h->swm = sweep_m(p);
+    h->swv = sweep_w(p);
     if (h->prec == LBM_FP32) {
         carve<float>(d, h->ws, &h->sf);
         h->dctl = h->sf.ctl;
@@ -642,12 +673,111 @@ const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : ""
 }  // extern "C"
 
 // ===========================================================================
+// Autotuner of the potential-sweep shape.
+
+namespace {
+
+struct TuneKey {
+    int nx, ny, prec;
+    bool operator<(const TuneKey& o) const {
+        return nx != o.nx ? nx < o.nx : ny != o.ny ? ny < o.ny : prec < o.prec;
+    }
+};
+std::mutex tune_mu;
+std::map<TuneKey, lbm_tune> tune_cache;
+
+constexpr int TUNE_M[] = {2, 4, 8};
+constexpr int TUNE_W[] = {4, 8};
+
+int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune* out) {
+    lbm_tune r{};
+    size_t need = 0;
+    for (int m : TUNE_M)
+        for (int w : TUNE_W) {
+            lbm_params q = *p;
+            q.sweep_block = m;
+            q.sweep_waves = w;
+            size_t b = 0;
+            int rc = lbm_workspace_bytes(&q, &b);
+            if (rc) return rc;
+            need = std::max(need, b);
+        }
+    void* ws = nullptr;
+    if (hipMalloc(&ws, need) != hipSuccess) return LBM_EHIP;
+    int rc = LBM_OK;
+    float best = 0.f;
+    for (int m : TUNE_M)
+        for (int w : TUNE_W) {
+            lbm_params q = *p;
+            q.sweep_block = m;
+            q.sweep_waves = w;
+            q.poisson_tol = -1.0;  // a short fixed initial solve: the timing needs no convergence
+            q.poisson_max_sweeps = 2 * m;
+            lbm_handle* h = nullptr;
+            rc = lbm_init(&q, ws, need, stream, &h);
+            if (rc) break;
+            float t0 = 0.f, t1 = 0.f;
+            rc = lbm_time_sweeps(h, launches * m, &t0);  // first pass warms caches and code
+            if (!rc) rc = lbm_time_sweeps(h, launches * m, &t1);
+            lbm_destroy(h);
+            if (rc) break;
+            float us = std::min(t0, t1) * 1e3f / (float)(launches * m);
+            int k = r.ncand++;
+            r.cand_block[k] = m;
+            r.cand_waves[k] = w;
+            r.us_per_sweep[k] = us;
+            if (k == 0 || us < best) {
+                best = us;
+                r.sweep_block = m;
+                r.sweep_waves = w;
+            }
+        }
+    (void)hipFree(ws);
+    if (rc) return rc;
+    *out = r;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_autotune(const lbm_params* p, void* stream, int launches, int flags, lbm_tune* out) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out || launches < 1) return LBM_EINVAL;
+    TuneKey key{p->nx, p->ny, p->precision};
+    if (!(flags & LBM_TUNE_FORCE)) {
+        std::lock_guard<std::mutex> g(tune_mu);
+        auto it = tune_cache.find(key);
+        if (it != tune_cache.end()) {
+            *out = it->second;
+            out->cached = 1;
+            return LBM_OK;
+        }
+    }
+    lbm_tune r{};
+    rc = tune_shapes(p, (hipStream_t)stream, launches, &r);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> g(tune_mu);
+        tune_cache[key] = r;
+    }
+    *out = r;
+    out->cached = 0;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
 // Batched form.
 
 struct lbm_batch {
     int ncases = 0;
     int prec = LBM_FP64;
     int swm = 8;
+    int swv = 4;
     hipStream_t stream = nullptr;
     std::vector<lbm_params> prm;
     std::vector<Dev> dev;
@@ -686,7 +816,8 @@ int batch_validate(int ncases, const lbm_params* cases) {
     for (int c = 0; c < ncases; c++) {
         int rc = validate(&cases[c]);
         if (rc) return rc;
-        if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]))
+        if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]) ||
+            sweep_w(&cases[c]) != sweep_w(&cases[0]))
             return LBM_EINVAL;
     }
     return LBM_OK;
@@ -732,19 +863,12 @@ template <> std::vector<lbm::BatchCase<float>>& bcases<float>(lbm_batch* b) { re
 template <typename R>
 const lbm::BatchCase<R>* btable(lbm_batch* b) { return (const lbm::BatchCase<R>*)b->table; }
 
-template <int M, typename R>
-void batch_launch_sweep(lbm_batch* b, int t) {
-    lbm::kb_sweep<M, R><<<b->sweep_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_sw, b->ncases, b->lcur0_d, t);
-}
-
 template <typename R>
 void batch_sweep(lbm_batch* b, int t) {
-    switch (b->swm) {
-        case 1: batch_launch_sweep<1, R>(b, t); break;
-        case 2: batch_launch_sweep<2, R>(b, t); break;
-        case 4: batch_launch_sweep<4, R>(b, t); break;
-        default: batch_launch_sweep<8, R>(b, t); break;
-    }
+    with_shape(b->swm, b->swv, [&](auto M, auto WV) {
+        lbm::kb_sweep<M, R, WV><<<b->sweep_blocks, 64 * WV, 0, b->stream>>>(btable<R>(b), b->first_sw, b->ncases,
+                                                                            b->lcur0_d, t);
+    });
 }
 
 template <typename R>
@@ -761,12 +885,9 @@ void batch_test(lbm_batch* b, int t) {
 template <typename R>
 void batch_fix(lbm_batch* b) {
     auto tb = btable<R>(b);
-    switch (b->swm) {
-        case 1: lbm::kb_sweep_fix<1, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
-        case 2: lbm::kb_sweep_fix<2, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
-        case 4: lbm::kb_sweep_fix<4, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
-        default: lbm::kb_sweep_fix<8, R><<<b->sweep_blocks, NT, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d); break;
-    }
+    with_shape(b->swm, b->swv, [&](auto M, auto WV) {
+        lbm::kb_sweep_fix<M, R, WV><<<b->sweep_blocks, 64 * WV, 0, b->stream>>>(tb, b->first_sw, b->ncases, b->fix_d);
+    });
 }
 
 // Lockstep potential loops of all cases.  Launch t performs sweeps t*M+1.. of every case
@@ -786,7 +907,7 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
     int maxmax = 0;
     for (auto& p : b->prm) maxmax = std::max(maxmax, p.poisson_max_sweeps);
     int tmax = (maxmax + b->swm - 1) / b->swm;  // launches that reach every case's cap
-    int nlaunch = std::max(1, (kmin - b->swm) / b->swm);
+    int nlaunch = std::min(256, std::max(1, (kmin - b->swm) / b->swm));
     int grow = 1, t = 0;
     const bool rebasing = std::is_same<R, float>::value;
     const int reb = lbm::REBASE_SWEEPS / b->swm;  // launches between FP32 rebase points
@@ -983,6 +1104,7 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
     b->ncases = ncases;
     b->prec = cases[0].precision;
     b->swm = sweep_m(&cases[0]);
+    b->swv = sweep_w(&cases[0]);
     b->stream = (hipStream_t)stream;
     b->prm.assign(cases, cases + ncases);
     for (int c = 0; c < ncases; c++) b->dev.push_back(make_dev(&cases[c]));

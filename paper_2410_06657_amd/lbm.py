@@ -25,7 +25,9 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_diagnostics", "lbm_get_field", "lbm_set_field", "lbm_get_pop", "lbm_set_pop",
            "lbm_sweep_log", "lbm_time_sweeps", "lbm_destroy", "lbm_strerror", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_diagnostics",
-           "lbm_batch_get_field", "lbm_batch_sweep_log", "lbm_batch_destroy"]
+           "lbm_batch_get_field", "lbm_batch_sweep_log", "lbm_batch_destroy", "lbm_autotune"]
+
+LBM_TUNE_FORCE = 1
 
 
 class LbmParams(C.Structure):
@@ -47,10 +49,11 @@ class LbmParams(C.Structure):
         ("poisson_tol", C.c_double), ("poisson_max_sweeps", C.c_int),
         ("readings", C.c_uint),
         ("sweep_block", C.c_int),
+        ("sweep_waves", C.c_int),
     ]
 
 
-LAUNCH_DEFAULTS = {"sweep_block": 0}
+LAUNCH_DEFAULTS = {"sweep_block": 0, "sweep_waves": 0}
 
 
 class LbmDiag(C.Structure):
@@ -61,6 +64,13 @@ class LbmDiag(C.Structure):
         ("front_y", C.c_double), ("height", C.c_double), ("max_u", C.c_double),
         ("resid", C.c_double), ("sweeps", C.c_int), ("noconv", C.c_int),
         ("t_fre", C.c_double), ("V_l0", C.c_double), ("nonfinite", C.c_int),
+    ]
+
+
+class LbmTune(C.Structure):
+    _fields_ = [
+        ("sweep_block", C.c_int), ("sweep_waves", C.c_int), ("cached", C.c_int), ("ncand", C.c_int),
+        ("cand_block", C.c_int * 8), ("cand_waves", C.c_int * 8), ("us_per_sweep", C.c_float * 8),
     ]
 
 
@@ -108,6 +118,7 @@ def lib():
         L.lbm_batch_get_field.argtypes = [vp, C.c_int, C.c_int, dp]
         L.lbm_batch_sweep_log.argtypes = [vp, C.c_int, ip, C.c_int, ip]
         L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_autotune.argtypes = [C.POINTER(LbmParams), vp, C.c_int, C.c_int, C.POINTER(LbmTune)]
         _lib = L
     return _lib
 
@@ -136,6 +147,53 @@ def workspace_bytes(case: dict, precision: str = "fp64") -> int:
 
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def tune_cache_path() -> str:
+    return os.environ.get("LBM_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_2410_06657_amd", "sweep_shapes.json")
+
+
+def autotune(case: dict, precision: str = "fp64", launches: int = 20, force: bool = False,
+             device: str = "cuda:0", persist: bool = True) -> dict:
+    """Fastest potential-sweep launch shape for this grid size and precision, from the
+    library's autotuner (lbm_autotune).  Choices are kept in the process (by the library) and
+    in a small JSON file (tune_cache_path(), key "nx x ny / precision"), so a shape is timed
+    once per machine; force=True re-times."""
+    import json
+
+    import torch
+
+    key = f"{int(case['nx'])}x{int(case['ny'])}/{precision}"
+    path = tune_cache_path()
+    table = {}
+    if persist and os.path.exists(path):
+        try:
+            with open(path) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+    if not force and key in table:
+        return dict(table[key], cached="file")
+    p = make_params(case, precision)
+    out = LbmTune()
+    with torch.cuda.device(torch.device(device)):
+        stream = torch.cuda.current_stream()
+        rc = lib().lbm_autotune(C.byref(p), C.c_void_p(stream.cuda_stream), int(launches),
+                                LBM_TUNE_FORCE if force else 0, C.byref(out))
+    if rc != LBM_OK:
+        raise LbmError("lbm_autotune", rc)
+    res = {"sweep_block": out.sweep_block, "sweep_waves": out.sweep_waves,
+           "candidates": [{"sweep_block": out.cand_block[k], "sweep_waves": out.cand_waves[k],
+                           "us_per_sweep": round(float(out.us_per_sweep[k]), 4)} for k in range(out.ncand)]}
+    if persist:
+        table[key] = res
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return dict(res, cached="library" if out.cached else "")
 
 
 class Solver:

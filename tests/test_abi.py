@@ -48,7 +48,8 @@ def test_workspace_size_and_validation(liblbm):
     big = liblbm.workspace_bytes(inputs.cfg3())
     assert big > 6e9
     for bad in (dict(c, nx=1), dict(c, ny=2), dict(c, M=0.0), dict(c, sig_l=-1.0),
-                dict(c, poisson_max_sweeps=0), dict(c, shape=3)):
+                dict(c, poisson_max_sweeps=0), dict(c, shape=3), dict(c, sweep_block=3),
+                dict(c, sweep_waves=2)):
         with pytest.raises(liblbm.LbmError) as e:
             liblbm.workspace_bytes(bad)
         assert e.value.code == liblbm.LBM_EINVAL

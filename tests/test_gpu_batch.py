@@ -24,10 +24,10 @@ def mixed_cases():
     ]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_equals_single_runs(precision):
+@pytest.mark.parametrize("precision,shape", [("fp64", (8, 4)), ("fp32", (8, 4)), ("fp32", (4, 8))])
+def test_batch_equals_single_runs(precision, shape):
     from paper_2410_06657_amd.lbm import Batch, Solver
-    cases = mixed_cases()
+    cases = [dict(c, sweep_block=shape[0], sweep_waves=shape[1]) for c in mixed_cases()]
     b = Batch(cases, precision=precision)
     b.step(15)
     for c, case in enumerate(cases):

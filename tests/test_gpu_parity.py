@@ -203,16 +203,17 @@ def test_full_size_sampled():
 
 
 def test_sweep_block_invariance():
-    """Every sweeps-per-launch choice gives bitwise the same state (the per-node arithmetic of
-    a sweep does not depend on the blocking) and the same sweep counts as the oracle."""
+    """Every launch shape (sweeps per launch x waves per workgroup) gives bitwise the same
+    state (the per-node arithmetic of a sweep does not depend on the blocking) and the same
+    sweep counts as the oracle."""
     c = small_cfg1(1, 96, 48)
     o = ob.Oracle(c)
     o.step(12)
     ref = None
-    for m in (1, 2, 4, 8):
-        g = solver(dict(c, sweep_block=m))
+    for m, w in ((1, 4), (2, 4), (4, 4), (8, 4), (1, 8), (2, 8), (4, 8), (8, 8)):
+        g = solver(dict(c, sweep_block=m, sweep_waves=w))
         g.step(12)
-        assert list(g.sweep_log()) == list(o.sweep_log()), m
+        assert list(g.sweep_log()) == list(o.sweep_log()), (m, w)
         state = {k: g.field(k) for k in ("psi", "ux", "uy", "p", "T", "phi")}
         state["l"] = g.pop("l")
         if ref is None:
@@ -220,4 +221,4 @@ def test_sweep_block_invariance():
             compare(g, o)
         else:
             for k in state:
-                assert np.array_equal(state[k], ref[k]), (m, k)
+                assert np.array_equal(state[k], ref[k]), (m, w, k)
