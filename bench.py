@@ -25,6 +25,32 @@ SWEEP_ELEMS, STEP_ELEMS = 11, 80
 ELEM = {"fp64": 8, "fp32": 4}
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_cfg2_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2410_06657_amd", "csrc", "lbm_kernels.hpp")
+
+
+def measured_traffic(precision, workload_name):
+    """HBM bytes per launch of the timed sweep kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel), or None when the summary
+    is missing, covers another workload, or was taken from a different kernel source."""
+    import hashlib
+    if workload_name != "cfg2" or not os.path.exists(COUNTERS_FILE):
+        return None
+    table = {}
+    with open(COUNTERS_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] in ("kernel_source_sha256", "traffic_bytes_per_launch_fp64",
+                                                "traffic_bytes_per_launch_fp32"):
+                table[parts[0]] = parts[1]
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if table.get("kernel_source_sha256") != sha:
+        return None
+    v = table.get(f"traffic_bytes_per_launch_{precision}")
+    return int(v) if v else None
+
+
 def workload(name):
     from paper_2410_06657_amd import inputs
     if name == "cfg2":
@@ -69,7 +95,7 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
             "step_s": step_s}
 
 
-def run_form(case, precision, steps, warmup, sweep_launches):
+def run_form(case, precision, steps, warmup, sweep_launches, workload_name="cfg2"):
     """Time `steps` coupled steps of one precision form, then the dominant kernel."""
     import numpy as np
     import torch
@@ -106,7 +132,8 @@ def run_form(case, precision, steps, warmup, sweep_launches):
     per_launch = SWEEP_ELEMS * es * n * m
     achieved = per_launch / launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(precision, workload_name) if m == 8 else None,
                 "kernel": f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>",
                 "avg_launch_us": round(launch_s * 1e6, 3), "sweeps_per_launch": m,
                 "algorithmic_bytes_per_launch": per_launch,
@@ -122,6 +149,64 @@ def run_form(case, precision, steps, warmup, sweep_launches):
         "init_s": round(init_s, 2), "roofline": roofline,
         "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"]},
     }
+
+
+def run_batched(steps, warmup, cap, seed=4, ncases=96):
+    """The batched form on the 96-case sweep (uneven grids 256x128 .. 1536x768, FP32): the
+    whole batch advanced `steps` steps with one launch per stage, against the same cases run
+    one at a time with the same settings.  Each potential solve stops at 1e-8 or at `cap`
+    sweeps (the initial transients of these grids need far more, so the cap bounds the
+    bench's time; both sides do identical work)."""
+    import numpy as np
+    import torch
+
+    from paper_2410_06657_amd import inputs
+    from paper_2410_06657_amd.lbm import Batch, Solver, autotune
+
+    cases = inputs.cfg4(seed, ncases)
+    big = max(cases, key=lambda c: c["nx"] * c["ny"])
+    tune = autotune(dict(big, poisson_max_sweeps=cap), "fp32", launches=10, persist=False)
+    shape = {"sweep_block": tune["sweep_block"], "sweep_waves": tune["sweep_waves"]}
+    cases = [dict(c, poisson_max_sweeps=cap, **shape) for c in cases]
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    t0 = time.perf_counter()
+    b = Batch(cases, precision="fp32")
+    torch.cuda.synchronize()
+    print(f"[bench] batched: {len(cases)} cases, {nodes} nodes, init {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    sw_b = int(sum(int(np.sum(b.sweep_log(c)[1 + warmup:])) for c in range(len(cases))))
+    del b
+    torch.cuda.empty_cache()
+    print(f"[bench] batched: {steps} steps in {dt_b:.2f}s", file=sys.stderr, flush=True)
+    dt_s, sw_s = 0.0, 0
+    for k, c in enumerate(cases):
+        s = Solver(c, precision="fp32")
+        s.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        dt_s += time.perf_counter() - t0
+        sw_s += int(np.sum(s.sweep_log()[1 + warmup:]))
+        del s
+        if k % 16 == 15:
+            print(f"[bench] one at a time: {k + 1} cases, {dt_s:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    return {"value": round(nodes * steps / dt_b / 1e6, 3), "unit": "MLUPS",
+            "ms_per_step": round(dt_b / steps * 1e3, 3),
+            "one_at_a_time_value": round(nodes * steps / dt_s / 1e6, 3),
+            "speedup_vs_one_at_a_time": round(dt_s / dt_b, 3),
+            "ncases": len(cases), "nodes": nodes, "steps": steps, "warmup": warmup,
+            "poisson_max_sweeps": cap, "dtype": "f32", "sweep_shape": shape,
+            "sweeps_total": sw_b, "sweeps_total_one_at_a_time": sw_s,
+            "workload": "96 sessile drops, Ny~U{128..768 step 16}, Nx=2Ny, R0=0.3125Ny, "
+                        "Ca_E~U[0,0.4], theta~U[45,135], R~logU[0.3,5], S~logU[0.5,3], Ste=0.1, seed 4"}
 
 
 def counters_probe(case, launches=20):
@@ -164,6 +249,10 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--sweep-block", type=int, default=0,
                     help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--batched-cap", type=int, default=2000,
+                    help="potential sweeps cap per solve in the batched comparison")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc passes (copy calibration + sweep launches)")
     args = ap.parse_args()
@@ -178,7 +267,7 @@ def main():
         counters_probe(case)
         return
     n = case["nx"] * case["ny"]
-    f64 = run_form(case, "fp64", args.steps, args.warmup, args.sweep_launches)
+    f64 = run_form(case, "fp64", args.steps, args.warmup, args.sweep_launches, args.workload)
     line = {
         "metric": METRIC, "value": f64["value"], "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f64["ms_per_step"],
@@ -195,9 +284,11 @@ def main():
         "state": f64["state"],
     }
     if not args.no_fp32:
-        f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches)
+        f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches, args.workload)
         f32["speedup_vs_fp64"] = round(f32["value"] / f64["value"], 3)
         line["forms"] = {"fp32": f32}
+    if not args.no_batched:
+        line.setdefault("forms", {})["batched"] = run_batched(args.batched_steps, 2, args.batched_cap)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(case, f64["sweeps_per_step"])
         cb.pop("step_s")

@@ -690,8 +690,8 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
     }
 }
 
-// Tag only separates launches in a profile: Tag 1 is used by the library's timing entry
-// point, so its launches appear under their own name; the code is the same.
+// Tag only separates launches in a profile (1: the timing entry point, 2: the autotuner),
+// so they appear under their own names; the code is the same.
 template <int M, typename R, int WV, int Tag = 0>
 __global__ void __launch_bounds__(64 * WV) k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
     b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, gridDim.x));
