@@ -92,6 +92,10 @@ typedef struct lbm_params {
     int sweep_waves;            /* 64-lane waves per sweep workgroup, 4 or 8 (0: 4): the
                                    region a workgroup sweeps is 64 x (8 * sweep_waves) nodes.
                                    Results do not depend on it (nor on sweep_block). */
+    int skip_initial_solve;     /* 1: lbm_init leaves the linear-ramp potential unsolved (sweep
+                                   log entry 0) for the caller to seed (lbm_warm_start) and
+                                   solve (lbm_solve_potential); 0: solve as in Algorithm 1.
+                                   Single-case handles only. */
 } lbm_params;
 
 /* Scalar fields for lbm_get_field / lbm_set_field. */
@@ -224,6 +228,60 @@ int lbm_batch_destroy(lbm_batch* b);
 
 const char* lbm_strerror(int code);
 const char* lbm_last_error(const lbm_handle* h);
+
+/* ---- Learned warm start of the potential ------------------------------------------
+   A network maps coarse maps of the state to the coarse deviation of the potential from the
+   linear electrode ramp; its prediction seeds the potential links, after which the plain
+   sweeps of Eqs. (31)-(34) run to the same stopping rule (they remain the judge).  The
+   network: six 3x3 convolutions, 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 channels, dilations
+   1, 2, 4, 8, 4, 1, tanh between layers, zero padding; FP16 weights and activations with
+   FP32 accumulation on the matrix cores; FP32 master parameters and Adam (beta 0.9, 0.999,
+   eps 1e-8).  Coarse maps are FP32, NHWC (x fastest): input 3 maps per pixel (psi clamped to
+   [0, 1], ln(sigma / sigma_gas), ln(eps / eps_gas), cell averages with sigma and eps mixed by
+   Eq. (1)), output 1 map ((phi - ramp) / (phi_top - phi_bot), cell average).  Coarse cell
+   (I, J) covers fine nodes [I f, (I+1) f) x [J f, (J+1) f); nx and ny must be multiples of
+   the factor f.
+
+   Parameter order (lbm_nn_param_count floats): for each layer l = 0..5 the weights
+   [tap = 3 ky + kx][out 0..31][in 0..cin-1] (cin = 8 for layer 0, else 32; tap offset
+   ((kx - 1) d, (ky - 1) d)), then the 6 x 32 biases.  Entries that are padding (inputs 3..7
+   of layer 0, outputs 1..31 of layer 5) are held at zero. */
+typedef struct lbm_nn lbm_nn;
+
+int lbm_nn_param_count(int* count);
+/* Device workspace for activations of up to max_pixels coarse pixels per call (images x
+   height x width); caller-owned, 256-byte aligned. */
+int lbm_nn_workspace_bytes(long long max_pixels, size_t* bytes);
+/* Glorot-uniform initial weights from SplitMix64(seed), zero biases; kernels run on
+   `stream`.  Synchronises the stream. */
+int lbm_nn_init(void* workspace, size_t bytes, long long max_pixels, unsigned long long seed, void* stream,
+                lbm_nn** out);
+/* Host FP32 parameters in the order above; set also resets the Adam state. */
+int lbm_nn_set_params(lbm_nn* nn, const float* host);
+int lbm_nn_get_params(lbm_nn* nn, float* host);
+/* x: device FP32 (n, h, w, 3); y: device FP32 (n, h, w).  Asynchronous on the stream. */
+int lbm_nn_forward(lbm_nn* nn, const float* x, float* y, int n, int h, int w);
+/* Gradient of L = sum over pixels of (y - t)^2 with respect to every parameter (host FP32,
+   parameter order; padding entries 0) and L (host).  x, t on the device.  Synchronises. */
+int lbm_nn_gradient(lbm_nn* nn, const float* x, const float* t, int n, int h, int w, float* grad, double* loss);
+/* One Adam step of learning rate lr on L; *loss (optional, synchronises) gets L before the step. */
+int lbm_nn_train_step(lbm_nn* nn, const float* x, const float* t, int n, int h, int w, float lr, double* loss);
+int lbm_nn_destroy(lbm_nn* nn);
+const char* lbm_nn_last_error(const lbm_nn* nn);
+
+/* Coarse input maps of the handle's current state (device FP32, (ny/f) x (nx/f) x 3), the
+   coarse target from its current potential ((ny/f) x (nx/f)), and the seeding of its
+   current potential links and phi from a coarse deviation map (bilinear between cell
+   centres, periodic in x, clamped in y; links at their equilibria w_i phi).  Asynchronous on
+   the handle's stream. */
+int lbm_nn_features(lbm_handle* h, int factor, float* x);
+int lbm_nn_target(lbm_handle* h, int factor, float* t);
+int lbm_nn_seed(lbm_handle* h, int factor, const float* y);
+/* features -> network -> seed, on the handle's stream, using the network's own buffers
+   ((nx/f)(ny/f) <= its pixel capacity).  Follow with lbm_solve_potential (or lbm_step). */
+int lbm_warm_start(lbm_handle* h, lbm_nn* nn, int factor);
+/* Training sample of case c of a batch: its input maps and target (device FP32).  Synchronises. */
+int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t);
 
 #ifdef __cplusplus
 }

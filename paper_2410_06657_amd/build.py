@@ -14,10 +14,10 @@ HIPFLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "csrc", "lbm_api.hip")
+    srcs = [os.path.join(HERE, "csrc", f) for f in ("lbm_api.hip", "nn_api.hip")]
     tmp = LIB + ".tmp"
     cmd = ["hipcc", *HIPFLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp, src]
+           "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -18,6 +18,7 @@
 
 #include "lbm.h"
 #include "lbm_kernels.hpp"
+#include "nn_state.hpp"
 
 using lbm::Ctl;
 using lbm::Dev;
@@ -76,6 +77,7 @@ int validate(const lbm_params* p) {
         p->sweep_block != 8)
         return LBM_EINVAL;
     if (p->sweep_waves != 0 && p->sweep_waves != 4 && p->sweep_waves != 8) return LBM_EINVAL;
+    if (p->skip_initial_solve != 0 && p->skip_initial_solve != 1) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -346,9 +348,14 @@ int init_state(lbm_handle* h) {
     lbm::k_init<R><<<h->nb, NT, 0, h->stream>>>(d, s);
     lbm::k_oml<R><<<h->nb, NT, 0, h->stream>>>(d, s, 0);
     LAUNCHCHK(h);
-    // first solve from equilibrium populations: the stopping test counts from sweep 2
-    int rc = run_sweeps<R>(h, h->prm.poisson_tol, 2, h->prm.poisson_max_sweeps, nullptr, nullptr);
-    if (rc && rc != LBM_ENOCONV) return rc;
+    if (h->prm.skip_initial_solve) {
+        // the caller seeds and solves the potential (warm start); the ramp stays for now
+        h->log.push_back(0);
+    } else {
+        // first solve from equilibrium populations: the stopping test counts from sweep 2
+        int rc = run_sweeps<R>(h, h->prm.poisson_tol, 2, h->prm.poisson_max_sweeps, nullptr, nullptr);
+        if (rc && rc != LBM_ENOCONV) return rc;
+    }
     lbm::k_vl0<R><<<h->nb, NT, 0, h->stream>>>(d, s);
     lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->partials, h->dctl, 1);
     LAUNCHCHK(h);
@@ -1197,6 +1204,90 @@ int lbm_batch_destroy(lbm_batch* b) {
     if (b->ctl_h) (void)hipHostFree(b->ctl_h);
     delete b;
     return LBM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Learned warm start on a solver handle.
+
+namespace {
+
+bool coarse_ok(const lbm_handle* h, int f) {
+    return f >= 1 && h->dev.nx % f == 0 && h->dev.ny % f == 0;
+}
+
+template <typename R>
+int nn_features(lbm_handle* h, int f, float* x) {
+    int nc = (h->dev.nx / f) * (h->dev.ny / f);
+    lbm::k_nn_features<R><<<(nc + NT - 1) / NT, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, f, x);
+    LAUNCHCHK(h);
+    return LBM_OK;
+}
+
+template <typename R>
+int nn_target(lbm_handle* h, int f, float* t) {
+    int nc = (h->dev.nx / f) * (h->dev.ny / f);
+    lbm::k_nn_target<R><<<(nc + NT - 1) / NT, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur, f, t);
+    LAUNCHCHK(h);
+    return LBM_OK;
+}
+
+template <typename R>
+int nn_seed(lbm_handle* h, int f, const float* y) {
+    lbm::k_nn_seed<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur, f, y);
+    LAUNCHCHK(h);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_nn_features(lbm_handle* h, int factor, float* x) {
+    if (!h) return LBM_ESTATE;
+    if (!x || !coarse_ok(h, factor)) return LBM_EINVAL;
+    return h->prec == LBM_FP32 ? nn_features<float>(h, factor, x) : nn_features<double>(h, factor, x);
+}
+
+int lbm_nn_target(lbm_handle* h, int factor, float* t) {
+    if (!h) return LBM_ESTATE;
+    if (!t || !coarse_ok(h, factor)) return LBM_EINVAL;
+    return h->prec == LBM_FP32 ? nn_target<float>(h, factor, t) : nn_target<double>(h, factor, t);
+}
+
+int lbm_nn_seed(lbm_handle* h, int factor, const float* y) {
+    if (!h) return LBM_ESTATE;
+    if (!y || !coarse_ok(h, factor)) return LBM_EINVAL;
+    return h->prec == LBM_FP32 ? nn_seed<float>(h, factor, y) : nn_seed<double>(h, factor, y);
+}
+
+int lbm_warm_start(lbm_handle* h, lbm_nn* nnh, int factor) {
+    if (!h || !nnh) return LBM_ESTATE;
+    if (!coarse_ok(h, factor)) return LBM_EINVAL;
+    int nxc = h->dev.nx / factor, nyc = h->dev.ny / factor;
+    if ((int64_t)nxc * nyc > nnh->cap) return LBM_EINVAL;
+    int rc = lbm_nn_features(h, factor, nnh->x);
+    if (!rc) rc = nnapi::forward(nnh, nnh->x, nnh->y, 1, nyc, nxc, h->stream);
+    if (rc) {
+        if (rc == LBM_EHIP) h->err = nnh->err;
+        return rc;
+    }
+    return lbm_nn_seed(h, factor, nnh->y);
+}
+
+int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t) {
+    if (!b) return LBM_ESTATE;
+    if (c < 0 || c >= b->ncases || !x || !t) return LBM_EINVAL;
+    lbm_handle h;
+    if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+    if (!coarse_ok(&h, factor)) return LBM_EINVAL;
+    int rc = lbm_nn_features(&h, factor, x);
+    if (!rc) rc = lbm_nn_target(&h, factor, t);
+    if (!rc && hipStreamSynchronize(b->stream) != hipSuccess) rc = LBM_EHIP;
+    if (rc) b->err = h.err;
+    h.hctl = nullptr;
+    return rc;
 }
 
 }  // extern "C"

@@ -1269,4 +1269,86 @@ __global__ void __launch_bounds__(NT) kb_vl_finalize(const BatchCase<R>* __restr
     c->V_prev = a;
 }
 
+// ---------------------------------------------------------------------------
+// Learned warm start of the potential: coarse input maps, coarse target, and the seeding of
+// the potential links.  Coarse cell (I, J) covers the fine nodes [I f, (I + 1) f) x
+// [J f, (J + 1) f); coarse maps are NHWC with the x index fastest.
+
+// Input maps averaged over a cell: clamped psi, ln(sigma / sigma_gas), ln(eps / eps_gas)
+// with sigma and eps mixed by Eq. (1) (0 when the gas permittivity is 0).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_nn_features(Dev d, State<R> s, int sp, int f, float* __restrict__ x) {
+    const int nxc = d.nx / f, nyc = d.ny / f;
+    const int c = blockIdx.x * NT + threadIdx.x;
+    if (c >= nxc * nyc) return;
+    const int I = c % nxc, J = c / nxc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int j = J * f; j < (J + 1) * f; j++)
+        for (int i = I * f; i < (I + 1) * f; i++) {
+            const int64_t n = at(d, i, j);
+            const double ps = (double)s.psi[sp][n], fs = (double)s.fs[sp][n];
+            a0 += clamp01(ps);
+            a1 += log(mix<double>(d.sig_s, d.sig_l, d.sig_g, ps, fs) / d.sig_g);
+            if (d.eps_g > 0.0) a2 += log(mix<double>(d.eps_s, d.eps_l, d.eps_g, ps, fs) / d.eps_g);
+        }
+    const double inv = 1.0 / ((double)f * f);
+    x[3 * (int64_t)c] = (float)(a0 * inv);
+    x[3 * (int64_t)c + 1] = (float)(a1 * inv);
+    x[3 * (int64_t)c + 2] = (float)(a2 * inv);
+}
+
+__device__ __forceinline__ double phi_ramp(const Dev& d, int j) {
+    return d.phi_bot + (d.phi_top - d.phi_bot) * (j + 0.5) / d.ny;
+}
+
+// Target: the cell average of (phi - ramp) / (phi_top - phi_bot).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_nn_target(Dev d, State<R> s, int lcur, int f, float* __restrict__ t) {
+    const int nxc = d.nx / f, nyc = d.ny / f;
+    const int c = blockIdx.x * NT + threadIdx.x;
+    if (c >= nxc * nyc) return;
+    const int I = c % nxc, J = c / nxc;
+    double a = 0.0;
+    for (int j = J * f; j < (J + 1) * f; j++)
+        for (int i = I * f; i < (I + 1) * f; i++) a += (double)s.phi[lcur][at(d, i, j)] - phi_ramp(d, j);
+    t[c] = (float)(a / ((double)f * f) / (d.phi_top - d.phi_bot));
+}
+
+// Seed: phi = ramp + (phi_top - phi_bot) * (bilinear interpolation of the coarse deviation at
+// the node, cell-centred values, periodic in x, clamped in y); the four links of buffer lcur
+// become their equilibria w_i phi (FP32: base/remainder pairs) and phi is written.
+template <typename R>
+__device__ __forceinline__ void b_nn_seed(const Dev& d, const State<R>& s, int lcur, int f,
+                                          const float* __restrict__ yc, int tile) {
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    const int nxc = d.nx / f, nyc = d.ny / f;
+    const double X = (i + 0.5) / f - 0.5, Y = (j + 0.5) / f - 0.5;
+    const int i0 = (int)floor(X), j0 = (int)floor(Y);
+    const double fx = X - i0, fy = Y - j0;
+    const int ia = (i0 % nxc + nxc) % nxc, ib = (ia + 1) % nxc;
+    const int ja = j0 < 0 ? 0 : (j0 > nyc - 1 ? nyc - 1 : j0);
+    const int jb = j0 + 1 > nyc - 1 ? nyc - 1 : (j0 + 1 < 0 ? 0 : j0 + 1);
+    const double v = (1.0 - fy) * ((1.0 - fx) * yc[ja * nxc + ia] + fx * yc[ja * nxc + ib]) +
+                     fy * ((1.0 - fx) * yc[jb * nxc + ia] + fx * yc[jb * nxc + ib]);
+    const double phi = phi_ramp(d, j) + (d.phi_top - d.phi_bot) * v;
+    const double leq = LWA * phi;
+    const int64_t n = at(d, i, j);
+    constexpr bool based = std::is_same<R, float>::value;
+    R base = based ? R(leq) : R(0);
+    R l = R(leq - (double)base);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        s.l[lcur][q * d.plane + n] = l;
+        if (based) s.lb[q * d.plane + n] = base;
+    }
+    s.phi[lcur][n] = based ? R(phi) : (l + l + l + l) * R(INV_1MW0);
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_nn_seed(Dev d, State<R> s, int lcur, int f, const float* __restrict__ yc) {
+    b_nn_seed<R>(d, s, lcur, f, yc, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 }  // namespace lbm
+

@@ -25,7 +25,11 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_diagnostics", "lbm_get_field", "lbm_set_field", "lbm_get_pop", "lbm_set_pop",
            "lbm_sweep_log", "lbm_time_sweeps", "lbm_destroy", "lbm_strerror", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_diagnostics",
-           "lbm_batch_get_field", "lbm_batch_sweep_log", "lbm_batch_destroy", "lbm_autotune"]
+           "lbm_batch_get_field", "lbm_batch_sweep_log", "lbm_batch_destroy", "lbm_autotune",
+           "lbm_nn_param_count", "lbm_nn_workspace_bytes", "lbm_nn_init", "lbm_nn_set_params",
+           "lbm_nn_get_params", "lbm_nn_forward", "lbm_nn_gradient", "lbm_nn_train_step",
+           "lbm_nn_destroy", "lbm_nn_last_error", "lbm_nn_features", "lbm_nn_target", "lbm_nn_seed",
+           "lbm_warm_start", "lbm_batch_nn_sample"]
 
 LBM_TUNE_FORCE = 1
 
@@ -50,10 +54,11 @@ class LbmParams(C.Structure):
         ("readings", C.c_uint),
         ("sweep_block", C.c_int),
         ("sweep_waves", C.c_int),
+        ("skip_initial_solve", C.c_int),
     ]
 
 
-LAUNCH_DEFAULTS = {"sweep_block": 0, "sweep_waves": 0}
+LAUNCH_DEFAULTS = {"sweep_block": 0, "sweep_waves": 0, "skip_initial_solve": 0}
 
 
 class LbmDiag(C.Structure):
@@ -119,6 +124,23 @@ def lib():
         L.lbm_batch_sweep_log.argtypes = [vp, C.c_int, ip, C.c_int, ip]
         L.lbm_batch_destroy.argtypes = [vp]
         L.lbm_autotune.argtypes = [C.POINTER(LbmParams), vp, C.c_int, C.c_int, C.POINTER(LbmTune)]
+        fp = C.POINTER(C.c_float)
+        L.lbm_nn_param_count.argtypes = [ip]
+        L.lbm_nn_workspace_bytes.argtypes = [C.c_longlong, C.POINTER(C.c_size_t)]
+        L.lbm_nn_init.argtypes = [vp, C.c_size_t, C.c_longlong, C.c_ulonglong, vp, C.POINTER(vp)]
+        L.lbm_nn_set_params.argtypes = [vp, fp]
+        L.lbm_nn_get_params.argtypes = [vp, fp]
+        L.lbm_nn_forward.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int]
+        L.lbm_nn_gradient.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, fp, dp]
+        L.lbm_nn_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, dp]
+        L.lbm_nn_destroy.argtypes = [vp]
+        L.lbm_nn_last_error.argtypes = [vp]
+        L.lbm_nn_last_error.restype = C.c_char_p
+        L.lbm_nn_features.argtypes = [vp, C.c_int, vp]
+        L.lbm_nn_target.argtypes = [vp, C.c_int, vp]
+        L.lbm_nn_seed.argtypes = [vp, C.c_int, vp]
+        L.lbm_warm_start.argtypes = [vp, vp, C.c_int]
+        L.lbm_batch_nn_sample.argtypes = [vp, C.c_int, C.c_int, vp, vp]
         _lib = L
     return _lib
 
@@ -278,6 +300,29 @@ class Solver:
         self._check("lbm_time_sweeps", lib().lbm_time_sweeps(self._h, int(n), C.byref(ms)))
         return ms.value
 
+    def nn_features(self, factor: int):
+        """Coarse input maps of the current state: torch FP32 (ny/f, nx/f, 3) on the device."""
+        import torch
+        x = torch.empty((self.ny // factor, self.nx // factor, 3), dtype=torch.float32, device=self.device)
+        self._check("lbm_nn_features", lib().lbm_nn_features(self._h, int(factor), C.c_void_p(x.data_ptr())))
+        return x
+
+    def nn_target(self, factor: int):
+        """Coarse potential deviation of the current state: torch FP32 (ny/f, nx/f)."""
+        import torch
+        t = torch.empty((self.ny // factor, self.nx // factor), dtype=torch.float32, device=self.device)
+        self._check("lbm_nn_target", lib().lbm_nn_target(self._h, int(factor), C.c_void_p(t.data_ptr())))
+        return t
+
+    def nn_seed(self, factor: int, y):
+        """Seed the potential from a coarse deviation map (torch FP32 (ny/f, nx/f) on the device)."""
+        y = y.contiguous()
+        self._check("lbm_nn_seed", lib().lbm_nn_seed(self._h, int(factor), C.c_void_p(y.data_ptr())))
+
+    def warm_start(self, net: "Net", factor: int):
+        """Features -> network -> seeded potential, on this solver's stream."""
+        self._check("lbm_warm_start", lib().lbm_warm_start(self._h, net._h, int(factor)))
+
     def sweep_log(self) -> np.ndarray:
         cnt = C.c_int()
         lib().lbm_sweep_log(self._h, None, 0, C.byref(cnt))
@@ -348,6 +393,19 @@ class Batch:
             raise LbmError("lbm_batch_get_field", rc)
         return out
 
+    def nn_sample(self, c: int, factor: int):
+        """Input maps and target of case c (torch FP32 on the device)."""
+        import torch
+        case = self.cases[c]
+        hc, wc = int(case["ny"]) // factor, int(case["nx"]) // factor
+        x = torch.empty((hc, wc, 3), dtype=torch.float32, device=self.device)
+        t = torch.empty((hc, wc), dtype=torch.float32, device=self.device)
+        rc = lib().lbm_batch_nn_sample(self._h, int(c), int(factor), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(t.data_ptr()))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_nn_sample", rc)
+        return x, t
+
     def sweep_log(self, c: int) -> np.ndarray:
         cnt = C.c_int()
         lib().lbm_batch_sweep_log(self._h, int(c), None, 0, C.byref(cnt))
@@ -355,3 +413,92 @@ class Batch:
         buf = (C.c_int * max(n, 1))()
         lib().lbm_batch_sweep_log(self._h, int(c), buf, n, C.byref(cnt))
         return np.array(buf[:n], dtype=np.int64)
+
+
+class Net:
+    """The warm-start network (lbm_nn_*): parameters, forward pass, gradient and Adam steps run
+    in the library's kernels on torch's current stream of `device`; inputs and outputs are
+    torch FP32 device tensors (x: (n, h, w, 3), y and targets: (n, h, w))."""
+
+    def __init__(self, max_pixels: int, seed: int = 1, device: str = "cuda:0"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library has no CPU path")
+        self.device = torch.device(device)
+        self.max_pixels = int(max_pixels)
+        nbytes = C.c_size_t()
+        rc = lib().lbm_nn_workspace_bytes(self.max_pixels, C.byref(nbytes))
+        if rc != LBM_OK:
+            raise LbmError("lbm_nn_workspace_bytes", rc)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = lib().lbm_nn_init(C.c_void_p(self.workspace.data_ptr()), nbytes, self.max_pixels, int(seed),
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError("lbm_nn_init", rc)
+        self._h = h
+        cnt = C.c_int()
+        lib().lbm_nn_param_count(C.byref(cnt))
+        self.nparams = cnt.value
+
+    def _check(self, what, rc):
+        if rc != LBM_OK:
+            raise LbmError(what, rc, lib().lbm_nn_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        self._check("lbm_nn_get_params", lib().lbm_nn_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        self._check("lbm_nn_set_params", lib().lbm_nn_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    @staticmethod
+    def _shape(x):
+        n, h, w, c = x.shape
+        assert c == 3
+        return int(n), int(h), int(w)
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        n, h, w = self._shape(x)
+        y = torch.empty((n, h, w), dtype=torch.float32, device=self.device)
+        self._check("lbm_nn_forward", lib().lbm_nn_forward(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                                           n, h, w))
+        return y
+
+    def gradient(self, x, t):
+        x, t = x.contiguous(), t.contiguous()
+        n, h, w = self._shape(x)
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = C.c_double()
+        self._check("lbm_nn_gradient", lib().lbm_nn_gradient(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                                             n, h, w, g.ctypes.data_as(C.POINTER(C.c_float)),
+                                                             C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float, want_loss: bool = False):
+        x, t = x.contiguous(), t.contiguous()
+        n, h, w = self._shape(x)
+        loss = C.c_double()
+        self._check("lbm_nn_train_step", lib().lbm_nn_train_step(
+            self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), n, h, w, float(lr),
+            C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None

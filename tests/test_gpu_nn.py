@@ -1,0 +1,153 @@
+"""The warm-start network's HIP kernels (MFMA forward, backward, Adam) against the FP64
+reference network of the oracle, and the coarse-map kernels against their definitions.
+
+The GPU stores weights and activations in FP16 (FP32 accumulation), so the reference is fed
+the same FP16-rounded weights and the bars are those of FP16 activations: forward relative
+L2 <= 5e-3, gradient relative L2 <= 3e-2 per layer."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+from paper_2410_06657_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, float) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def fp16(p):
+    return np.asarray(p, np.float32).astype(np.float16).astype(np.float64)
+
+
+def layer_slices():
+    off, out = 0, []
+    for l in range(cnn.NL):
+        n = 9 * 32 * cnn.CIN_STORED[l]
+        out.append(slice(off, off + n))
+        off += n
+    return out, off
+
+
+def reference_params(p32):
+    """The GPU's effective parameters: FP16 weights, FP32 biases."""
+    sl, nw = layer_slices()
+    q = np.asarray(p32, np.float64).copy()
+    q[:nw] = fp16(p32[:nw])
+    return q
+
+
+def inputs_for(n, h, w, seed):
+    rng = np.random.default_rng(seed)
+    x = np.stack([rng.uniform(0, 1, (n, h, w)), rng.normal(0, 1, (n, h, w)), rng.normal(0, 0.5, (n, h, w))], -1)
+    t = rng.normal(0, 0.1, (n, h, w))
+    return x, t
+
+
+@pytest.mark.parametrize("shape", [(2, 16, 64), (3, 9, 45)])
+def test_forward_matches_reference(shape):
+    import torch
+    from paper_2410_06657_amd.lbm import Net
+    n, h, w = shape
+    net = Net(n * h * w, seed=11)
+    x, _ = inputs_for(n, h, w, 1)
+    y = net.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    p = net.params()
+    y_ref, _ = cnn.forward(reference_params(p), x.astype(np.float32).astype(np.float64))
+    e = rel(y, y_ref)
+    print(f"forward rel L2 {e:.2e}")
+    assert e <= 5e-3
+
+
+def test_gradient_matches_reference():
+    import torch
+    from paper_2410_06657_amd.lbm import Net
+    n, h, w = 2, 12, 40
+    net = Net(n * h * w, seed=5)
+    x, t = inputs_for(n, h, w, 2)
+    # targets the untrained network is far from, so every layer carries gradient
+    t = t * 10
+    loss, g = net.gradient(torch.tensor(x, dtype=torch.float32, device="cuda"),
+                           torch.tensor(t, dtype=torch.float32, device="cuda"))
+    p = net.params()
+    loss_ref, g_ref = cnn.loss_and_grad(reference_params(p), x.astype(np.float32).astype(np.float64),
+                                        t.astype(np.float32).astype(np.float64))
+    assert loss == pytest.approx(loss_ref, rel=1e-2)
+    sl, nw = layer_slices()
+    for l in range(cnn.NL):
+        e = rel(g[sl[l]], g_ref[sl[l]])
+        eb = rel(g[nw + 32 * l:nw + 32 * (l + 1)], g_ref[nw + 32 * l:nw + 32 * (l + 1)])
+        print(f"layer {l}: dW rel {e:.2e}, db rel {eb:.2e}")
+        assert e <= 3e-2 and eb <= 3e-2, l
+    # padding entries carry exactly zero gradient
+    ref_zero = g_ref == 0.0
+    assert np.all(g[ref_zero] == 0.0)
+
+
+def test_training_reduces_the_loss():
+    """Adam steps on a fixed batch: the loss falls by 10x (targets from a smooth map of the
+    inputs that the network can represent)."""
+    import torch
+    from paper_2410_06657_amd.lbm import Net
+    n, h, w = 8, 16, 32
+    net = Net(n * h * w, seed=3)
+    x, _ = inputs_for(n, h, w, 4)
+    t = 0.2 * np.tanh(x[..., 0] - 0.5 * x[..., 1])
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    l0 = net.train_step(xd, td, 1e-3, want_loss=True)
+    for k in range(300):
+        net.train_step(xd, td, 1e-3)
+    l1 = net.train_step(xd, td, 1e-3, want_loss=True)
+    print(f"loss {l0:.3e} -> {l1:.3e}")
+    assert l1 < 0.1 * l0
+
+
+def test_coarse_maps_and_seed():
+    """Features, target and seed kernels against their definitions on the solver's fields."""
+    import torch
+    from paper_2410_06657_amd.lbm import Solver
+    c = inputs.sessile_drop(128, 64, 20.0, 70.0, 3.0, 2.0, 0.2, 0.1, seed=9)
+    s = Solver(c)
+    s.step(3)
+    f = 8
+    psi, fs, phi = s.field("psi"), s.field("fs"), s.field("phi")
+
+    def cells(a):
+        return a.reshape(64 // f, f, 128 // f, f).mean(axis=(1, 3))
+
+    pc = np.clip(psi, 0, 1)
+    mixr = lambda a_s, a_l, a_g: fs * a_s + (1 - fs) * pc * a_l + (1 - fs) * (1 - pc) * a_g
+    sig = mixr(c["sig_s"], c["sig_l"], c["sig_g"])
+    eps = mixr(c["eps_s"], c["eps_l"], c["eps_g"])
+    x = s.nn_features(f).cpu().numpy()
+    assert np.allclose(x[..., 0], cells(pc), atol=1e-6)
+    assert np.allclose(x[..., 1], cells(np.log(sig / c["sig_g"])), atol=1e-5)
+    assert np.allclose(x[..., 2], cells(np.log(eps / c["eps_g"])), atol=1e-5)
+    ramp = c["phi_bot"] + (c["phi_top"] - c["phi_bot"]) * (np.arange(64)[:, None] + 0.5) / 64
+    t = s.nn_target(f).cpu().numpy()
+    assert np.allclose(t, cells(phi - ramp) / (c["phi_top"] - c["phi_bot"]), atol=1e-6)
+    # seed from a known coarse map and read phi back: bilinear between cell centres
+    rng = np.random.default_rng(0)
+    yc = rng.normal(0, 0.05, (64 // f, 128 // f)).astype(np.float32)
+    s.nn_seed(f, torch.tensor(yc, device="cuda"))
+    got = s.field("phi")
+    X = (np.arange(128) + 0.5) / f - 0.5
+    Y = (np.arange(64) + 0.5) / f - 0.5
+    i0 = np.floor(X).astype(int)
+    j0 = np.floor(Y).astype(int)
+    fx, fy = X - i0, Y - j0
+    ia, ib = i0 % (128 // f), (i0 + 1) % (128 // f)
+    ja, jb = np.clip(j0, 0, 64 // f - 1), np.clip(j0 + 1, 0, 64 // f - 1)
+    yd = yc.astype(np.float64)
+    v = ((1 - fy)[:, None] * ((1 - fx)[None, :] * yd[ja][:, ia] + fx[None, :] * yd[ja][:, ib]) +
+         fy[:, None] * ((1 - fx)[None, :] * yd[jb][:, ia] + fx[None, :] * yd[jb][:, ib]))
+    assert np.allclose(got, ramp + v * (c["phi_top"] - c["phi_bot"]), atol=1e-12)
+    links = s.pop("l")
+    assert np.allclose(links, np.broadcast_to(got / 6.0, links.shape), atol=1e-15)
+    # the sweeps then take over from the seeded state
+    rc, k, r = s.solve_potential(1e-8, 200000)
+    assert rc == 0 and k > 1 and math.isfinite(r)
