@@ -29,6 +29,21 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_cfg2_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2410_06657_amd", "csrc", "lbm_kernels.hpp")
 
 
+SWEEP_BEGIN = "// Blocked potential sweeps"
+SWEEP_END = "// FP32 form: renormalise"
+
+
+def sweep_source_digest():
+    """SHA-256 of the sweep kernel's source section (its test, body and launch wrapper)."""
+    import hashlib
+    with open(KERNEL_SOURCE, encoding="utf-8") as f:
+        text = f.read()
+    a, b = text.find(SWEEP_BEGIN), text.find(SWEEP_END)
+    if a < 0 or b <= a:
+        return None
+    return hashlib.sha256(text[a:b].encode()).hexdigest()
+
+
 def measured_traffic(precision, workload_name):
     """HBM bytes per launch of the timed sweep kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel), or None when the summary
@@ -43,9 +58,8 @@ def measured_traffic(precision, workload_name):
             if len(parts) >= 2 and parts[0] in ("kernel_source_sha256", "traffic_bytes_per_launch_fp64",
                                                 "traffic_bytes_per_launch_fp32"):
                 table[parts[0]] = parts[1]
-    with open(KERNEL_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if table.get("kernel_source_sha256") != sha:
+    sha = sweep_source_digest()
+    if sha is None or table.get("kernel_source_sha256") != sha:
         return None
     v = table.get(f"traffic_bytes_per_launch_{precision}")
     return int(v) if v else None
@@ -209,6 +223,65 @@ def run_batched(steps, warmup, cap, seed=4, ncases=96):
                         "Ca_E~U[0,0.4], theta~U[45,135], R~logU[0.3,5], S~logU[0.5,3], Ste=0.1, seed 4"}
 
 
+def run_warm(steps=20, seed=6):
+    """Learned warm start on the 2048 x 1024 grid (R0 = 320, theta = 90, R = 3, S = 1,
+    Ca_E = 0.1): the initial potential solve from the linear ramp
+    (cold) against network seed + the same sweeps (warm), both to 1e-8, and the potential
+    error of each against a solve to 1e-12; then `steps` steps with every solve started from
+    the previous step's potential against every solve seeded by the network."""
+    import numpy as np
+    import torch
+
+    from paper_2410_06657_amd import inputs, warm
+    from paper_2410_06657_amd.lbm import Solver
+
+    nx, ny = 2048, 1024
+    f = warm.factor_for(ny)
+    net = warm.load((nx // f) * (ny // f))
+    c = inputs.sessile_drop(nx, ny, 0.3125 * ny, 90.0, 3.0, 1.0, 0.1, 0.1, seed=seed)
+    c["poisson_max_sweeps"] = 4000000
+    t0 = time.perf_counter()
+    cold = Solver(c)
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - t0
+    k_cold = int(cold.sweep_log()[0])
+    print(f"[bench] warm: cold initial solve {k_cold} sweeps, {t_cold:.2f}s", file=sys.stderr, flush=True)
+    w = Solver(dict(c, skip_initial_solve=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w.warm_start(net, f)
+    rc, k_warm, _ = w.solve_potential(c["poisson_tol"], c["poisson_max_sweeps"])
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    print(f"[bench] warm: warm initial solve {k_warm} sweeps, {t_warm:.2f}s", file=sys.stderr, flush=True)
+    ref = Solver(c)
+    ref.solve_potential(1e-12, c["poisson_max_sweeps"])
+    pr = ref.field("phi")
+    err = lambda s: float(np.linalg.norm(s.field("phi") - pr) / np.linalg.norm(pr))
+    e_cold, e_warm = err(cold), err(w)
+    del ref
+    torch.cuda.empty_cache()
+    # mid-run: the same state stepped with and without the per-step network seed
+    res = {}
+    for name, s in (("previous_step", cold), ("network", w)):
+        if name == "network":
+            s.set_warm_start(net, f)
+        n0 = len(s.sweep_log())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"ms_per_step": round(dt / steps * 1e3, 3),
+                     "sweeps_per_step": round(float(np.mean(s.sweep_log()[n0:])), 2)}
+    return {"workload": f"{nx}x{ny} sessile drop, R0=320, theta=90, R=3, S=1, Ca_E=0.1, seed {seed}, FP64",
+            "coarse_factor": f,
+            "t0": {"cold_sweeps": k_cold, "cold_s": round(t_cold, 3), "warm_sweeps": k_warm,
+                   "warm_s": round(t_warm, 3), "speedup": round(t_cold / t_warm, 2),
+                   "phi_rel_error_cold": e_cold, "phi_rel_error_warm": e_warm},
+            "mid_run": {"steps": steps, **res}}
+
+
 def counters_probe(case, launches=20):
     """Short run for hardware-counter passes (rocprofv3 --pmc): a plain copy kernel of known
     size (the calibration of the byte counters), then `launches` blocked sweep launches per
@@ -250,6 +323,7 @@ def main():
     ap.add_argument("--sweep-block", type=int, default=0,
                     help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--batched-cap", type=int, default=2000,
                     help="potential sweeps cap per solve in the batched comparison")
@@ -287,6 +361,8 @@ def main():
         f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches, args.workload)
         f32["speedup_vs_fp64"] = round(f32["value"] / f64["value"], 3)
         line["forms"] = {"fp32": f32}
+    if not args.no_warm:
+        line.setdefault("forms", {})["warm"] = run_warm()
     if not args.no_batched:
         line.setdefault("forms", {})["batched"] = run_batched(args.batched_steps, 2, args.batched_cap)
     if not args.no_cpu_baseline:

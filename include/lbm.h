@@ -280,6 +280,10 @@ int lbm_nn_seed(lbm_handle* h, int factor, const float* y);
 /* features -> network -> seed, on the handle's stream, using the network's own buffers
    ((nx/f)(ny/f) <= its pixel capacity).  Follow with lbm_solve_potential (or lbm_step). */
 int lbm_warm_start(lbm_handle* h, lbm_nn* nn, int factor);
+/* From now on every lbm_step seeds its potential solve from the network (maps of the new
+   psi and of f_s^n) instead of starting from the previous step's potential; nn = NULL
+   restores the plain method.  The network handle must outlive its use here. */
+int lbm_set_warm_start(lbm_handle* h, lbm_nn* nn, int factor);
 /* Training sample of case c of a batch: its input maps and target (device FP32).  Synchronises. */
 int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t);
 

@@ -45,6 +45,8 @@ struct lbm_handle {
     double last_resid = 0.0;
     int noconv = 0;
     int kprev = 0;            // sweeps of the previous solve (first batch size)
+    lbm_nn* wnn = nullptr;    // warm-start network used before every step's solve (or none)
+    int wfactor = 0;
     Ctl* hctl = nullptr;      // pinned host mirror of the control block
     Ctl* dctl = nullptr;      // device control block
     double* partials = nullptr;
@@ -324,6 +326,19 @@ int one_step(lbm_handle* h) {
     lbm::k_f_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp);
     lbm::k_f_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
     LAUNCHCHK(h);
+    if (h->wnn) {
+        // warm start from the network: maps of the new psi (and f_s^n, as 1/tau_l uses)
+        const int f = h->wfactor, nxc = d.nx / f, nyc = d.ny / f;
+        lbm::k_nn_features<R><<<(nxc * nyc + NT - 1) / NT, NT, 0, st>>>(d, s, sp ^ 1, sp, f, h->wnn->x);
+        LAUNCHCHK(h);
+        int frc = nnapi::forward(h->wnn, h->wnn->x, h->wnn->y, 1, nyc, nxc, st);
+        if (frc) {
+            h->err = h->wnn->err;
+            return frc;
+        }
+        lbm::k_nn_seed<R><<<h->nb, NT, 0, st>>>(d, s, h->lcur, f, h->wnn->y);
+        LAUNCHCHK(h);
+    }
     int rc = run_sweeps<R>(h, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, nullptr, nullptr);
     if (rc == LBM_ENOCONV)
         h->noconv++;
@@ -1220,7 +1235,7 @@ bool coarse_ok(const lbm_handle* h, int f) {
 template <typename R>
 int nn_features(lbm_handle* h, int f, float* x) {
     int nc = (h->dev.nx / f) * (h->dev.ny / f);
-    lbm::k_nn_features<R><<<(nc + NT - 1) / NT, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, f, x);
+    lbm::k_nn_features<R><<<(nc + NT - 1) / NT, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, h->sp, f, x);
     LAUNCHCHK(h);
     return LBM_OK;
 }
@@ -1274,6 +1289,19 @@ int lbm_warm_start(lbm_handle* h, lbm_nn* nnh, int factor) {
         return rc;
     }
     return lbm_nn_seed(h, factor, nnh->y);
+}
+
+int lbm_set_warm_start(lbm_handle* h, lbm_nn* nnh, int factor) {
+    if (!h) return LBM_ESTATE;
+    if (!nnh) {
+        h->wnn = nullptr;
+        h->wfactor = 0;
+        return LBM_OK;
+    }
+    if (!coarse_ok(h, factor) || (int64_t)(h->dev.nx / factor) * (h->dev.ny / factor) > nnh->cap) return LBM_EINVAL;
+    h->wnn = nnh;
+    h->wfactor = factor;
+    return LBM_OK;
 }
 
 int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t) {

@@ -1275,9 +1275,11 @@ __global__ void __launch_bounds__(NT) kb_vl_finalize(const BatchCase<R>* __restr
 // [J f, (J + 1) f); coarse maps are NHWC with the x index fastest.
 
 // Input maps averaged over a cell: clamped psi, ln(sigma / sigma_gas), ln(eps / eps_gas)
-// with sigma and eps mixed by Eq. (1) (0 when the gas permittivity is 0).
+// with sigma and eps mixed by Eq. (1) (0 when the gas permittivity is 0), from psi of buffer
+// psp and f_s of buffer fsp.
 template <typename R>
-__global__ void __launch_bounds__(NT) k_nn_features(Dev d, State<R> s, int sp, int f, float* __restrict__ x) {
+__global__ void __launch_bounds__(NT) k_nn_features(Dev d, State<R> s, int psp, int fsp, int f,
+                                                    float* __restrict__ x) {
     const int nxc = d.nx / f, nyc = d.ny / f;
     const int c = blockIdx.x * NT + threadIdx.x;
     if (c >= nxc * nyc) return;
@@ -1286,7 +1288,7 @@ __global__ void __launch_bounds__(NT) k_nn_features(Dev d, State<R> s, int sp, i
     for (int j = J * f; j < (J + 1) * f; j++)
         for (int i = I * f; i < (I + 1) * f; i++) {
             const int64_t n = at(d, i, j);
-            const double ps = (double)s.psi[sp][n], fs = (double)s.fs[sp][n];
+            const double ps = (double)s.psi[psp][n], fs = (double)s.fs[fsp][n];
             a0 += clamp01(ps);
             a1 += log(mix<double>(d.sig_s, d.sig_l, d.sig_g, ps, fs) / d.sig_g);
             if (d.eps_g > 0.0) a2 += log(mix<double>(d.eps_s, d.eps_l, d.eps_g, ps, fs) / d.eps_g);

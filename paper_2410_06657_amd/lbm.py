@@ -29,7 +29,7 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_nn_param_count", "lbm_nn_workspace_bytes", "lbm_nn_init", "lbm_nn_set_params",
            "lbm_nn_get_params", "lbm_nn_forward", "lbm_nn_gradient", "lbm_nn_train_step",
            "lbm_nn_destroy", "lbm_nn_last_error", "lbm_nn_features", "lbm_nn_target", "lbm_nn_seed",
-           "lbm_warm_start", "lbm_batch_nn_sample"]
+           "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample"]
 
 LBM_TUNE_FORCE = 1
 
@@ -140,6 +140,7 @@ def lib():
         L.lbm_nn_target.argtypes = [vp, C.c_int, vp]
         L.lbm_nn_seed.argtypes = [vp, C.c_int, vp]
         L.lbm_warm_start.argtypes = [vp, vp, C.c_int]
+        L.lbm_set_warm_start.argtypes = [vp, vp, C.c_int]
         L.lbm_batch_nn_sample.argtypes = [vp, C.c_int, C.c_int, vp, vp]
         _lib = L
     return _lib
@@ -322,6 +323,11 @@ class Solver:
     def warm_start(self, net: "Net", factor: int):
         """Features -> network -> seeded potential, on this solver's stream."""
         self._check("lbm_warm_start", lib().lbm_warm_start(self._h, net._h, int(factor)))
+
+    def set_warm_start(self, net, factor: int = 0):
+        """Seed every step's potential solve from `net` (None: the previous step's potential)."""
+        self._warm_net = net  # keep the network alive while the library refers to it
+        self._check("lbm_set_warm_start", lib().lbm_set_warm_start(self._h, net._h if net else None, int(factor)))
 
     def sweep_log(self) -> np.ndarray:
         cnt = C.c_int()
