@@ -173,6 +173,21 @@ int lbm_set_pop(lbm_handle* h, int set, const double* src);
    copies min(count, cap) entries, *count gets the total. */
 int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count);
 
+/* Step until the freezing time is detected (R30: t_fre > 0 after a step) or max_steps steps,
+   testing every check_every steps (so up to check_every - 1 steps may follow the freezing
+   step); *steps_done gets the steps taken.  t_fre itself comes from lbm_diagnostics. */
+int lbm_run_until_frozen(lbm_handle* h, int max_steps, int check_every, int* steps_done);
+
+/* Checkpoint: the whole state of a handle (every plane of the workspace, the control block,
+   buffer indices, step counter and sweep log) as one host image.  With host == NULL only
+   *bytes is set (the image size, which grows with the sweep log); else *bytes must be at
+   least that size (LBM_ESPACE otherwise) and receives it.  Restore takes an image written by
+   a handle of the same grid, precision and launch shape (LBM_EINVAL otherwise) and continues
+   bitwise as the original would have.  Both synchronise the stream; host memory is the
+   caller's. */
+int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes);
+int lbm_restore(lbm_handle* h, const void* host, size_t bytes);
+
 /* Measurement: launch exactly n potential sweeps (Eqs. (31)-(34), the step's inner
    loop, in the launch configuration lbm_step uses: the first workgroup of each launch
    also evaluates the previous launch's residuals, but the loop never stops early) on
@@ -218,6 +233,13 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
                    void* stream, lbm_batch** out);
 /* n time steps of every case. */
 int lbm_batch_step(lbm_batch* b, int n);
+/* Step the batch until every case has frozen (R30) or max_steps steps.  A case stops
+   advancing right after the step in which its freezing time is detected: its workgroups exit
+   at once in every later launch, its state, sweep log and step count stay those of that step
+   (bitwise the single-case run stopped there), and the others continue.  Reads the control
+   blocks after every step; *steps_done gets the batch steps taken. */
+int lbm_batch_run_until_frozen(lbm_batch* b, int max_steps, int* steps_done);
+
 /* FP64 diagnostics of every case into per_case[0..ncases-1]; synchronises. */
 int lbm_batch_diagnostics(lbm_batch* b, lbm_diag* per_case);
 /* One field of case c as nx_c*ny_c FP64 values; synchronises. */

@@ -663,6 +663,113 @@ int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count) {
     return LBM_OK;
 }
 
+// Checkpoint image: header, sweep log, then the used workspace bytes verbatim (every plane,
+// partial sum and the control block are workspace-relative, so a handle of the same
+// parameters can take the image).
+namespace {
+struct CkptHeader {
+    uint64_t magic;
+    int32_t version, nx, ny, precision, sweep_block, sweep_waves;
+    int32_t sp, lcur, kprev, noconv, last_sweeps, nlog;
+    int64_t step;
+    double last_resid;
+    uint64_t ws_bytes;
+};
+constexpr uint64_t CKPT_MAGIC = 0x4c424d434b505431ull;  // "LBMCKPT1"
+
+size_t ckpt_bytes(const lbm_handle* h) {
+    return sizeof(CkptHeader) + sizeof(int32_t) * h->log.size() + carve_bytes(&h->prm, h->dev);
+}
+}  // namespace
+
+int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
+    if (!h) return LBM_ESTATE;
+    if (!bytes) return LBM_EINVAL;
+    size_t need = ckpt_bytes(h);
+    if (!host) {
+        *bytes = need;
+        return LBM_OK;
+    }
+    if (*bytes < need) return LBM_ESPACE;
+    CkptHeader hd{};
+    hd.magic = CKPT_MAGIC;
+    hd.version = 1;
+    hd.nx = h->dev.nx;
+    hd.ny = h->dev.ny;
+    hd.precision = h->prec;
+    hd.sweep_block = h->swm;
+    hd.sweep_waves = h->swv;
+    hd.sp = h->sp;
+    hd.lcur = h->lcur;
+    hd.kprev = h->kprev;
+    hd.noconv = h->noconv;
+    hd.last_sweeps = h->last_sweeps;
+    hd.nlog = (int32_t)h->log.size();
+    hd.step = h->step;
+    hd.last_resid = h->last_resid;
+    hd.ws_bytes = carve_bytes(&h->prm, h->dev);
+    char* out = (char*)host;
+    std::memcpy(out, &hd, sizeof hd);
+    out += sizeof hd;
+    for (int v : h->log) {
+        int32_t w = v;
+        std::memcpy(out, &w, sizeof w);
+        out += sizeof w;
+    }
+    HIPCHK(h, hipMemcpyAsync(out, h->ws, hd.ws_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *bytes = need;
+    return LBM_OK;
+}
+
+int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
+    if (!h) return LBM_ESTATE;
+    if (!host || bytes < sizeof(CkptHeader)) return LBM_EINVAL;
+    CkptHeader hd;
+    std::memcpy(&hd, host, sizeof hd);
+    size_t ws = carve_bytes(&h->prm, h->dev);
+    if (hd.magic != CKPT_MAGIC || hd.version != 1 || hd.nx != h->dev.nx || hd.ny != h->dev.ny ||
+        hd.precision != h->prec || hd.sweep_block != h->swm || hd.sweep_waves != h->swv || hd.ws_bytes != ws ||
+        hd.nlog < 0 || bytes < sizeof hd + sizeof(int32_t) * (size_t)hd.nlog + ws)
+        return LBM_EINVAL;
+    const char* in = (const char*)host + sizeof hd;
+    std::vector<int> log(hd.nlog);
+    for (int k = 0; k < hd.nlog; k++) {
+        int32_t w;
+        std::memcpy(&w, in, sizeof w);
+        in += sizeof w;
+        log[k] = w;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->ws, in, ws, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->sp = hd.sp;
+    h->lcur = hd.lcur;
+    h->kprev = hd.kprev;
+    h->noconv = hd.noconv;
+    h->last_sweeps = hd.last_sweeps;
+    h->step = hd.step;
+    h->last_resid = hd.last_resid;
+    h->log = std::move(log);
+    return fetch_ctl(h);
+}
+
+int lbm_run_until_frozen(lbm_handle* h, int max_steps, int check_every, int* steps_done) {
+    if (!h) return LBM_ESTATE;
+    if (max_steps < 0 || check_every < 1) return LBM_EINVAL;
+    int k = 0;
+    while (k < max_steps) {
+        int rc = fetch_ctl(h);
+        if (rc) return rc;
+        if (h->hctl->t_fre > 0.0) break;
+        int n = std::min(check_every, max_steps - k);
+        rc = lbm_step(h, n);
+        if (rc) return rc;
+        k += n;
+    }
+    if (steps_done) *steps_done = k;
+    return fetch_ctl(h);
+}
+
 int lbm_time_sweeps(lbm_handle* h, int n, float* ms) {
     if (!h) return LBM_ESTATE;
     if (n < 1 || !ms) return LBM_EINVAL;
@@ -823,6 +930,8 @@ struct lbm_batch {
     int node_blocks = 0, sweep_blocks = 0;
     std::vector<int> lcur, kprev;
     std::vector<std::vector<int>> log;
+    std::vector<int> frozen_sp;          // buffer parity of a frozen case's final state (-1: running)
+    std::vector<long long> case_step;    // steps each case has taken
     int sp = 0;
     long long step = 0;
     bool graphs = false;
@@ -963,6 +1072,10 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
     std::vector<lbm::SweepLaunch> fix(nc);
     bool any = false;
     for (int c = 0; c < nc; c++) {
+        if (b->frozen_sp[c] >= 0) {
+            fix[c] = lbm::SweepLaunch{};
+            continue;
+        }
         const Ctl& ct = b->ctl_h[c];
         int f = ct.fix_launch;
         int src = (b->lcur[c] + f) % 3;
@@ -1084,6 +1197,8 @@ int batch_step_impl(lbm_batch* b) {
     if (rc) return rc;
     b->sp ^= 1;
     b->step++;
+    for (int c = 0; c < b->ncases; c++)
+        if (b->frozen_sp[c] < 0) b->case_step[c]++;
     return LBM_OK;
 }
 
@@ -1096,12 +1211,13 @@ int batch_case_handle(lbm_batch* b, int c, lbm_handle* h) {
     h->st<R>() = bcases<R>(b)[c].s;
     h->stream = b->stream;
     h->nb = b->dev[c].gx * b->dev[c].gy;
-    h->sp = b->sp;
+    h->sp = b->frozen_sp[c] >= 0 ? b->frozen_sp[c] : b->sp;
     h->lcur = b->lcur[c];
     h->swm = b->swm;
+    h->swv = b->swv;
     h->dctl = bcases<R>(b)[c].s.ctl;
     h->partials = bcases<R>(b)[c].s.partials;
-    h->step = b->step;
+    h->step = b->case_step[c];
     h->hctl = b->ctl_h + c;
     return LBM_OK;
 }
@@ -1147,6 +1263,8 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
     b->lcur.assign(ncases, 0);
     b->kprev.assign(ncases, 0);
     b->log.assign(ncases, {});
+    b->frozen_sp.assign(ncases, -1);
+    b->case_step.assign(ncases, 0);
     if (hipHostMalloc((void**)&b->ctl_h, sizeof(Ctl) * ncases, hipHostMallocDefault) != hipSuccess) {
         delete b;
         return LBM_EHIP;
@@ -1167,6 +1285,31 @@ int lbm_batch_step(lbm_batch* b, int n) {
         int rc = b->prec == LBM_FP32 ? batch_step_impl<float>(b) : batch_step_impl<double>(b);
         if (rc) return rc;
     }
+    return LBM_OK;
+}
+
+int lbm_batch_run_until_frozen(lbm_batch* b, int max_steps, int* steps_done) {
+    if (!b) return LBM_ESTATE;
+    if (max_steps < 0) return LBM_EINVAL;
+    int k = 0;
+    for (; k < max_steps; k++) {
+        bool all = true;
+        for (int c = 0; c < b->ncases; c++) all = all && b->frozen_sp[c] >= 0;
+        if (all) break;
+        int rc = b->prec == LBM_FP32 ? batch_step_impl<float>(b) : batch_step_impl<double>(b);
+        if (rc) return rc;
+        // freezing detector of every case, after this step's liquid-volume update
+        BHIP(b, hipMemcpyAsync(b->ctl_h, b->ctl_d, sizeof(Ctl) * b->ncases, hipMemcpyDeviceToHost, b->stream));
+        BHIP(b, hipStreamSynchronize(b->stream));
+        for (int c = 0; c < b->ncases; c++) {
+            if (b->frozen_sp[c] >= 0 || !(b->ctl_h[c].t_fre > 0.0)) continue;
+            b->frozen_sp[c] = b->sp;  // its final state is in the buffer just written
+            const int one = 1;
+            BHIP(b, hipMemcpyAsync(&b->ctl_d[c].frozen, &one, sizeof(int), hipMemcpyHostToDevice, b->stream));
+            BHIP(b, hipStreamSynchronize(b->stream));
+        }
+    }
+    if (steps_done) *steps_done = k;
     return LBM_OK;
 }
 

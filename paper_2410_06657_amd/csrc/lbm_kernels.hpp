@@ -65,7 +65,8 @@ struct Dev {
 // no fences or atomics: every block stores its FP64 partial sums, and a later launch (the
 // next sweep's block 0, or a one-block finalize kernel) adds them in block order.
 struct Ctl {
-    int done, count, conv, pad0;     // potential loop: finished, sweeps, converged
+    int done, count, conv;           // potential loop: finished, sweeps, converged
+    int frozen;                      // batched runs to freezing: the case no longer advances
     int fix_launch, fix_n;           // launch holding the final sweep, and its sweeps up to it
     int min_sweeps, max_sweeps;
     double tol, resid;
@@ -77,9 +78,9 @@ struct Ctl {
 };
 
 // Offsets into the partial-sum array (nb = blocks of a node-parallel launch).
-constexpr int SW_MAXM = 8;
+constexpr int SW_MAXM = 8;  // most sweeps one blocked launch performs
 // FP32 potential base moves every REBASE_SWEEPS sweeps of a long solve (multiple of SW_MAXM)
-constexpr int REBASE_SWEEPS = 256;  // most sweeps one blocked launch performs
+constexpr int REBASE_SWEEPS = 256;
 __host__ __device__ constexpr int64_t part_vl(int nb) { return 0; }
 __host__ __device__ constexpr int64_t part_diag(int nb) { return (int64_t)nb; }
 __host__ __device__ constexpr int64_t part_sweep(int nb, int nbt, int slot) {
@@ -1138,6 +1139,7 @@ __device__ __forceinline__ int find_case(const int* __restrict__ first, int ncas
         int b = xcd_tile(blockIdx.x, gridDim.x);                                            \
         int c = find_case(first, ncases, b);                                                \
         const BatchCase<R>& bc = cases[c];                                                  \
+        if (bc.s.ctl->frozen) return;                                                       \
         body<R>(bc.d, bc.s, ##__VA_ARGS__, b - first[c]);                                   \
     }
 
@@ -1162,7 +1164,7 @@ __global__ void __launch_bounds__(NT) kb_rebase_running(const BatchCase<R>* __re
     int b = xcd_tile(blockIdx.x, gridDim.x);
     int c = find_case(first, ncases, b);
     const BatchCase<R>& bc = cases[c];
-    if (bc.s.ctl->done) return;
+    if (bc.s.ctl->done || bc.s.ctl->frozen) return;
     b_rebase<R>(bc.d, bc.s, (lcur0[c] + t) % 3, b - first[c]);
 }
 
@@ -1230,9 +1232,9 @@ __global__ void kb_ctl_reset(const BatchCase<R>* __restrict__ cases, int ncases,
     Ctl* ct = cases[c].s.ctl;
     ct->fix_launch = 0;
     ct->fix_n = 0;
-    ct->done = 0;
+    ct->done = ct->frozen;  // a frozen case takes no part in the loop
     ct->count = 0;
-    ct->conv = 0;
+    ct->conv = ct->frozen;
     ct->resid = 0.0;
     ct->tol = tol[c];
     ct->min_sweeps = min_sweeps;
@@ -1246,6 +1248,7 @@ __global__ void __launch_bounds__(NT) kb_vl_finalize(const BatchCase<R>* __restr
     const BatchCase<R>& bc = cases[blockIdx.x];
     const Dev& d = bc.d;
     Ctl* c = bc.s.ctl;
+    if (c->frozen) return;
     int nb = d.gx * d.gy;
     const double* pv = bc.s.partials + part_vl(nb);
     double a = 0.0;

@@ -29,7 +29,8 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_nn_param_count", "lbm_nn_workspace_bytes", "lbm_nn_init", "lbm_nn_set_params",
            "lbm_nn_get_params", "lbm_nn_forward", "lbm_nn_gradient", "lbm_nn_train_step",
            "lbm_nn_destroy", "lbm_nn_last_error", "lbm_nn_features", "lbm_nn_target", "lbm_nn_seed",
-           "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample"]
+           "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample", "lbm_checkpoint", "lbm_restore",
+           "lbm_run_until_frozen", "lbm_batch_run_until_frozen"]
 
 LBM_TUNE_FORCE = 1
 
@@ -141,6 +142,10 @@ def lib():
         L.lbm_nn_seed.argtypes = [vp, C.c_int, vp]
         L.lbm_warm_start.argtypes = [vp, vp, C.c_int]
         L.lbm_set_warm_start.argtypes = [vp, vp, C.c_int]
+        L.lbm_checkpoint.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.lbm_restore.argtypes = [vp, vp, C.c_size_t]
+        L.lbm_run_until_frozen.argtypes = [vp, C.c_int, C.c_int, ip]
+        L.lbm_batch_run_until_frozen.argtypes = [vp, C.c_int, ip]
         L.lbm_batch_nn_sample.argtypes = [vp, C.c_int, C.c_int, vp, vp]
         _lib = L
     return _lib
@@ -324,6 +329,25 @@ class Solver:
         """Features -> network -> seeded potential, on this solver's stream."""
         self._check("lbm_warm_start", lib().lbm_warm_start(self._h, net._h, int(factor)))
 
+    def run_until_frozen(self, max_steps: int, check_every: int = 1) -> int:
+        """Step until the freezing time is detected; returns the steps taken."""
+        k = C.c_int()
+        self._check("lbm_run_until_frozen", lib().lbm_run_until_frozen(self._h, int(max_steps), int(check_every),
+                                                                       C.byref(k)))
+        return k.value
+
+    def checkpoint(self) -> bytes:
+        """The whole state as one host image (lbm_checkpoint)."""
+        n = C.c_size_t()
+        self._check("lbm_checkpoint", lib().lbm_checkpoint(self._h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        self._check("lbm_checkpoint", lib().lbm_checkpoint(self._h, buf, C.byref(n)))
+        return bytes(buf[:n.value])
+
+    def restore(self, image: bytes):
+        buf = (C.c_char * len(image)).from_buffer_copy(image)
+        self._check("lbm_restore", lib().lbm_restore(self._h, buf, len(image)))
+
     def set_warm_start(self, net, factor: int = 0):
         """Seed every step's potential solve from `net` (None: the previous step's potential)."""
         self._warm_net = net  # keep the network alive while the library refers to it
@@ -398,6 +422,14 @@ class Batch:
         if rc != LBM_OK:
             raise LbmError("lbm_batch_get_field", rc)
         return out
+
+    def run_until_frozen(self, max_steps: int) -> int:
+        """Step until every case has frozen (each stops at its own freezing step)."""
+        k = C.c_int()
+        rc = lib().lbm_batch_run_until_frozen(self._h, int(max_steps), C.byref(k))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_run_until_frozen", rc)
+        return k.value
 
     def nn_sample(self, c: int, factor: int):
         """Input maps and target of case c (torch FP32 on the device)."""

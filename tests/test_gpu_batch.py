@@ -71,3 +71,28 @@ def test_batch_freezing_times():
         assert ds["t_fre"] > 0, c
         assert d[c]["t_fre"] == ds["t_fre"], c
         assert d[c]["V_s"] == ds["V_s"], c
+
+
+def test_batch_run_until_frozen_matches_single_runs():
+    """Cases freezing at different steps: each stops at its own freezing step inside the batch
+    (its workgroups idle from then on) and ends bitwise where its single-case run stops."""
+    from paper_2410_06657_amd.lbm import Batch, Solver
+    cases = [inputs.stefan_strip(4, 24 + 8 * k, h0=8.0 + 2 * k, Ste=0.4 + 0.1 * k, rho_ratio_sl=0.9)
+             for k in range(3)]
+    cases.append(inputs.sessile_drop(64, 32, 10.0, 90.0, 3.0, 1.0, 0.1, 0.5, seed=5))
+    b = Batch(cases, precision="fp64")
+    nb = b.run_until_frozen(5000)
+    d = b.diag()
+    steps = []
+    for c, case in enumerate(cases):
+        s = Solver(case)
+        k = s.run_until_frozen(5000, 1)
+        ds = s.diag()
+        steps.append(k)
+        assert ds["t_fre"] > 0 and d[c]["t_fre"] == ds["t_fre"], c
+        assert d[c]["step"] == ds["step"] == k, c
+        assert list(b.sweep_log(c)) == list(s.sweep_log()), c
+        for name in ("psi", "T", "fs", "phi", "ux"):
+            assert np.array_equal(b.field(c, name), s.field(name)), (c, name)
+    print("freezing steps", steps, "batch steps", nb)
+    assert nb == max(steps) and len(set(steps)) > 1
