@@ -282,6 +282,64 @@ def run_warm(steps=20, seed=6):
             "mid_run": {"steps": steps, **res}}
 
 
+def run_time_to_freeze(nbatch=8, max_steps=100000):
+    """Time to freeze (R30) of the 128 x 64 sessile drop (R0 = 24, theta = 90, R = 3, S = 1,
+    Ca_E = 0.1, Ste = 0.1): FP64, FP32, FP64 with the learned warm start of the initial
+    potential, and `nbatch` seeds (centre jitter) in one FP32 batch against the same seeds one
+    at a time.  Speedups are quoted with the freezing times they reach."""
+    import torch
+
+    from paper_2410_06657_amd import inputs, warm
+    from paper_2410_06657_amd.lbm import Batch, Solver
+
+    def one(case, precision, net=None, factor=0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if net is None:
+            s = Solver(case, precision)
+        else:
+            s = Solver(dict(case, skip_initial_solve=1), precision)
+            s.warm_start(net, factor)
+            s.solve_potential(case["poisson_tol"], case["poisson_max_sweeps"])
+        k = s.run_until_frozen(max_steps, 1)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, s.diag()["t_fre"], k
+
+    c = inputs.cfg1(0)
+    out = {"workload": "128x64 sessile drop, R0=24, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"}
+    t64, f64, k64 = one(c, "fp64")
+    t32, f32, _ = one(c, "fp32")
+    f = warm.factor_for(64)
+    net = warm.load((128 // f) * (64 // f))
+    tw, fw, _ = one(c, "fp64", net, f)
+    out["fp64"] = {"wall_s": round(t64, 3), "t_fre": f64, "steps": k64}
+    out["fp32"] = {"wall_s": round(t32, 3), "t_fre": f32, "t_fre_rel_diff": abs(f32 - f64) / f64,
+                   "speedup_vs_fp64": round(t64 / t32, 3)}
+    out["warm_fp64"] = {"wall_s": round(tw, 3), "t_fre": fw, "t_fre_rel_diff": abs(fw - f64) / f64,
+                        "speedup_vs_fp64": round(t64 / tw, 3)}
+    print(f"[bench] time to freeze: fp64 {t64:.2f}s, fp32 {t32:.2f}s, warm {tw:.2f}s", file=sys.stderr, flush=True)
+    cases = [inputs.cfg1(sd) for sd in range(nbatch)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = Batch(cases, precision="fp32")
+    b.run_until_frozen(max_steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    fb = [d["t_fre"] for d in b.diag()]
+    del b
+    ts, fs = 0.0, []
+    for case in cases:
+        dt, fr, _ = one(case, "fp32")
+        ts += dt
+        fs.append(fr)
+    out["batched_fp32"] = {"cases": nbatch, "wall_s": round(tb, 3), "one_at_a_time_wall_s": round(ts, 3),
+                           "speedup_vs_one_at_a_time": round(ts / tb, 3),
+                           "t_fre_rel_diff_vs_fp64_seed0": abs(fb[0] - f64) / f64,
+                           "t_fre_equal_to_single_runs": fb == fs}
+    print(f"[bench] time to freeze: batch of {nbatch} {tb:.2f}s, one at a time {ts:.2f}s", file=sys.stderr, flush=True)
+    return out
+
+
 def counters_probe(case, launches=20):
     """Short run for hardware-counter passes (rocprofv3 --pmc): a plain copy kernel of known
     size (the calibration of the byte counters), then `launches` blocked sweep launches per
@@ -324,6 +382,7 @@ def main():
                     help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--no-time-to-freeze", action="store_true", help="skip the time-to-freeze runs")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--batched-cap", type=int, default=2000,
                     help="potential sweeps cap per solve in the batched comparison")
@@ -361,6 +420,8 @@ def main():
         f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches, args.workload)
         f32["speedup_vs_fp64"] = round(f32["value"] / f64["value"], 3)
         line["forms"] = {"fp32": f32}
+    if not args.no_time_to_freeze:
+        line["time_to_freeze"] = run_time_to_freeze()
     if not args.no_warm:
         line.setdefault("forms", {})["warm"] = run_warm()
     if not args.no_batched:
