@@ -217,17 +217,17 @@ template <typename R>
 void launch_test(lbm_handle* h, const lbm::SweepLaunch& a) {
     State<R>& s = h->st<R>();
     switch (h->swm) {
-        case 1: lbm::k_sweep_test<1, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
-        case 2: lbm::k_sweep_test<2, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
-        case 4: lbm::k_sweep_test<4, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
-        default: lbm::k_sweep_test<8, R><<<1, NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 1: lbm::k_sweep_test<1, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 2: lbm::k_sweep_test<2, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 4: lbm::k_sweep_test<4, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
+        default: lbm::k_sweep_test<8, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
     }
 }
 
 // Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; block 0 of
 // each launch tests every sweep of the previous launch, and each batch of launches ends
 // with a one-block test of its last launch, after which the host reads the flag.  The
-// first batch covers the previous solve's count less one launch, later batches double
+// first batch covers the previous solve's count plus one launch, later batches double
 // from one launch.  Launches queued after a test ended the loop exit at once.  If the
 // final sweep is not the last of its launch, that launch's sweeps up to it are
 // recomputed from its input (three buffers keep that input intact past the launches
@@ -241,9 +241,11 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     std::vector<lbm::SweepLaunch> plan;
     int next = 1;       // next sweep index
     int buf = h->lcur;  // buffer holding the state before sweep `next`
-    // first batch: the previous solve's count less one launch, at most 256 launches (after
-    // a solve that stopped at its cap the count says little about the next one)
-    int nlaunch = std::min(256, std::max(1, (h->kprev - h->swm) / h->swm));
+    // first batch: enough launches for the previous solve's count and one more, at most 256
+    // (after a solve that stopped at its cap the count says little about the next one);
+    // launches beyond the stopping one exit at once, so one host round trip usually ends
+    // the loop
+    int nlaunch = h->kprev > 0 ? std::min(256, (h->kprev + h->swm - 1) / h->swm + 1) : 1;
     int grow = 1;
     const bool rebasing = std::is_same<R, float>::value;
     for (;;) {
@@ -1011,10 +1013,10 @@ template <typename R>
 void batch_test(lbm_batch* b, int t) {
     auto tb = btable<R>(b);
     switch (b->swm) {
-        case 1: lbm::kb_sweep_test<1, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-        case 2: lbm::kb_sweep_test<2, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-        case 4: lbm::kb_sweep_test<4, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-        default: lbm::kb_sweep_test<8, R><<<b->ncases, NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        case 1: lbm::kb_sweep_test<1, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        case 2: lbm::kb_sweep_test<2, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        case 4: lbm::kb_sweep_test<4, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
+        default: lbm::kb_sweep_test<8, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
     }
 }
 
@@ -1039,11 +1041,11 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
     BHIP(b, hipMemcpyAsync(b->lcur0_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     lbm::kb_ctl_reset<R><<<(nc + 63) / 64, 64, 0, b->stream>>>(btable<R>(b), nc, b->tol_d, min_sweeps, b->maxsw_d);
     BHIP(b, hipGetLastError());
-    int kmin = *std::min_element(b->kprev.begin(), b->kprev.end());
+    int kmax = *std::max_element(b->kprev.begin(), b->kprev.end());
     int maxmax = 0;
     for (auto& p : b->prm) maxmax = std::max(maxmax, p.poisson_max_sweeps);
     int tmax = (maxmax + b->swm - 1) / b->swm;  // launches that reach every case's cap
-    int nlaunch = std::min(256, std::max(1, (kmin - b->swm) / b->swm));
+    int nlaunch = kmax > 0 ? std::min(256, (kmax + b->swm - 1) / b->swm + 1) : 1;
     int grow = 1, t = 0;
     const bool rebasing = std::is_same<R, float>::value;
     const int reb = lbm::REBASE_SWEEPS / b->swm;  // launches between FP32 rebase points

@@ -725,12 +725,14 @@ __global__ void __launch_bounds__(NT) k_rebase(Dev d, State<R> s, int lcur) {
     b_rebase<R>(d, s, lcur, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-// One block: the convergence test of the last launch of a batch (same rule as above).
+// One block: the convergence test of the last launch of a batch (same rule as above), with
+// 1024 threads so the partial sums of every tile are read in few rounds.
+constexpr int TEST_NT = 1024;
 template <int M, typename R>
-__global__ void __launch_bounds__(NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a) {
-    __shared__ double sh[NT / 64 * 2 * M];
+__global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a) {
+    __shared__ double sh[TEST_NT / 64 * 2 * M];
     if (s.ctl->done) return;
-    sweep_test<M, R>(d, s, a, sh);
+    sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
 }
 
 __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) {
@@ -1214,14 +1216,14 @@ __global__ void __launch_bounds__(64 * WV) kb_sweep_fix(const BatchCase<R>* __re
 
 // One block per case: test the case's launch t (the last of a batch).
 template <int M, typename R>
-__global__ void __launch_bounds__(NT) kb_sweep_test(const BatchCase<R>* __restrict__ cases, const int* __restrict__ lcur0,
-                                                    int t) {
-    __shared__ double sh[NT / 64 * 2 * M];
+__global__ void __launch_bounds__(TEST_NT) kb_sweep_test(const BatchCase<R>* __restrict__ cases,
+                                                         const int* __restrict__ lcur0, int t) {
+    __shared__ double sh[TEST_NT / 64 * 2 * M];
     const BatchCase<R>& bc = cases[blockIdx.x];
     if (bc.s.ctl->done) return;
     SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x], t + 1);
     if (a.prev_nsw <= 0) return;
-    sweep_test<M, R>(bc.d, bc.s, a, sh);
+    sweep_test<M, R, TEST_NT / 64>(bc.d, bc.s, a, sh);
 }
 
 template <typename R>
