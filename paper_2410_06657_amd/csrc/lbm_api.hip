@@ -171,6 +171,8 @@ size_t carve(const Dev& d, char* base, State<R>* s) {
     // the deviation bases exist only in the FP32 form
     const bool based = std::is_same<R, float>::value;
     t.lb = based ? c.take<R>(4 * P) : nullptr;
+    t.dl = based ? c.take<R>(4 * P) : nullptr;
+    t.pbp = based ? c.take<R>(P) : nullptr;
     t.hb = based ? c.take<R>(P) : nullptr;
     R** singles[] = {&t.usx, &t.usy, &t.pux, &t.puy, &t.Ax, &t.Ay, &t.oml, &t.S, &t.Fx,
                      &t.Fy, &t.rho, &t.Ftx, &t.Fty, &t.Gx, &t.Gy, &t.omh, &t.fl};
@@ -234,8 +236,10 @@ void launch_test(lbm_handle* h, const lbm::SweepLaunch& a) {
 // that follow it in the batch, which all exit at once).
 template <typename R>
 int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid) {
-    if (std::is_same<R, float>::value)
+    if (std::is_same<R, float>::value) {
         lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
+        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
+    }
     lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
     LAUNCHCHK(h);
     std::vector<lbm::SweepLaunch> plan;
@@ -283,8 +287,10 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
         if (rc) return rc;
         if (h->hctl->done || next > max_sweeps) break;
         // FP32: keep the stored links small during long solves
-        if (rebasing && (next - 1) % lbm::REBASE_SWEEPS == 0)
+        if (rebasing && (next - 1) % lbm::REBASE_SWEEPS == 0) {
             lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), buf);
+            lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
+        }
         nlaunch = grow;
         grow = std::min(grow * 2, 256);
     }
@@ -400,8 +406,10 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
     hipEvent_t a, b;
     HIPCHK(h, hipEventCreate(&a));
     HIPCHK(h, hipEventCreate(&b));
-    if (std::is_same<R, float>::value)
+    if (std::is_same<R, float>::value) {
         lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
+        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
+    }
     lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, -1.0, 1, n);
     HIPCHK(h, hipEventRecord(a, h->stream));
     int buf = h->lcur;
@@ -1036,8 +1044,11 @@ void batch_fix(lbm_batch* b) {
 template <typename R>
 int batch_sweeps(lbm_batch* b, int min_sweeps) {
     int nc = b->ncases;
-    if (std::is_same<R, float>::value)
+    if (std::is_same<R, float>::value) {
         lbm::kb_rebase<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc, b->sp, b->lcur_d);
+        lbm::kb_sweep_prep<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc, b->sp,
+                                                                   b->lcur_d);
+    }
     BHIP(b, hipMemcpyAsync(b->lcur0_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     lbm::kb_ctl_reset<R><<<(nc + 63) / 64, 64, 0, b->stream>>>(btable<R>(b), nc, b->tol_d, min_sweeps, b->maxsw_d);
     BHIP(b, hipGetLastError());
@@ -1065,9 +1076,12 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
             b->err = "potential loops ended without a decision";
             return LBM_EHIP;
         }
-        if (rebasing && t % reb == 0)
+        if (rebasing && t % reb == 0) {
             lbm::kb_rebase_running<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc,
                                                                             b->lcur0_d, t);
+            lbm::kb_sweep_prep<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc, b->sp,
+                                                                       b->lcur_d);
+        }
         nlaunch = grow;
         grow = std::min(grow * 2, 256);
     }

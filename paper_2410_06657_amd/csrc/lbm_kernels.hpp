@@ -296,6 +296,8 @@ struct State {
     R* md[2];
     R* phi[3];         // raw phi
     R* lb;             // 4 base planes of the FP32 potential links (unused in FP64)
+    R* dl;             // FP32: the 4 pulled base increments D of the current bases (see k_sweep_prep)
+    R* pbp;            // FP32: the base potential phi_B = sum b / (1 - w_0)
     R* hb;             // enthalpy base of the FP32 rest link and H (unused in FP64)
     R *usx, *usy, *pux, *puy, *Ax, *Ay, *oml, *S, *Fx, *Fy;
     R *rho, *Ftx, *Fty, *Gx, *Gy, *omh, *fl;
@@ -553,55 +555,23 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
         double accd[M], accp[M];
 #pragma unroll
         for (int m = 0; m < M; m++) accd[m] = accp[m] = 0.0;
-        // FP32 pair storage: with link = b + l and phi_B the base's moment, the collided
-        // link is A(l) + C with A the collision of the remainders on their own moment and
-        // C = b - omega (b - w phi_B) constant within the launch.  A remainder pulled from
-        // node y therefore gains D = C(y) - b(x); at the electrodes the anti-bounce-back
-        // remainder is D - A with D = 2 w phi_wall - C_opp(x) - b(x).  D is formed in FP64
-        // and rounded once (it is a small difference of nearly equal bases).
+        // FP32 pair storage (link = b + l): the sweep works on the remainders l; the pulled
+        // base increments D and phi_B are launch constants prepared by k_sweep_prep
         R D1[SW_NPT], D2[SW_NPT], D3[SW_NPT], D4[SW_NPT];
         if constexpr (based) {
-            __shared__ double cup[WV][64], cdn[WV][64];
-            double C2[SW_NPT], C4[SW_NPT];
-            R B2[SW_NPT], B4[SW_NPT];
 #pragma unroll
             for (int k = 0; k < SW_NPT; k++) {
                 int gj = y0 + k;
-                R b1 = R(0), b2 = R(0), b3 = R(0), b4 = R(0);
                 if (gj >= 0 && gj < d.ny) {
                     int64_t n = at(d, gi, gj);
-                    b1 = s.lb[n];
-                    b2 = s.lb[P + n];
-                    b3 = s.lb[2 * P + n];
-                    b4 = s.lb[3 * P + n];
+                    D1[k] = s.dl[n];
+                    D2[k] = s.dl[P + n];
+                    D3[k] = s.dl[2 * P + n];
+                    D4[k] = s.dl[3 * P + n];
+                    PB[k] = s.pbp[n];
+                } else {
+                    D1[k] = D2[k] = D3[k] = D4[k] = R(0);
                 }
-                double pb = (((double)b1 + (double)b2) + ((double)b3 + (double)b4)) * INV_1MW0;
-                double om = (double)OM[k];
-                double e = LWA * pb;
-                double c1 = (double)b1 - om * ((double)b1 - e);
-                double c3 = (double)b3 - om * ((double)b3 - e);
-                C2[k] = (double)b2 - om * ((double)b2 - e);
-                C4[k] = (double)b4 - om * ((double)b4 - e);
-                D1[k] = R(__shfl_up(c1, 1, 64) - (double)b1);
-                D3[k] = R(__shfl_down(c3, 1, 64) - (double)b3);
-                B2[k] = b2;
-                B4[k] = b4;
-                PB[k] = R(pb);
-            }
-            cup[w][lane] = C2[SW_NPT - 1];
-            cdn[w][lane] = C4[0];
-            __syncthreads();
-            double cbelow = w > 0 ? cup[w - 1][lane] : 0.0;
-            double cabove = w < WV - 1 ? cdn[w + 1][lane] : 0.0;
-#pragma unroll
-            for (int k = 0; k < SW_NPT; k++) {
-                int gj = y0 + k;
-                double c2n = k > 0 ? C2[k - 1] : cbelow;
-                double c4n = k < SW_NPT - 1 ? C4[k + 1] : cabove;
-                if (gj == 0) c2n = 2.0 * LWA * d.phi_bot - C4[k];
-                if (gj == d.ny - 1) c4n = 2.0 * LWA * d.phi_top - C2[k];
-                D2[k] = R(c2n - (double)B2[k]);
-                D4[k] = R(c4n - (double)B4[k]);
             }
         }
         const R wbot0 = R(2.0 * LWA * d.phi_bot), wtop0 = R(2.0 * LWA * d.phi_top);
@@ -704,6 +674,7 @@ __global__ void __launch_bounds__(64 * WV) k_sweep_tb(Dev d, State<R> s, SweepLa
 template <typename R>
 __device__ __forceinline__ void b_rebase(const Dev& d, const State<R>& s, int lcur, int tile) {
 #pragma clang fp contract(off)
+    if constexpr (!std::is_same<R, float>::value) return;  // FP64 keeps no bases
     int i, j;
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
@@ -723,6 +694,45 @@ __device__ __forceinline__ void b_rebase(const Dev& d, const State<R>& s, int lc
 template <typename R>
 __global__ void __launch_bounds__(NT) k_rebase(Dev d, State<R> s, int lcur) {
     b_rebase<R>(d, s, lcur, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// FP32 form, after every renormalisation and with the solve's 1/tau_l: the launch constants
+// of the sweeps.  With link = b + l and phi_B the bases' moment, the collided link is
+// A(l) + C with A the collision of the remainders on their own moment and
+// C = b - omega (b - w phi_B); a remainder pulled from node y therefore gains
+// D = C(y) - b(x), and at an electrode the anti-bounce-back remainder is D - A with
+// D = 2 w phi_wall - C_opp(x) - b(x).  D is formed in FP64 and rounded once (a small
+// difference of nearly equal bases).
+template <typename R>
+__device__ __forceinline__ void b_sweep_prep(const Dev& d, const State<R>& s, int tile) {
+    if constexpr (!std::is_same<R, float>::value) return;  // FP64 keeps no bases
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    const int64_t P = d.plane;
+    auto cq = [&](int q, int ii, int jj) -> double {  // C of link q at node (ii, jj)
+        const int64_t m = at(d, ii, jj);
+        const double b1 = s.lb[m], b2 = s.lb[P + m], b3 = s.lb[2 * P + m], b4 = s.lb[3 * P + m];
+        const double pb = ((b1 + b2) + (b3 + b4)) * INV_1MW0;
+        const double om = (double)s.oml[m];
+        const double bq = q == 1 ? b1 : q == 2 ? b2 : q == 3 ? b3 : b4;
+        return bq - om * (bq - LWA * pb);
+    };
+    const int64_t n = at(d, i, j);
+    const double b1 = s.lb[n], b2 = s.lb[P + n], b3 = s.lb[2 * P + n], b4 = s.lb[3 * P + n];
+    const double d1 = cq(1, wrapx(i - 1, d.nx), j) - b1;
+    const double d3 = cq(3, wrapx(i + 1, d.nx), j) - b3;
+    const double d2 = (j == 0 ? 2.0 * LWA * d.phi_bot - cq(4, i, j) : cq(2, i, j - 1)) - b2;
+    const double d4 = (j == d.ny - 1 ? 2.0 * LWA * d.phi_top - cq(2, i, j) : cq(4, i, j + 1)) - b4;
+    s.dl[n] = R(d1);
+    s.dl[P + n] = R(d2);
+    s.dl[2 * P + n] = R(d3);
+    s.dl[3 * P + n] = R(d4);
+    s.pbp[n] = R(((b1 + b2) + (b3 + b4)) * INV_1MW0);
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s) {
+    b_sweep_prep<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // One block: the convergence test of the last launch of a batch (same rule as above), with
@@ -1150,6 +1160,7 @@ LBM_BATCHED(kb_oml, b_oml, sp)
 LBM_BATCHED(kb_f_prep, b_f_prep, sp)
 LBM_BATCHED(kb_f_stream, b_f_stream, sp)
 LBM_BATCHED(kb_rebase, b_rebase, lcur[c])
+LBM_BATCHED(kb_sweep_prep, b_sweep_prep)
 LBM_BATCHED(kb_h_prep1, b_h_prep1, sp, lcur[c])
 LBM_BATCHED(kb_h_prep2, b_h_prep2, sp)
 LBM_BATCHED(kb_h_stream, b_h_stream, sp)

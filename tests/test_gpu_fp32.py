@@ -50,15 +50,21 @@ def perturbed(solver, seed=1):
         solver.set_pop(k, p * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, p.shape)))
 
 
+# independently rounded FP32 state sets per step: the f, h and g populations and the potential
+# links each carry one unit roundoff of their own into the next step
+ROUNDINGS = 4
+
+
 def test_fp32_thousand_steps_cfg1():
     """The 128 x 64 sessile drop, 1000 steps, FP32 against the FP64 oracle.
 
     The coupled freezing problem amplifies perturbations: the FP64 method itself, restarted
     from a state perturbed once by one FP32 unit roundoff, departs from the unperturbed run by
     G(m) after m steps (measured here on the GPU FP64 path, which equals the oracle to 1e-12).
-    FP32 arithmetic injects such a perturbation every step, so after n steps its error is
-    bounded by its direct rounding (2e-5 covers it: the first 20 steps are held to that) plus
-    the sum of the responses, n * max_{m <= n} G(m); that bound is the test."""
+    FP32 arithmetic injects such perturbations every step, one per independently rounded
+    state set (f, h, g, the potential links: 4), so after n steps its error is bounded by its
+    direct rounding (2e-5 covers it: the first 20 steps are held to that) plus the sum of the
+    responses, 4 n max_{m <= n} G(m); that bound is the test."""
     from paper_2410_06657_amd.lbm import Solver
     c = inputs.cfg1(0)
     g, o = solver32(c), ob.Oracle(c)
@@ -76,7 +82,7 @@ def test_fp32_thousand_steps_cfg1():
         sens = max(rel_l2(b.field(k), a.field(k)) for k in FIELDS)
         gmax = max(gmax, sens)
         worst = max(e.values())
-        bound = TOL32 + n * gmax
+        bound = TOL32 + ROUNDINGS * n * gmax
         print(f"step {n}: fp32 error {worst:.2e}, one-roundoff response {sens:.2e}, bound {bound:.2e}",
               flush=True)
         if n <= 20:
