@@ -160,6 +160,30 @@ __device__ __forceinline__ void node_of(const Dev& d, int t, int& i, int& j) {
     j = by * TY + (threadIdx.x / TX);
 }
 
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Wave-wide lane shifts by one lane on the VALU (DPP wave_shr / wave_shl): lane_up gives lane
+// i the value of lane i - 1, lane_down the value of lane i + 1 (the lane at the end gets 0).
+__device__ __forceinline__ float lane_up(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_down(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_up(double x) {
+    const long long v = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x138, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_down(double x) {
+    const long long v = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Sum over the block in a fixed order; the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -515,8 +539,8 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
 
 template <int M, typename R, int WV>
 __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& a, int tile) {
-    // every product is rounded on its own, so the result does not depend on how the
-    // compiler unrolls the M sweeps (bitwise equal for every M)
+    // no implicit contraction: the fused operations are written out, so the result does not
+    // depend on how the compiler unrolls the M sweeps (bitwise equal for every launch shape)
 #pragma clang fp contract(off)
     __shared__ R bup[2][WV][64], bdn[2][WV][64];
     __shared__ double sh[WV * 2 * M];
@@ -584,10 +608,12 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                 R ph = (L1[k] + L2[k] + L3[k] + L4[k]) * inv;
                 PH[k] = ph;
                 R e = lw * ph;
-                A1[k] = L1[k] - OM[k] * (L1[k] - e);
-                A2[k] = L2[k] - OM[k] * (L2[k] - e);
-                A3[k] = L3[k] - OM[k] * (L3[k] - e);
-                A4[k] = L4[k] - OM[k] * (L4[k] - e);
+                // l - omega (l - e) as one fused multiply-add (explicit, so every launch shape
+                // rounds it the same way)
+                A1[k] = fma_r(-OM[k], L1[k] - e, L1[k]);
+                A2[k] = fma_r(-OM[k], L2[k] - e, L2[k]);
+                A3[k] = fma_r(-OM[k], L3[k] - e, L3[k]);
+                A4[k] = fma_r(-OM[k], L4[k] - e, L4[k]);
             }
             int par = m & 1;
             bup[par][w][lane] = A2[SW_NPT - 1];
@@ -598,8 +624,8 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
 #pragma unroll
             for (int k = 0; k < SW_NPT; k++) {
                 int gj = y0 + k;
-                R n1 = __shfl_up(A1[k], 1, 64);
-                R n3 = __shfl_down(A3[k], 1, 64);
+                R n1 = lane_up(A1[k]);
+                R n3 = lane_down(A3[k]);
                 R n2 = k > 0 ? A2[k - 1] : below;
                 R n4 = k < SW_NPT - 1 ? A4[k + 1] : above;
                 if constexpr (based) {
@@ -620,8 +646,8 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                     R ph = (n1 + n2 + n3 + n4) * inv;
                     double dd = (double)(ph - PH[k]);
                     double pr = based ? (double)ph + (double)PB[k] : (double)ph;
-                    accd[m] += dd * dd;
-                    accp[m] += pr * pr;
+                    accd[m] = __builtin_fma(dd, dd, accd[m]);
+                    accp[m] = __builtin_fma(pr, pr, accp[m]);
                 }
             }
         }
