@@ -342,8 +342,8 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
 
 def counters_probe(case, launches=20):
     """Short run for hardware-counter passes (rocprofv3 --pmc): a plain copy kernel of known
-    size (the calibration of the byte counters), then `launches` blocked sweep launches per
-    precision on the workload's grid.  The initial potential solve is capped at 16 sweeps so
+    size (the calibration of the byte counters), then `launches` blocked sweep launches and
+    three steps per precision on the workload's grid.  The initial potential solve is capped at 16 sweeps so
     the run stays short; a launch's memory traffic does not depend on convergence."""
     import torch
 
@@ -362,8 +362,9 @@ def counters_probe(case, launches=20):
     for precision in ("fp64", "fp32"):
         s = Solver(c, precision=precision)
         s.time_sweeps(launches * m)
+        s.step(3)  # the stage kernels of a step (with 16-sweep solves)
         torch.cuda.synchronize()
-        print(f"[counters] {precision}: {launches} launches of {m} sweeps on {c['nx']}x{c['ny']}",
+        print(f"[counters] {precision}: {launches} launches of {m} sweeps and 3 steps on {c['nx']}x{c['ny']}",
               file=sys.stderr, flush=True)
         del s
 
