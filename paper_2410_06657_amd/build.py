@@ -8,6 +8,9 @@ LIB = os.path.join(HERE, "liblbm.so")
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no implicit fused multiply-adds: every instantiation of a stage body (single case,
+    # batched) rounds identically; the kernels write the fused operations they want
+    "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

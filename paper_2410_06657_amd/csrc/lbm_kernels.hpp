@@ -163,6 +163,28 @@ __device__ __forceinline__ void node_of(const Dev& d, int t, int& i, int& j) {
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Neighbourhood staging for the streaming kernels: the collision inputs of a node tile
+// (TX x TY) and of the one-node ring around it, gathered once into LDS so the nine pulls of a
+// node read them there.  Slot (r, c) holds node (i0 - 1 + c, j0 - 1 + r) of the tile with
+// origin (i0, j0), x wrapped (periodic); rows outside the grid stay unset (the pulls that
+// would read them take the wall conditions instead).  Every thread of the block takes part.
+constexpr int RX = TX + 2, RY = TY + 2, RN = RX * RY;
+template <typename T, typename F>
+__device__ __forceinline__ void stage_ring(const Dev& d, int tile, T* ring, F&& load) {
+    const int i0 = (tile % d.gx) * TX - 1, j0 = (tile / d.gx) * TY - 1;
+    for (int k = threadIdx.x; k < RN; k += NT) {
+        const int gj = j0 + k / RX;
+        if (gj < 0 || gj >= d.ny) continue;
+        int gi = (i0 + k % RX) % d.nx;
+        if (gi < 0) gi += d.nx;
+        ring[k] = load(at(d, gi, gj));
+    }
+    __syncthreads();
+}
+// Slot of this thread's node, and of its neighbour (i - cx, j - cy).
+__device__ __forceinline__ int ring_self() { return (threadIdx.x / TX + 1) * RX + (threadIdx.x & (TX - 1)) + 1; }
+__device__ __forceinline__ int ring_from(int self, int cx, int cy) { return self - cy * RX - cx; }
+
 // Wave-wide lane shifts by one lane on the VALU (DPP wave_shr / wave_shl): lane_up gives lane
 // i the value of lane i - 1, lane_down the value of lane i + 1 (the lane at the end gets 0).
 __device__ __forceinline__ float lane_up(float x) {
@@ -243,6 +265,11 @@ __device__ __forceinline__ R coll_f(int q, R fq, R psi, R ux, R uy, R Ax, R Ay, 
     R F = R(QW[q]) * (R(3) * (R(QX[q]) * Ax + R(QY[q]) * Ay) + psi * md);
     return fq - R(d.omf) * (fq - feq) + R(d.facf) * F;
 }
+
+template <typename R>
+struct FIn {
+    R psi, ux, uy, Ax, Ay, md;
+};
 
 // Flow, Eqs. (21)-(24).  (Ftx, Fty) = F~, (Gx, Gy) = F + rho f_solid.
 template <typename R>
@@ -425,16 +452,19 @@ __global__ void __launch_bounds__(NT) k_f_prep(Dev d, State<R> s, int sp) {
 // walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.
 template <typename R>
 __device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int sp, int tile) {
+    __shared__ FIn<R> ring[RN];
+    const R* psi = s.psi[sp];
+    const R* ux = s.ux[sp];
+    const R* uy = s.uy[sp];
+    const R* md = s.md[sp];
+    stage_ring(d, tile, ring, [&](int64_t m) { return FIn<R>{psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m]}; });
     int i, j;
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
     const R* fsrc = s.f[sp];
     R* fdst = s.f[sp ^ 1];
-    const R* psi = s.psi[sp];
-    const R* ux = s.ux[sp];
-    const R* uy = s.uy[sp];
-    const R* md = s.md[sp];
+    const int me = ring_self();
     R sum = R(0);
 #pragma unroll
     for (int q = 0; q < 9; q++) {
@@ -442,10 +472,12 @@ __device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int 
         R val;
         if (jj < 0 || jj >= d.ny) {
             int o = QOPP[q];
-            val = coll_f<R>(o, fsrc[o * d.plane + n], psi[n], ux[n], uy[n], s.Ax[n], s.Ay[n], md[n], d);
+            const FIn<R>& a = ring[me];
+            val = coll_f<R>(o, fsrc[o * d.plane + n], a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
         } else {
             int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            val = coll_f<R>(q, fsrc[q * d.plane + m], psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m], d);
+            const FIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
+            val = coll_f<R>(q, fsrc[q * d.plane + m], a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
         }
         fdst[q * d.plane + n] = val;
         sum += val;
@@ -882,13 +914,16 @@ __device__ __forceinline__ HIn<R> h_inputs(const State<R>& s, int sp, int64_t m)
 // u* (Eq. (25)), u (Eq. (26) with u_s = 0), p (Eq. (27)).
 template <typename R>
 __device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int sp, int tile) {
+    __shared__ HIn<R> ring[RN];
+    stage_ring(d, tile, ring, [&](int64_t m) { return h_inputs<R>(s, sp, m); });
     int i, j;
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
     const R* hsrc = s.h[sp];
     R* hdst = s.h[sp ^ 1];
-    HIn<R> self = h_inputs<R>(s, sp, n);
+    const int me = ring_self();
+    const HIn<R> self = ring[me];
     R sx = R(0), sy = R(0), s0 = R(0);
 #pragma unroll
     for (int q = 0; q < 9; q++) {
@@ -899,7 +934,7 @@ __device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int 
             val = coll_h<R>(o, hsrc[o * d.plane + n], self);
         } else {
             int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            val = coll_h<R>(q, hsrc[q * d.plane + m], h_inputs<R>(s, sp, m));
+            val = coll_h<R>(q, hsrc[q * d.plane + m], ring[ring_from(me, QX[q], QY[q])]);
         }
         hdst[q * d.plane + n] = val;
         sx += R(QX[q]) * val;
@@ -943,6 +978,8 @@ __device__ __forceinline__ GIn<R> g_inputs(const Dev& d, const State<R>& s, int 
 // and mdot.  Per-block FP64 liquid volume for the freezing-time detector.
 template <typename R>
 __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int sp, int tile) {
+    __shared__ GIn<R> ring[RN];
+    stage_ring(d, tile, ring, [&](int64_t m) { return g_inputs<R>(d, s, sp, m); });
     int i, j;
     node_of(d, tile, i, j);
     double vl = 0.0;
@@ -951,7 +988,8 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
         const R* gsrc = s.g[sp];
         R* gdst = s.g[sp ^ 1];
         const R Cref = R(d.Cref);
-        GIn<R> self = g_inputs<R>(d, s, sp, n);
+        const int me = ring_self();
+        const GIn<R> self = ring[me];
         R sum = R(0), g0 = R(0);
 #pragma unroll
         for (int q = 0; q < 9; q++) {
@@ -964,7 +1002,7 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
                 val = coll_g<R>(o, gsrc[o * d.plane + n], self, Cref);
             } else {
                 int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-                val = coll_g<R>(q, gsrc[q * d.plane + m], g_inputs<R>(d, s, sp, m), Cref);
+                val = coll_g<R>(q, gsrc[q * d.plane + m], ring[ring_from(me, QX[q], QY[q])], Cref);
             }
             if (q == 0) g0 = val;
             gdst[q * d.plane + n] = val;
