@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -48,6 +49,9 @@ struct lbm_handle {
     lbm_nn* wnn = nullptr;    // warm-start network used before every step's solve (or none)
     int wfactor = 0;
     Ctl* hctl = nullptr;      // pinned host mirror of the control block
+    unsigned long long* hword = nullptr;  // pinned coherent words the loop test publishes to
+    unsigned seq = 0;         // sequence number of the last published test
+    bool resid_stale = false; // last_resid not yet read back from the control block
     Ctl* dctl = nullptr;      // device control block
     double* partials = nullptr;
     std::string err;
@@ -203,6 +207,10 @@ __global__ void k_ctl_zero(Ctl* c) { *c = Ctl{}; }
 int fetch_ctl(lbm_handle* h) {
     HIPCHK(h, hipMemcpyAsync(h->hctl, h->dctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->resid_stale) {
+        h->last_resid = h->hctl->resid;
+        h->resid_stale = false;
+    }
     return LBM_OK;
 }
 
@@ -216,14 +224,48 @@ void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
 }
 
 template <typename R>
-void launch_test(lbm_handle* h, const lbm::SweepLaunch& a) {
+void launch_test(lbm_handle* h, const lbm::SweepLaunch& a, unsigned seq) {
     State<R>& s = h->st<R>();
+    unsigned long long* w = h->hword;
     switch (h->swm) {
-        case 1: lbm::k_sweep_test<1, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
-        case 2: lbm::k_sweep_test<2, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
-        case 4: lbm::k_sweep_test<4, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
-        default: lbm::k_sweep_test<8, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a); break;
+        case 1: lbm::k_sweep_test<1, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
+        case 2: lbm::k_sweep_test<2, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
+        case 4: lbm::k_sweep_test<4, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
+        default: lbm::k_sweep_test<8, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
     }
+}
+
+// Outcome of a loop test as published by k_sweep_test.
+struct LoopState {
+    int done, conv, count, fix_launch, fix_n;
+};
+
+// Wait for the test with sequence number `seq`: spin on the two published words (the GPU
+// keeps running the queued work meanwhile); after 2 s without them, synchronise the stream
+// (which reports a failed launch) and look once more.
+int wait_test(lbm_handle* h, unsigned seq, LoopState* out) {
+    auto ready = [&](unsigned long long& w0, unsigned long long& w1) {
+        w0 = __atomic_load_n(&h->hword[0], __ATOMIC_ACQUIRE);
+        w1 = __atomic_load_n(&h->hword[1], __ATOMIC_ACQUIRE);
+        return (unsigned)(w0 >> 32) == seq && (unsigned)(w1 >> 32) == seq;
+    };
+    unsigned long long w0 = 0, w1 = 0;
+    auto t0 = std::chrono::steady_clock::now();
+    while (!ready(w0, w1)) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            if (ready(w0, w1)) break;
+            h->err = "potential loop test was not published";
+            return LBM_EHIP;
+        }
+    }
+    out->count = (int)(unsigned)w0;
+    const unsigned b = (unsigned)w1;
+    out->done = b & 1u;
+    out->conv = (b >> 1) & 1u;
+    out->fix_n = (b >> 2) & 15u;
+    out->fix_launch = (int)(b >> 6);
+    return LBM_OK;
 }
 
 // Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; block 0 of
@@ -243,6 +285,7 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
     LAUNCHCHK(h);
     std::vector<lbm::SweepLaunch> plan;
+    LoopState ls{};
     int next = 1;       // next sweep index
     int buf = h->lcur;  // buffer holding the state before sweep `next`
     // first batch: enough launches for the previous solve's count and one more, at most 256
@@ -281,11 +324,12 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
         tst.prev_nsw = last.nsw;
         tst.prev_slot = last.slot;
         tst.launch = (int)plan.size();
-        launch_test<R>(h, tst);
+        const unsigned seq = ++h->seq;
+        launch_test<R>(h, tst, seq);
         LAUNCHCHK(h);
-        int rc = fetch_ctl(h);
+        int rc = wait_test(h, seq, &ls);
         if (rc) return rc;
-        if (h->hctl->done || next > max_sweeps) break;
+        if (ls.done || next > max_sweeps) break;
         // FP32: keep the stored links small during long solves
         if (rebasing && (next - 1) % lbm::REBASE_SWEEPS == 0) {
             lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), buf);
@@ -294,18 +338,18 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
         nlaunch = grow;
         grow = std::min(grow * 2, 256);
     }
-    if (!h->hctl->done) {
+    if (!ls.done) {
         h->err = "potential loop ended without a decision";
         return LBM_EHIP;
     }
-    int k = h->hctl->count;
-    const lbm::SweepLaunch& f = plan[h->hctl->fix_launch];
+    int k = ls.count;
+    const lbm::SweepLaunch& f = plan[ls.fix_launch];
     int final_buf = f.dst;
-    if (h->hctl->fix_n != f.nsw) {
+    if (ls.fix_n != f.nsw) {
         lbm::SweepLaunch a{};
         a.src = f.src;
         a.dst = (f.src + 2) % 3;
-        a.nsw = h->hctl->fix_n;
+        a.nsw = ls.fix_n;
         a.k0 = f.k0;
         a.slot = (int)plan.size() & 1;
         a.launch = (int)plan.size();
@@ -317,11 +361,15 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     h->lcur = final_buf;
     h->kprev = k;
     h->last_sweeps = k;
-    h->last_resid = h->hctl->resid;
+    h->resid_stale = true;  // the final residual stays on the device until someone asks
     h->log.push_back(k);
     if (sweeps) *sweeps = k;
-    if (resid) *resid = h->hctl->resid;
-    if (tol >= 0 && !h->hctl->conv) return LBM_ENOCONV;
+    if (resid) {
+        int rc = fetch_ctl(h);
+        if (rc) return rc;
+        *resid = h->hctl->resid;
+    }
+    if (tol >= 0 && !ls.conv) return LBM_ENOCONV;
     return LBM_OK;
 }
 
@@ -584,7 +632,13 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
         h->dctl = h->sd.ctl;
         h->partials = h->sd.partials;
     }
+    if (hipHostMalloc((void**)&h->hword, 2 * sizeof(unsigned long long), hipHostMallocCoherent) != hipSuccess) {
+        delete h;
+        return LBM_EHIP;
+    }
+    h->hword[0] = h->hword[1] = 0;
     if (hipHostMalloc((void**)&h->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(h->hword);
         delete h;
         return LBM_EHIP;
     }
@@ -695,6 +749,10 @@ size_t ckpt_bytes(const lbm_handle* h) {
 int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
     if (!h) return LBM_ESTATE;
     if (!bytes) return LBM_EINVAL;
+    if (h->resid_stale) {
+        int rc = fetch_ctl(h);
+        if (rc) return rc;
+    }
     size_t need = ckpt_bytes(h);
     if (!host) {
         *bytes = need;
@@ -759,6 +817,7 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
     h->last_sweeps = hd.last_sweeps;
     h->step = hd.step;
     h->last_resid = hd.last_resid;
+    h->resid_stale = false;
     h->log = std::move(log);
     return fetch_ctl(h);
 }
@@ -790,6 +849,7 @@ int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;
     (void)hipStreamSynchronize(h->stream);
     if (h->hctl) (void)hipHostFree(h->hctl);
+    if (h->hword) (void)hipHostFree(h->hword);
     delete h;
     return LBM_OK;
 }

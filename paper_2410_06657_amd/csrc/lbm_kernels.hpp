@@ -796,11 +796,23 @@ __global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s) {
 // One block: the convergence test of the last launch of a batch (same rule as above), with
 // 1024 threads so the partial sums of every tile are read in few rounds.
 constexpr int TEST_NT = 1024;
+// The outcome is published to host memory the caller polls: two 64-bit words, each carrying
+// the sequence number `seq` in its upper half (the host waits for both), written with
+// system-scope atomic stores: word 0 = count, word 1 = fix_launch << 6 | fix_n << 2 |
+// conv << 1 | done.
 template <int M, typename R>
-__global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a) {
+__global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a,
+                                                        unsigned long long* word, unsigned seq) {
     __shared__ double sh[TEST_NT / 64 * 2 * M];
-    if (s.ctl->done) return;
-    sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
+    if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
+    if (threadIdx.x != 0) return;
+    const Ctl* c = s.ctl;
+    const unsigned long long hi = (unsigned long long)seq << 32;
+    const unsigned long long w0 = hi | (unsigned)c->count;
+    const unsigned long long w1 = hi | ((unsigned)c->fix_launch << 6 | (unsigned)c->fix_n << 2 |
+                                        (unsigned)c->conv << 1 | (unsigned)c->done);
+    __hip_atomic_store(&word[0], w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&word[1], w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) {
