@@ -1023,7 +1023,7 @@ int batch_validate(int ncases, const lbm_params* cases) {
         int rc = validate(&cases[c]);
         if (rc) return rc;
         if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]) ||
-            sweep_w(&cases[c]) != sweep_w(&cases[0]))
+            sweep_w(&cases[c]) != sweep_w(&cases[0]) || cases[c].skip_initial_solve)
             return LBM_EINVAL;
     }
     return LBM_OK;

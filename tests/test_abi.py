@@ -64,3 +64,16 @@ def test_error_strings(liblbm):
     # calls on a null handle report a state error instead of crashing
     assert L.lbm_step(None, 1) == liblbm.LBM_ESTATE
     assert L.lbm_destroy(None) == 0
+
+
+def test_batch_validation(liblbm):
+    import ctypes as C
+    from paper_2410_06657_amd import inputs
+    a = inputs.cfg1(0)
+    for bad in ([a, dict(a, skip_initial_solve=1)], [a, dict(a, sweep_block=4)], [a, dict(a, sweep_waves=8)]):
+        arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in bad])
+        n = C.c_size_t()
+        assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_EINVAL
+    arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in (a, inputs.scaled(a, 64, 32))])
+    n = C.c_size_t()
+    assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_OK and n.value > 0

@@ -63,3 +63,22 @@ def test_warm_start_before_every_step():
     b.set_warm_start(None)
     b.step(2)
     assert b.sweep_log()[-1] < kb.min()
+
+
+def test_warm_start_fp32():
+    """The FP32 form takes the seed as base/remainder link pairs and gains the same way."""
+    from paper_2410_06657_amd import warm
+    from paper_2410_06657_amd.lbm import Solver
+    nx, ny = 512, 256
+    f = warm.factor_for(ny)
+    net = warm.load((nx // f) * (ny // f))
+    c = inputs.sessile_drop(nx, ny, 0.3125 * ny, 90.0, 3.0, 1.0, 0.1, 0.1, seed=79)
+    c.update(poisson_max_sweeps=CAP)
+    cold = Solver(c, "fp32")
+    kc = int(cold.sweep_log()[0])
+    w = Solver(dict(c, skip_initial_solve=1), "fp32")
+    w.warm_start(net, f)
+    rc, kw, _ = w.solve_potential(c["poisson_tol"], CAP)
+    e = rel(w.field("phi"), cold.field("phi"))
+    print(f"fp32: cold {kc} sweeps, warm {kw} sweeps, phi difference {e:.2e}")
+    assert rc == 0 and kw <= 0.6 * kc and e <= 1e-3
