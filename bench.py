@@ -23,6 +23,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # populations and 13 + 13 fields (80 s)
 SWEEP_ELEMS, STEP_ELEMS = 11, 80
 ELEM = {"fp64": 8, "fp32": 4}
+# compulsory HBM bytes per node of one blocked launch (read once, written once, whatever the
+# number of sweeps): FP64 reads 4 links and 1/tau_l and writes 4 links and phi; FP32 reads 4
+# link remainders, 1/tau_l, the 4 pulled base increments and phi_B and writes 4 remainders and phi
+SWEEP_COMPULSORY = {"fp64": 10 * 8, "fp32": 15 * 4}
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_cfg2_counters.md")
@@ -151,7 +155,7 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name="cfg2
                 "kernel": f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>",
                 "avg_launch_us": round(launch_s * 1e6, 3), "sweeps_per_launch": m,
                 "algorithmic_bytes_per_launch": per_launch,
-                "compulsory_hbm_bytes_per_launch": SWEEP_ELEMS * es * n}
+                "compulsory_hbm_bytes_per_launch": SWEEP_COMPULSORY[precision] * n}
     coupled_bytes = (STEP_ELEMS + SWEEP_ELEMS * kmean) * es * n
     coupled_gbs = coupled_bytes / (ms_step * 1e-3) / 1e9
     return {
