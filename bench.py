@@ -9,6 +9,7 @@ timed on a bounded sample of the same workload.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -227,11 +228,23 @@ def run_batched(steps, warmup, cap, seed=4, ncases=96):
                         "Ca_E~U[0,0.4], theta~U[45,135], R~logU[0.3,5], S~logU[0.5,3], Ste=0.1, seed 4"}
 
 
+def finite_or_null(v):
+    """The result line as strict JSON: a non-finite float becomes null."""
+    if isinstance(v, dict):
+        return {k: finite_or_null(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [finite_or_null(x) for x in v]
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    return v
+
+
 def run_warm(steps=20, seed=6):
     """Learned warm start on the 2048 x 1024 grid (R0 = 320, theta = 90, R = 3, S = 1,
     Ca_E = 0.1): the initial potential solve from the linear ramp
-    (cold) against network seed + the same sweeps (warm), both to 1e-8, and the potential
-    error of each against a solve to 1e-12; then `steps` steps with every solve started from
+    (cold) against network seed + the same sweeps (warm), both to 1e-8, and the relative L2
+    difference of the two potentials (the stopping rule's accuracy: both stop at the same
+    relative change, from different sides); then `steps` steps with every solve started from
     the previous step's potential against every solve seeded by the network."""
     import numpy as np
     import torch
@@ -258,13 +271,8 @@ def run_warm(steps=20, seed=6):
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     print(f"[bench] warm: warm initial solve {k_warm} sweeps, {t_warm:.2f}s", file=sys.stderr, flush=True)
-    ref = Solver(c)
-    ref.solve_potential(1e-12, c["poisson_max_sweeps"])
-    pr = ref.field("phi")
-    err = lambda s: float(np.linalg.norm(s.field("phi") - pr) / np.linalg.norm(pr))
-    e_cold, e_warm = err(cold), err(w)
-    del ref
-    torch.cuda.empty_cache()
+    pc, pw = cold.field("phi"), w.field("phi")
+    diff = float(np.linalg.norm(pw - pc) / np.linalg.norm(pc))
     # mid-run: the same state stepped with and without the per-step network seed
     res = {}
     for name, s in (("previous_step", cold), ("network", w)):
@@ -282,7 +290,7 @@ def run_warm(steps=20, seed=6):
             "coarse_factor": f,
             "t0": {"cold_sweeps": k_cold, "cold_s": round(t_cold, 3), "warm_sweeps": k_warm,
                    "warm_s": round(t_warm, 3), "speedup": round(t_cold / t_warm, 2),
-                   "phi_rel_error_cold": e_cold, "phi_rel_error_warm": e_warm},
+                   "phi_rel_diff_warm_vs_cold": diff},
             "mid_run": {"steps": steps, **res}}
 
 
@@ -435,7 +443,7 @@ def main():
         cb = cpu_baseline(case, f64["sweeps_per_step"])
         cb.pop("step_s")
         line["cpu_baseline"] = cb
-    print(json.dumps(line), flush=True)
+    print(json.dumps(finite_or_null(line), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
