@@ -228,7 +228,10 @@ class Solver:
     """One case on one GPU.  The workspace is a torch uint8 tensor; the stream is torch's
     current stream on `device` at construction."""
 
-    def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0"):
+    def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0", workspace=None):
+        """`workspace`: optional caller-owned uint8 device tensor of at least
+        `workspace_bytes(case, precision)` bytes (its contents do not matter); by default one
+        is allocated."""
         import torch
 
         if not torch.cuda.is_available():
@@ -239,7 +242,12 @@ class Solver:
         self.params = make_params(case, precision)
         nbytes = workspace_bytes(case, precision)
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if workspace is None:
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            else:
+                if workspace.dtype != torch.uint8 or workspace.device != self.device or workspace.numel() < nbytes:
+                    raise ValueError(f"workspace must be a uint8 tensor on {self.device} of at least {nbytes} bytes")
+                self.workspace = workspace
             self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         rc = lib().lbm_init(C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
