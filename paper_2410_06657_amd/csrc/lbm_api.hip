@@ -271,9 +271,9 @@ int wait_test(lbm_handle* h, unsigned seq, LoopState* out) {
 // Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; block 0 of
 // each launch tests every sweep of the previous launch, and each batch of launches ends
 // with a one-block test of its last launch, after which the host reads the flag.  The
-// first batch covers the previous solve's count plus one launch, later batches double
-// from one launch.  Launches queued after a test ended the loop exit at once.  If the
-// final sweep is not the last of its launch, that launch's sweeps up to it are
+// first batch covers the previous solve's count, later batches double from one launch.
+// Launches queued after a test ended the loop exit at once.  If the final sweep is not
+// the last of its launch, that launch's sweeps up to it are
 // recomputed from its input (three buffers keep that input intact past the launches
 // that follow it in the batch, which all exit at once).
 template <typename R>
@@ -288,11 +288,13 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     LoopState ls{};
     int next = 1;       // next sweep index
     int buf = h->lcur;  // buffer holding the state before sweep `next`
-    // first batch: enough launches for the previous solve's count and one more, at most 256
-    // (after a solve that stopped at its cap the count says little about the next one);
-    // launches beyond the stopping one exit at once, so one host round trip usually ends
-    // the loop
-    int nlaunch = h->kprev > 0 ? std::min(256, (h->kprev + h->swm - 1) / h->swm + 1) : 1;
+    // first batch: enough launches for the previous solve's count, at most 256 (after a
+    // solve that stopped at its cap the count says little about the next one).  A stop in
+    // the batch's last launch is seen by the batch-end test; a stop earlier is seen only at
+    // the end of the launch after it (the lagged test), which then ran in vain, so no spare
+    // launch is queued: a solve that needs more sweeps than the previous one pays a host
+    // round trip and one more launch instead
+    int nlaunch = h->kprev > 0 ? std::min(256, (h->kprev + h->swm - 1) / h->swm) : 1;
     int grow = 1;
     const bool rebasing = std::is_same<R, float>::value;
     for (;;) {
