@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -277,17 +278,20 @@ int wait_test(lbm_handle* h, unsigned seq, LoopState* out) {
 // recomputed from its input (three buffers keep that input intact past the launches
 // that follow it in the batch, which all exit at once).
 template <typename R>
-int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid) {
+int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid,
+               bool armed = false, const std::function<void()>* tail = nullptr) {
     if (std::is_same<R, float>::value) {
         lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
         lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
     }
-    lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
+    // armed: an earlier kernel of the step already reset the loop with these tol/min/max
+    if (!armed) lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
     LAUNCHCHK(h);
     std::vector<lbm::SweepLaunch> plan;
     LoopState ls{};
     int next = 1;       // next sweep index
     int buf = h->lcur;  // buffer holding the state before sweep `next`
+    const int lcur0 = h->lcur;
     // first batch: enough launches for the previous solve's count, at most 256 (after a
     // solve that stopped at its cap the count says little about the next one).  A stop in
     // the batch's last launch is seen by the batch-end test; a stop earlier is seen only at
@@ -326,8 +330,20 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
         tst.prev_nsw = last.nsw;
         tst.prev_slot = last.slot;
         tst.launch = (int)plan.size();
+        tst.src = lcur0;
         const unsigned seq = ++h->seq;
         launch_test<R>(h, tst, seq);
+        if (tail) {
+            // what follows the loop goes out before the host reads the outcome: the
+            // recomputation of the stopping launch and the gated stage kernels run only if
+            // this test (or an earlier one) ended the loop, so the device does not wait for
+            // the host round trip
+            lbm::SweepLaunch fx{};
+            fx.devfix = 1;
+            fx.src = lcur0;
+            launch_sweep<R>(h, fx);
+            (*tail)();
+        }
         LAUNCHCHK(h);
         int rc = wait_test(h, seq, &ls);
         if (rc) return rc;
@@ -347,7 +363,9 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     int k = ls.count;
     const lbm::SweepLaunch& f = plan[ls.fix_launch];
     int final_buf = f.dst;
-    if (ls.fix_n != f.nsw) {
+    if (ls.fix_n != f.nsw && tail) {
+        final_buf = (f.src + 2) % 3;  // recomputed on the device (devfix) behind the last test
+    } else if (ls.fix_n != f.nsw) {
         lbm::SweepLaunch a{};
         a.src = f.src;
         a.dst = (f.src + 2) % 3;
@@ -381,7 +399,9 @@ int one_step(lbm_handle* h) {
     int sp = h->sp;
     hipStream_t st = h->stream;
     State<R>& s = h->st<R>();
-    lbm::k_f_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp);
+    const double tol = h->prm.poisson_tol;
+    const int maxsw = h->prm.poisson_max_sweeps;
+    lbm::k_f_prep_arm<R><<<h->nb, NT, 0, st>>>(d, s, sp, tol, 1, maxsw);
     lbm::k_f_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
     LAUNCHCHK(h);
     if (h->wnn) {
@@ -397,16 +417,20 @@ int one_step(lbm_handle* h) {
         lbm::k_nn_seed<R><<<h->nb, NT, 0, st>>>(d, s, h->lcur, f, h->wnn->y);
         LAUNCHCHK(h);
     }
-    int rc = run_sweeps<R>(h, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, nullptr, nullptr);
+    // stages 3-4 and the volume sum, gated on the loop's end and reading its final buffer
+    // from the control block; queued behind every test of the loop (see run_sweeps)
+    const std::function<void()> tail = [&]() {
+        lbm::k_h_prep1<R><<<h->nb, NT, 0, st>>>(d, s, sp, -1);
+        lbm::k_h_prep2<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_h_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_g_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_vl_finalize<<<1, NT, 0, st>>>(d, h->partials, h->dctl, 0, 1);
+    };
+    int rc = run_sweeps<R>(h, tol, 1, maxsw, nullptr, nullptr, true, &tail);
     if (rc == LBM_ENOCONV)
         h->noconv++;
     else if (rc)
         return rc;
-    lbm::k_h_prep1<R><<<h->nb, NT, 0, st>>>(d, s, sp, h->lcur);
-    lbm::k_h_prep2<R><<<h->nb, NT, 0, st>>>(d, s, sp);
-    lbm::k_h_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
-    lbm::k_g_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
-    lbm::k_vl_finalize<<<1, NT, 0, st>>>(d, h->partials, h->dctl, 0);
     LAUNCHCHK(h);
     h->sp ^= 1;
     h->step++;
@@ -430,7 +454,7 @@ int init_state(lbm_handle* h) {
         if (rc && rc != LBM_ENOCONV) return rc;
     }
     lbm::k_vl0<R><<<h->nb, NT, 0, h->stream>>>(d, s);
-    lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->partials, h->dctl, 1);
+    lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->partials, h->dctl, 1, 0);
     LAUNCHCHK(h);
     return fetch_ctl(h);
 }

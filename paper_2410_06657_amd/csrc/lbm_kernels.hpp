@@ -72,10 +72,24 @@ struct Ctl {
     double tol, resid;
     double V_l0, V_prev, t_fre;      // freezing-time detector
     long long step;
-    int nonfinite, pad1;
+    int nonfinite;
+    int final_buf;                   // potential buffer holding the last loop's final state
     double dsum[6];                  // sum psi, sum f, sum g, V_l, V_s, max |u|
     double front, height;
 };
+
+// Arms the potential loop: clears its outcome and sets its stopping rule.
+__device__ __forceinline__ void ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) {
+    c->fix_launch = 0;
+    c->fix_n = 0;
+    c->done = 0;
+    c->count = 0;
+    c->conv = 0;
+    c->resid = 0.0;
+    c->tol = tol;
+    c->min_sweeps = min_sweeps;
+    c->max_sweeps = max_sweeps;
+}
 
 // Offsets into the partial-sum array (nb = blocks of a node-parallel launch).
 constexpr int SW_MAXM = 8;  // most sweeps one blocked launch performs
@@ -447,6 +461,13 @@ template <typename R>
 __global__ void __launch_bounds__(NT) k_f_prep(Dev d, State<R> s, int sp) {
     b_f_prep<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
+// The same, also arming the step's potential loop (one launch less per step).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_f_prep_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
+                                                   int max_sweeps) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
+    b_f_prep<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+}
 
 // Stage 1b: f pulled and collided at its source, half-way bounce-back at the
 // walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.
@@ -533,7 +554,20 @@ struct SweepLaunch {
     int prev_k0, prev_nsw, prev_slot;  // previous launch to test (prev_nsw = 0: none)
     int launch;                 // index of this launch within the solve
     int force;                  // run even if the loop has ended (recomputation)
+    int devfix;                 // recompute the stopping launch up to the final sweep as the
+                                // control block records it (src = the solve's first buffer);
+                                // nothing if the loop has not ended or ended on a launch boundary
 };
+
+// Buffer of the stopping launch's input, and of the final state, for a loop that started
+// from buffer lcur0 (launch t reads buffer (lcur0 + t) mod 3 and writes the next one; a
+// recomputation writes the third).
+__device__ __forceinline__ int stop_src(const Ctl* c, int lcur0) { return (lcur0 + c->fix_launch) % 3; }
+template <int M>
+__device__ __forceinline__ bool stop_recompute(const Ctl* c) {
+    const int k0 = c->fix_launch * M + 1;
+    return c->fix_n != min(M, c->max_sweeps + 1 - k0);
+}
 
 template <int M, typename R, int NW = NT / 64>
 __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh) {
@@ -570,13 +604,23 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
 }
 
 template <int M, typename R, int WV>
-__device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& a, int tile) {
+__device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& ain, int tile) {
     // no implicit contraction: the fused operations are written out, so the result does not
     // depend on how the compiler unrolls the M sweeps (bitwise equal for every launch shape)
 #pragma clang fp contract(off)
     __shared__ R bup[2][WV][64], bdn[2][WV][64];
     __shared__ double sh[WV * 2 * M];
     const Ctl* c = s.ctl;
+    SweepLaunch a = ain;
+    if (a.devfix) {
+        if (!c->done || !stop_recompute<M>(c)) return;
+        a.src = stop_src(c, ain.src);
+        a.dst = (a.src + 2) % 3;
+        a.k0 = c->fix_launch * M + 1;
+        a.nsw = c->fix_n;
+        a.force = 1;
+        a.prev_nsw = 0;
+    }
     if (c->done && !a.force) return;
     if (a.nsw > 0) {
         constexpr int OX = 64 - 2 * M, OY = WV * SW_NPT - 2 * M;
@@ -806,6 +850,12 @@ __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, Sweep
     __shared__ double sh[TEST_NT / 64 * 2 * M];
     if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
     if (threadIdx.x != 0) return;
+    // a.src: the solve's first buffer; the stage kernels that follow a loop read its final
+    // buffer from here
+    if (s.ctl->done) {
+        const int src = stop_src(s.ctl, a.src);
+        s.ctl->final_buf = stop_recompute<M>(s.ctl) ? (src + 2) % 3 : (src + 1) % 3;
+    }
     const Ctl* c = s.ctl;
     const unsigned long long hi = (unsigned long long)seq << 32;
     const unsigned long long w0 = hi | (unsigned)c->count;
@@ -816,32 +866,18 @@ __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, Sweep
 }
 
 __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) {
-    c->fix_launch = 0;
-    c->fix_n = 0;
-    c->done = 0;
-    c->count = 0;
-    c->conv = 0;
-    c->resid = 0.0;
-    c->tol = tol;
-    c->min_sweeps = min_sweeps;
-    c->max_sweeps = max_sweeps;
+    ctl_reset(c, tol, min_sweeps, max_sweeps);
 }
 
 // ---------------------------------------------------------------------------
 // Stage 3a: surface tension (Eqs. (3)-(5)) and electric force (Eq. (14)) with
 // psi^{n+1}; S = rho mdot + u . grad(rho) (Eq. (24)).
 template <typename R>
-__device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
-    int64_t n = at(d, i, j);
-    const R* psi = s.psi[sp ^ 1];
-    const R* fs = s.fs[sp];
+__device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int sp, int lcur, int i, int j,
+                                           int64_t n, const R (&vp)[3][3], const R (&vf)[3][3], R& FxOut,
+                                           R& FyOut) {
     const R* phi = s.phi[lcur];
-    R vp[3][3], vf[3][3], vph[3][3], ve[3][3], vr[3][3];
-    load3<GWET, R>(psi, d, i, j, vp);
-    load3<GMIRROR, R>(fs, d, i, j, vf);
+    R vph[3][3], ve[3][3], vr[3][3];
     load3<GPHI, R>(phi, d, i, j, vph);
 #pragma unroll
     for (int a = 0; a < 3; a++)
@@ -866,27 +902,40 @@ __device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int s
     Fy += qv * Ey - R(0.5) * E2 * gey;
     s.Fx[n] = Fx;
     s.Fy[n] = Fy;
+    FxOut = Fx;
+    FyOut = Fy;
     R grx, gry;
     grad_lap<R>(vr, grx, gry, dum);
     s.S[n] = vr[1][1] * s.md[sp][n] + s.ux[sp][n] * grx + s.uy[sp][n] * gry;
 }
 template <typename R>
+__device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    int64_t n = at(d, i, j);
+    R vp[3][3], vf[3][3], Fx, Fy;
+    load3<GWET, R>(s.psi[sp ^ 1], d, i, j, vp);
+    load3<GMIRROR, R>(s.fs[sp], d, i, j, vf);
+    h_prep1_at<R>(d, s, sp, lcur, i, j, n, vp, vf, Fx, Fy);
+}
+// Stage kernels queued behind a potential loop before the host knows its outcome are gated:
+// they run only if the loop has ended (else the host queues them again once it has), and
+// take the final potential buffer from the control block (lcur < 0).
+template <typename R>
 __global__ void __launch_bounds__(NT) k_h_prep1(Dev d, State<R> s, int sp, int lcur) {
+    if (lcur < 0) {
+        if (!s.ctl->done) return;
+        lcur = s.ctl->final_buf;
+    }
     b_h_prep1<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Stage 3b: collision inputs of h: rho, F~, F + rho f_solid, 1/tau_h.
 template <typename R>
-__device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int sp, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
-    int64_t n = at(d, i, j);
-    const R* psi = s.psi[sp ^ 1];
-    const R* fs = s.fs[sp];
-    R vp[3][3], vf[3][3], vr[3][3], vpr[3][3];
-    load3<GWET, R>(psi, d, i, j, vp);
-    load3<GMIRROR, R>(fs, d, i, j, vf);
+__device__ __forceinline__ void h_prep2_at(const Dev& d, const State<R>& s, int sp, int i, int j, int64_t n,
+                                           const R (&vp)[3][3], const R (&vf)[3][3], R Fx, R Fy) {
+    R vr[3][3], vpr[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
@@ -902,7 +951,6 @@ __device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int s
     }
     R rho = vr[1][1];
     R fsn = vf[1][1];
-    R Fx = s.Fx[n], Fy = s.Fy[n];
     s.rho[n] = rho;
     s.Ftx[n] = Fx - gpx + R(CS2) * grx + R(CS2) * gsx;
     s.Fty[n] = Fy - gpy + R(CS2) * gry + R(CS2) * gsy;
@@ -912,10 +960,21 @@ __device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int s
     s.omh[n] = R(1) / (mu / (rho * R(CS2)) + R(0.5));
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_h_prep2(Dev d, State<R> s, int sp) {
+__device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int sp, int tile) {
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    int64_t n = at(d, i, j);
+    R vp[3][3], vf[3][3];
+    load3<GWET, R>(s.psi[sp ^ 1], d, i, j, vp);
+    load3<GMIRROR, R>(s.fs[sp], d, i, j, vf);
+    h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, s.Fx[n], s.Fy[n]);
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_h_prep2(Dev d, State<R> s, int sp, int gate) {
+    if (gate && !s.ctl->done) return;
     b_h_prep2<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
-
 template <typename R>
 __device__ __forceinline__ HIn<R> h_inputs(const State<R>& s, int sp, int64_t m) {
     return HIn<R>{s.p[sp][m], s.rho[m], s.ux[sp][m], s.uy[sp][m], s.S[m],
@@ -970,7 +1029,8 @@ __device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int 
     s.p[sp ^ 1][n] = R(CS2 / (1.0 - W0)) * (s0 + R(0.5) * self.S + (R(1) / self.om) * R0 + rho * s0u);
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_h_stream(Dev d, State<R> s, int sp) {
+__global__ void __launch_bounds__(NT) k_h_stream(Dev d, State<R> s, int sp, int gate) {
+    if (gate && !s.ctl->done) return;
     b_h_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
@@ -1049,15 +1109,17 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
     if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + tile] = bv;
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_g_stream(Dev d, State<R> s, int sp) {
+__global__ void __launch_bounds__(NT) k_g_stream(Dev d, State<R> s, int sp, int gate) {
+    if (gate && !s.ctl->done) return;
     b_g_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // One block: liquid volume of the new state (block partials in order).  mode 1 records
 // V_l0 after initialisation; mode 0 advances the step counter and runs the freezing-time
 // detector: t_fre is the first step with V_l <= 1% of V_l0, interpolated linearly.
-__global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, const double* partials, Ctl* c, int mode) {
+__global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, const double* partials, Ctl* c, int mode, int gate) {
     __shared__ double sh[NT / 64];
+    if (gate && !c->done) return;
     int nb = d.gx * d.gy;
     const double* pv = partials + part_vl(nb);
     double a = 0.0;
