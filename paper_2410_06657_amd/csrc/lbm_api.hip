@@ -220,7 +220,8 @@ void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
     int nbt = h->dev.tbx * h->dev.tby;
     State<R>& s = h->st<R>();
     with_shape(h->swm, h->swv, [&](auto M, auto WV) {
-        lbm::k_sweep_tb<M, R, WV, Tag><<<nbt, 64 * WV, 0, h->stream>>>(h->dev, s, a);
+        // one block per tile (and in FP32 one for the test of the previous launch)
+        lbm::k_sweep_tb<M, R, WV, Tag><<<nbt + (lbm::SEP_TEST<R> ? 1 : 0), 64 * WV, 0, h->stream>>>(h->dev, s, a);
     });
 }
 

@@ -200,23 +200,24 @@ __device__ __forceinline__ int ring_self() { return (threadIdx.x / TX + 1) * RX 
 __device__ __forceinline__ int ring_from(int self, int cx, int cy) { return self - cy * RX - cx; }
 
 // Wave-wide lane shifts by one lane on the VALU (DPP wave_shr / wave_shl): lane_up gives lane
-// i the value of lane i - 1, lane_down the value of lane i + 1 (the lane at the end gets 0).
+// i the value of lane i - 1, lane_down the value of lane i + 1 (the lane at the end gets 0,
+// written by the DPP bound control, so no register has to be cleared first).
 __device__ __forceinline__ float lane_up(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_down(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_up(double x) {
     const long long v = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x138, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double lane_down(double x) {
     const long long v = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x130, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -603,13 +604,18 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
     }
 }
 
-template <int M, typename R, int WV>
+// InlineTest: block 0 of the launch tests the previous launch after its own sweeps (the
+// batched form); otherwise the launch carries one extra block for that test.
+template <int M, typename R, int WV, bool InlineTest = true>
 __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& ain, int tile) {
     // no implicit contraction: the fused operations are written out, so the result does not
     // depend on how the compiler unrolls the M sweeps (bitwise equal for every launch shape)
 #pragma clang fp contract(off)
     __shared__ R bup[2][WV][64], bdn[2][WV][64];
     __shared__ double sh[WV * 2 * M];
+    // each thread's FP64 residual sums of every sweep, parked here at the end of the sweep
+    // instead of in registers (16 accumulators would cost the kernel a wave per SIMD)
+    __shared__ double accs[2 * M][64 * WV];
     const Ctl* c = s.ctl;
     SweepLaunch a = ain;
     if (a.devfix) {
@@ -627,7 +633,8 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
         const R inv = R(INV_1MW0), lw = R(LWA);
         int nbt = d.tbx * d.tby;
         int bx = tile % d.tbx, by = tile / d.tbx;
-        int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        // w (the wave) and everything derived from it is wave-uniform: scalar registers
+        int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         int x0 = bx * OX - M, y0 = by * OY - M + w * SW_NPT;
         int graw = x0 + lane;
         int gi = graw % d.nx;
@@ -636,7 +643,9 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
         const R* ls = s.l[a.src];
         const int64_t P = d.plane;
         constexpr bool based = std::is_same<R, float>::value;
-        R L1[SW_NPT], L2[SW_NPT], L3[SW_NPT], L4[SW_NPT], OM[SW_NPT], PB[SW_NPT];
+        // OMC = 1 - omega: the collision l - omega (l - w phi) is evaluated as
+        // (1 - omega) l + omega w phi, the second term once per node
+        R L1[SW_NPT], L2[SW_NPT], L3[SW_NPT], L4[SW_NPT], OMC[SW_NPT], PB[SW_NPT], PH[SW_NPT];
 #pragma unroll
         for (int k = 0; k < SW_NPT; k++) {
             int gj = y0 + k;
@@ -646,15 +655,13 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                 L2[k] = ls[P + n];
                 L3[k] = ls[2 * P + n];
                 L4[k] = ls[3 * P + n];
-                OM[k] = s.oml[n];
+                OMC[k] = R(1) - s.oml[n];
             } else {
-                L1[k] = L2[k] = L3[k] = L4[k] = OM[k] = R(0);
+                L1[k] = L2[k] = L3[k] = L4[k] = OMC[k] = R(0);
             }
             PB[k] = R(0);
+            PH[k] = (L1[k] + L2[k] + L3[k] + L4[k]) * inv;
         }
-        double accd[M], accp[M];
-#pragma unroll
-        for (int m = 0; m < M; m++) accd[m] = accp[m] = 0.0;
         // FP32 pair storage (link = b + l): the sweep works on the remainders l; the pulled
         // base increments D and phi_B are launch constants prepared by k_sweep_prep
         R D1[SW_NPT], D2[SW_NPT], D3[SW_NPT], D4[SW_NPT];
@@ -675,21 +682,27 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
             }
         }
         const R wbot0 = R(2.0 * LWA * d.phi_bot), wtop0 = R(2.0 * LWA * d.phi_top);
+        double rw[SW_NPT];  // 1: the row is written by this block (inner rows inside the domain)
+#pragma unroll
+        for (int k = 0; k < SW_NPT; k++) {
+            const int r = w * SW_NPT + k, gj = y0 + k;
+            rw[k] = (r >= M && r < M + OY && gj >= 0 && gj < d.ny) ? 1.0 : 0.0;
+        }
 #pragma unroll
         for (int m = 0; m < M; m++) {
             if (m >= a.nsw) break;
-            R A1[SW_NPT], A2[SW_NPT], A3[SW_NPT], A4[SW_NPT], PH[SW_NPT];
+            R A1[SW_NPT], A2[SW_NPT], A3[SW_NPT], A4[SW_NPT];
+            double accd = 0.0, accp = 0.0;
 #pragma unroll
             for (int k = 0; k < SW_NPT; k++) {
-                R ph = (L1[k] + L2[k] + L3[k] + L4[k]) * inv;
-                PH[k] = ph;
-                R e = lw * ph;
-                // l - omega (l - e) as one fused multiply-add (explicit, so every launch shape
-                // rounds it the same way)
-                A1[k] = fma_r(-OM[k], L1[k] - e, L1[k]);
-                A2[k] = fma_r(-OM[k], L2[k] - e, L2[k]);
-                A3[k] = fma_r(-OM[k], L3[k] - e, L3[k]);
-                A4[k] = fma_r(-OM[k], L4[k] - e, L4[k]);
+                // PH: phi of the current links (from the load, then from the previous sweep)
+                R e = lw * PH[k];
+                R q = fma_r(-OMC[k], e, e);  // omega w phi
+                // explicit fused multiply-adds, so every launch shape rounds them the same way
+                A1[k] = fma_r(OMC[k], L1[k], q);
+                A2[k] = fma_r(OMC[k], L2[k], q);
+                A3[k] = fma_r(OMC[k], L3[k], q);
+                A4[k] = fma_r(OMC[k], L4[k], q);
             }
             int par = m & 1;
             bup[par][w][lane] = A2[SW_NPT - 1];
@@ -717,15 +730,17 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                 L2[k] = n2;
                 L3[k] = n3;
                 L4[k] = n4;
-                int r = w * SW_NPT + k;
-                if (ownx && r >= M && r < M + OY && gj >= 0 && gj < d.ny) {
-                    R ph = (n1 + n2 + n3 + n4) * inv;
-                    double dd = (double)(ph - PH[k]);
-                    double pr = based ? (double)ph + (double)PB[k] : (double)ph;
-                    accd[m] = __builtin_fma(dd, dd, accd[m]);
-                    accp[m] = __builtin_fma(pr, pr, accp[m]);
-                }
+                const R ph = (n1 + n2 + n3 + n4) * inv;
+                // rows count with the wave-uniform weight rw[k] (1 or 0: a scalar operand, no
+                // per-node select); the column mask ownx is applied when the sums are parked
+                double dd = (double)(ph - PH[k]);
+                double pr = based ? (double)ph + (double)PB[k] : (double)ph;
+                accd = __builtin_fma(dd * rw[k], dd, accd);
+                accp = __builtin_fma(pr * rw[k], pr, accp);
+                PH[k] = ph;
             }
+            accs[2 * m][threadIdx.x] = ownx ? accd : 0.0;
+            accs[2 * m + 1][threadIdx.x] = ownx ? accp : 0.0;
         }
         R* ld = s.l[a.dst];
         R* pd = s.phi[a.dst];
@@ -739,35 +754,55 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                 ld[P + n] = L2[k];
                 ld[2 * P + n] = L3[k];
                 ld[3 * P + n] = L4[k];
-                pd[n] = based ? PB[k] + (L1[k] + L2[k] + L3[k] + L4[k]) * inv
-                              : (L1[k] + L2[k] + L3[k] + L4[k]) * inv;
+                pd[n] = based ? PB[k] + PH[k] : PH[k];
             }
         }
+        // block sums of the 2M parked values: G threads per value, each adding a fixed
+        // strided subset, then a butterfly over the G lanes (a fixed order: reproducible)
         double* pw = s.partials + part_sweep(d.gx * d.gy, nbt, a.slot);
-        double acc[2 * M];
+        constexpr int NTH = 64 * WV, G0 = NTH / (2 * M), G = G0 < 64 ? G0 : 64;
+        __syncthreads();
+        const int t = threadIdx.x;
+        if (t < 2 * M * G) {
+            const int v = t / G, p = t % G;
+            double sum = 0.0;
+            for (int q = p; q < NTH; q += G) sum += accs[v][q];
 #pragma unroll
-        for (int m = 0; m < M; m++) {
-            acc[2 * m] = accd[m];
-            acc[2 * m + 1] = accp[m];
+            for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+            if (p == 0 && v / 2 < a.nsw) pw[((int64_t)(v / 2) * nbt + tile) * 2 + (v & 1)] = sum;
         }
-        block_sum_n<2 * M, WV>(acc, sh);
-        if (threadIdx.x == 0)
-            for (int m = 0; m < M && m < a.nsw; m++) {
-                pw[((int64_t)m * nbt + tile) * 2] = acc[2 * m];
-                pw[((int64_t)m * nbt + tile) * 2 + 1] = acc[2 * m + 1];
-            }
     }
-    if (tile == 0 && a.prev_nsw > 0) {
+    if (InlineTest && tile == 0 && a.prev_nsw > 0) {
         __syncthreads();
         sweep_test<M, R, WV>(d, s, a, sh);
     }
 }
 
+// One launch of the single-case loop.  FP32 (SEP_TEST): blocks 0 .. nb-1 sweep their tiles
+// and one extra block tests the previous launch meanwhile (its partial sums are complete
+// when the launch starts), which takes the test off the launch's critical path (20.4 us
+// against 26.8 us per 8-sweep launch at 1024 x 512).  A block that starts after that test
+// has ended the loop exits at once, as the whole launch would have: its output is never
+// used (the final state is the previous launch's, or recomputed from its input).  FP64
+// keeps the test in block 0, where it does not lengthen the launch.
 // Tag only separates launches in a profile (1: the timing entry point, 2: the autotuner),
 // so they appear under their own names; the code is the same.
+template <typename R>
+constexpr bool SEP_TEST = std::is_same<R, float>::value;
 template <int M, typename R, int WV, int Tag = 0>
-__global__ void __launch_bounds__(64 * WV) k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
-    b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, gridDim.x));
+__global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)))
+k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
+    if constexpr (SEP_TEST<R>) {
+        const int nb = gridDim.x - 1;
+        if ((int)blockIdx.x == nb) {
+            __shared__ double sh[WV * 2 * M];
+            if (a.prev_nsw > 0 && !a.devfix && !s.ctl->done) sweep_test<M, R, WV>(d, s, a, sh);
+            return;
+        }
+        b_sweep_tb<M, R, WV, false>(d, s, a, xcd_tile(blockIdx.x, nb));
+    } else {
+        b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, gridDim.x));
+    }
 }
 
 // FP32 form: renormalise every link pair (b, l) by Knuth's two-sum, b' = fl(b + l) and
@@ -1340,7 +1375,7 @@ __device__ __forceinline__ SweepLaunch lockstep_launch(const Ctl* c, int lcur0, 
 }
 
 template <int M, typename R, int WV>
-__global__ void __launch_bounds__(64 * WV) kb_sweep(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
+__global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3))) kb_sweep(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
                                                     int ncases, const int* __restrict__ lcur0, int t) {
     int b = xcd_tile(blockIdx.x, gridDim.x);
     int c = find_case(first, ncases, b);
@@ -1353,7 +1388,7 @@ __global__ void __launch_bounds__(64 * WV) kb_sweep(const BatchCase<R>* __restri
 // Recomputation of each finished case's last launch up to its final sweep (fix[c].nsw = 0:
 // nothing to redo for that case).
 template <int M, typename R, int WV>
-__global__ void __launch_bounds__(64 * WV) kb_sweep_fix(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
+__global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3))) kb_sweep_fix(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
                                                         int ncases, const SweepLaunch* __restrict__ fix) {
     int b = xcd_tile(blockIdx.x, gridDim.x);
     int c = find_case(first, ncases, b);
