@@ -220,8 +220,8 @@ void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
     int nbt = h->dev.tbx * h->dev.tby;
     State<R>& s = h->st<R>();
     with_shape(h->swm, h->swv, [&](auto M, auto WV) {
-        // one block per tile (and in FP32 one for the test of the previous launch)
-        lbm::k_sweep_tb<M, R, WV, Tag><<<nbt + (lbm::SEP_TEST<R> ? 1 : 0), 64 * WV, 0, h->stream>>>(h->dev, s, a);
+        // one block per tile and one for the test of the previous launch
+        lbm::k_sweep_tb<M, R, WV, Tag><<<nbt + 1, 64 * WV, 0, h->stream>>>(h->dev, s, a);
     });
 }
 
@@ -1099,8 +1099,9 @@ const lbm::BatchCase<R>* btable(lbm_batch* b) { return (const lbm::BatchCase<R>*
 template <typename R>
 void batch_sweep(lbm_batch* b, int t) {
     with_shape(b->swm, b->swv, [&](auto M, auto WV) {
-        lbm::kb_sweep<M, R, WV><<<b->sweep_blocks, 64 * WV, 0, b->stream>>>(btable<R>(b), b->first_sw, b->ncases,
-                                                                            b->lcur0_d, t);
+        // the tiles of every case, then one test block per case
+        lbm::kb_sweep<M, R, WV><<<b->sweep_blocks + b->ncases, 64 * WV, 0, b->stream>>>(
+            btable<R>(b), b->first_sw, b->ncases, b->lcur0_d, t);
     });
 }
 
@@ -1124,7 +1125,7 @@ void batch_fix(lbm_batch* b) {
 }
 
 // Lockstep potential loops of all cases.  Launch t performs sweeps t*M+1.. of every case
-// that is still running (and, in block 0 of each case, tests its launch t-1); a batch of
+// that is still running (and, in one extra block per case, tests its launch t-1); a batch of
 // launches ends with a one-block-per-case test of its last launch, then the host reads
 // all control blocks.  Finished cases whose final sweep was not the last of its launch
 // are recomputed together in one launch.

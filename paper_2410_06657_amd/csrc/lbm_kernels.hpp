@@ -604,15 +604,14 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
     }
 }
 
-// InlineTest: block 0 of the launch tests the previous launch after its own sweeps (the
-// batched form); otherwise the launch carries one extra block for that test.
-template <int M, typename R, int WV, bool InlineTest = true>
+// The test of the previous launch (a.prev_*) is not made here: the launches carry extra
+// blocks for it (k_sweep_tb, kb_sweep).
+template <int M, typename R, int WV>
 __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& ain, int tile) {
     // no implicit contraction: the fused operations are written out, so the result does not
     // depend on how the compiler unrolls the M sweeps (bitwise equal for every launch shape)
 #pragma clang fp contract(off)
     __shared__ R bup[2][WV][64], bdn[2][WV][64];
-    __shared__ double sh[WV * 2 * M];
     // each thread's FP64 residual sums of every sweep, parked here at the end of the sweep
     // instead of in registers (16 accumulators would cost the kernel a wave per SIMD)
     __shared__ double accs[2 * M][64 * WV];
@@ -772,37 +771,26 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
             if (p == 0 && v / 2 < a.nsw) pw[((int64_t)(v / 2) * nbt + tile) * 2 + (v & 1)] = sum;
         }
     }
-    if (InlineTest && tile == 0 && a.prev_nsw > 0) {
-        __syncthreads();
-        sweep_test<M, R, WV>(d, s, a, sh);
-    }
 }
 
-// One launch of the single-case loop.  FP32 (SEP_TEST): blocks 0 .. nb-1 sweep their tiles
-// and one extra block tests the previous launch meanwhile (its partial sums are complete
-// when the launch starts), which takes the test off the launch's critical path (20.4 us
-// against 26.8 us per 8-sweep launch at 1024 x 512).  A block that starts after that test
-// has ended the loop exits at once, as the whole launch would have: its output is never
-// used (the final state is the previous launch's, or recomputed from its input).  FP64
-// keeps the test in block 0, where it does not lengthen the launch.
+// One launch of the single-case loop: blocks 0 .. nb-1 sweep their tiles and one extra
+// block tests the previous launch meanwhile (its partial sums are complete when the launch
+// starts), which takes the test off the launch's critical path (20.2 us against 25.4 us per
+// 8-sweep FP64 launch at 1024 x 512).  A block that starts after that test has ended the
+// loop exits at once, as the whole launch would have: its output is never used (the final
+// state is the previous launch's, or recomputed from its input).
 // Tag only separates launches in a profile (1: the timing entry point, 2: the autotuner),
 // so they appear under their own names; the code is the same.
-template <typename R>
-constexpr bool SEP_TEST = std::is_same<R, float>::value;
 template <int M, typename R, int WV, int Tag = 0>
 __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)))
 k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
-    if constexpr (SEP_TEST<R>) {
-        const int nb = gridDim.x - 1;
-        if ((int)blockIdx.x == nb) {
-            __shared__ double sh[WV * 2 * M];
-            if (a.prev_nsw > 0 && !a.devfix && !s.ctl->done) sweep_test<M, R, WV>(d, s, a, sh);
-            return;
-        }
-        b_sweep_tb<M, R, WV, false>(d, s, a, xcd_tile(blockIdx.x, nb));
-    } else {
-        b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, gridDim.x));
+    const int nb = gridDim.x - 1;
+    if ((int)blockIdx.x == nb) {
+        __shared__ double sh[WV * 2 * M];
+        if (a.prev_nsw > 0 && !a.devfix && !s.ctl->done) sweep_test<M, R, WV>(d, s, a, sh);
+        return;
     }
+    b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, nb));
 }
 
 // FP32 form: renormalise every link pair (b, l) by Knuth's two-sum, b' = fl(b + l) and
@@ -1377,7 +1365,17 @@ __device__ __forceinline__ SweepLaunch lockstep_launch(const Ctl* c, int lcur0, 
 template <int M, typename R, int WV>
 __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3))) kb_sweep(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
                                                     int ncases, const int* __restrict__ lcur0, int t) {
-    int b = xcd_tile(blockIdx.x, gridDim.x);
+    // the last ncases blocks test each case's previous launch while the others sweep (as
+    // in the single-case launch: the test is off the critical path)
+    const int ntiles = gridDim.x - ncases;
+    if ((int)blockIdx.x >= ntiles) {
+        __shared__ double sh[WV * 2 * M];
+        const BatchCase<R>& bc = cases[blockIdx.x - ntiles];
+        SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x - ntiles], t);
+        if (a.nsw > 0 && a.prev_nsw > 0 && !bc.s.ctl->done) sweep_test<M, R, WV>(bc.d, bc.s, a, sh);
+        return;
+    }
+    int b = xcd_tile(blockIdx.x, ntiles);
     int c = find_case(first, ncases, b);
     const BatchCase<R>& bc = cases[c];
     SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t);
