@@ -294,6 +294,42 @@ def run_warm(steps=20, seed=6):
             "mid_run": {"steps": steps, **res}}
 
 
+def run_validation():
+    """The paper's validation problems (Sec. 4) as FP64 batches: the Fig. 5 deformation sweeps
+    (12 free drops, R0 = 20 in 160 x 160, 10,000 steps), the Neumann front at four Stefan
+    numbers and the final height of six freezing layers, with wall times and the largest
+    deviations from the closed forms."""
+    import torch
+
+    from paper_2410_06657_amd import validation as v
+
+    out = {}
+    t0 = time.perf_counter()
+    d = v.deformation_sweep()
+    torch.cuda.synchronize()
+    out["deformation"] = {
+        "workload": "12 free drops, R0=20 in 160x160, Ca_E=0.2, R=5 with S in 1..15 and S=2 with R in 0.5..8, FP64 batch, D averaged over steps 6000-10000",
+        "wall_s": round(time.perf_counter() - t0, 2),
+        "points": [{k: (round(x, 5) if isinstance(x, float) else x) for k, x in r.items()} for r in d],
+        "sign_agrees_with_feng": all((r["D"] > 0) == (r["feng"] > 0) for r in d),
+        "max_outside_taylor_feng_band": round(max(max(min(r["feng"], r["taylor"]) - r["D"],
+                                                      r["D"] - max(r["feng"], r["taylor"]), 0.0) for r in d), 5)}
+    print(f"[bench] validation: deformation sweep {out['deformation']['wall_s']}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    nm = v.neumann_sweep()
+    out["neumann_front"] = {"workload": "4x48 strips, alpha_s=0.2, Ste in {0.05, 0.1, 0.2, 0.5}, FP64 batch",
+                            "wall_s": round(time.perf_counter() - t0, 2),
+                            "max_rel_err": round(max(max(r["rel_err"]) for r in nm), 5)}
+    t0 = time.perf_counter()
+    fh = v.final_height_sweep()
+    out["final_height"] = {"workload": "4x48 strips, h0=16, Ste in {0.2, 0.5} x rho_s/rho_l in {0.9, 1.0, 1.1}, FP64 batch",
+                           "wall_s": round(time.perf_counter() - t0, 2),
+                           "max_rel_err": round(max(abs(r["h_f_over_h_0"] / r["closed_form"] - 1) for r in fh), 5)}
+    print(f"[bench] validation: Stefan sweeps {out['neumann_front']['wall_s']}s + {out['final_height']['wall_s']}s",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def run_time_to_freeze(nbatch=8, max_steps=100000):
     """Time to freeze (R30) of the 128 x 64 sessile drop (R0 = 24, theta = 90, R = 3, S = 1,
     Ca_E = 0.1, Ste = 0.1): FP64, FP32, FP64 with the learned warm start of the initial
@@ -396,6 +432,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-time-to-freeze", action="store_true", help="skip the time-to-freeze runs")
+    ap.add_argument("--no-validation", action="store_true", help="skip the validation problems")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--batched-cap", type=int, default=2000,
                     help="potential sweeps cap per solve in the batched comparison")
@@ -435,6 +472,8 @@ def main():
         line["forms"] = {"fp32": f32}
     if not args.no_time_to_freeze:
         line["time_to_freeze"] = run_time_to_freeze()
+    if not args.no_validation:
+        line["validation"] = run_validation()
     if not args.no_warm:
         line.setdefault("forms", {})["warm"] = run_warm()
     if not args.no_batched:

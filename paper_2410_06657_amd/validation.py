@@ -1,0 +1,142 @@
+"""The paper's validation problems (Sec. 4) run on the library, each sweep as one batch.
+
+* Deformation of a free leaky-dielectric drop in a uniform field (Fig. 5): D = (L - H)/(L + H),
+  L the extent along the field, against Taylor's small-deformation value (f_T as printed in
+  Sec. 4) and Feng's 2D first-order value; R = 5 with S swept and S = 2 with R swept, Ca_E = 0.2.
+* Three-phase Stefan problem (Fig. 2): the one-phase Neumann front s = 2 lambda sqrt(alpha_s t)
+  of a liquid at T_m on a substrate at -Ste, and the final height h_f = rho_l h_0 / rho_s of a
+  layer that freezes completely.
+
+Freezing is off for the drops (T_w = T_g above T_m).  Inputs come from `inputs.free_drop` and
+`inputs.stefan_strip`.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import inputs
+
+CA_E = 0.2
+S_SWEEP = [(5.0, S) for S in (1.0, 3.0, 6.0, 9.0, 12.0, 15.0)]   # Fig. 5(a): R = 5
+R_SWEEP = [(R, 2.0) for R in (0.5, 1.0, 2.0, 3.0, 5.0, 8.0)]     # Fig. 5(b): S = 2
+
+
+def feng(R: float, S: float, Ca: float) -> float:
+    """Feng's 2D first-order deformation, D = Ca_E f_F / (3 (1 + R)^2), f_F = R^2 + R + 1 - 3S."""
+    return Ca * (R * R + R + 1 - 3 * S) / (3 * (1 + R) ** 2)
+
+
+def taylor(R: float, S: float, Ca: float, B: float = 1.0) -> float:
+    """Taylor's small-deformation value 9 Ca_E f_T / (16 (2 + R)^2), B the viscosity ratio."""
+    fT = R * R + 1 - 2 * S + 0.6 * (R - S) * (2 + 3 * B) / (1 + B)
+    return 9 * Ca / 16 * fT / (2 + R) ** 2
+
+
+def neumann_lambda(ste: float) -> float:
+    """Root of lambda exp(lambda^2) erf(lambda) = Ste / sqrt(pi) (one-phase Neumann problem)."""
+    lo, hi = 1e-12, 3.0
+    f = lambda x: x * math.exp(x * x) * math.erf(x) - ste / math.sqrt(math.pi)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi)
+
+
+def _span(v: np.ndarray) -> float:
+    """Length of the psi >= 1/2 run along a line, ends interpolated linearly."""
+    idx = np.where(v >= 0.5)[0]
+    a, b = idx[0], idx[-1]
+    lo = a - (v[a] - 0.5) / (v[a] - v[a - 1])
+    hi = b + (v[b] - 0.5) / (v[b] - v[b + 1])
+    return hi - lo
+
+
+def deformation(psi: np.ndarray, case: dict) -> float:
+    """(L - H)/(L + H) through the drop centre; the field is along y."""
+    ic, jc = int(round(case["xc"])), int(round(case["yc"]))
+    L, H = _span(psi[:, ic]), _span(psi[jc, :])
+    return (L - H) / (L + H)
+
+
+def front(fl_column: np.ndarray) -> float:
+    """Distance of the f_l = 1/2 crossing from the substrate (the wall is at y = -1/2)."""
+    m = int(np.where(fl_column >= 0.5)[0][0])
+    return (m - 1) + (0.5 - fl_column[m - 1]) / (fl_column[m] - fl_column[m - 1]) + 0.5
+
+
+def deformation_sweep(n: int = 160, R0: float = 20.0, settle: int = 5000, samples: int = 5,
+                      every: int = 1000, precision: str = "fp64") -> list[dict]:
+    """Both Fig. 5 sweeps as one batch; D averaged over `samples` readings `every` steps apart
+    after `settle` steps."""
+    from .lbm import Batch
+    pts = S_SWEEP + R_SWEEP
+    cases = [inputs.free_drop(n, n, R0, R=R, S=S, Ca_E=CA_E) for R, S in pts]
+    b = Batch(cases, precision=precision)
+    b.step(settle)
+    reads = []
+    for _ in range(samples):
+        b.step(every)
+        reads.append([deformation(b.field(k, "psi"), cases[k]) for k in range(len(pts))])
+    reads = np.array(reads)
+    out = []
+    for k, (R, S) in enumerate(pts):
+        out.append({"R": R, "S": S, "D": float(reads[:, k].mean()),
+                    "spread": float(reads[:, k].max() - reads[:, k].min()),
+                    "feng": feng(R, S, CA_E), "taylor": taylor(R, S, CA_E)})
+    return out
+
+
+def neumann_sweep(stes=(0.05, 0.1, 0.2, 0.5), alpha: float = 0.2, ny: int = 48,
+                  at=(12.0, 18.0, 24.0), chunk: int = 250, precision: str = "fp64") -> list[dict]:
+    """Front position against Neumann's when the front has travelled about `at` nodes."""
+    from .lbm import Batch
+    cases = [inputs.stefan_strip(4, ny, h0=1e6, Ste=s, rho_ratio_sl=1.0, alpha_s=alpha) for s in stes]
+    b = Batch(cases, precision=precision)
+    lams = [neumann_lambda(s) for s in stes]
+    when = [sorted({chunk * math.ceil((x / (2 * lam)) ** 2 / alpha / chunk) for x in at}) for lam in lams]
+    res = [{"Ste": s, "lambda": lam, "t": [], "s": [], "s_neumann": [], "rel_err": []}
+           for s, lam in zip(stes, lams)]
+    t = 0
+    while t < max(w[-1] for w in when):
+        b.step(chunk)
+        t += chunk
+        for k, lam in enumerate(lams):
+            if t in when[k]:
+                s = front(b.field(k, "fl")[:, 0])
+                ref = 2 * lam * math.sqrt(alpha * t)
+                r = res[k]
+                r["t"].append(t)
+                r["s"].append(s)
+                r["s_neumann"].append(ref)
+                r["rel_err"].append(abs(s - ref) / ref)
+    return res
+
+
+def final_height_sweep(stes=(0.2, 0.5), ratios=(0.9, 1.0, 1.1), h0: float = 16.0, ny: int = 48,
+                       chunk: int = 500, max_chunks: int = 60, precision: str = "fp64") -> list[dict]:
+    """Layers freezing completely; the material volume per column ends at rho_l/rho_s of its
+    start (h_f / h_0 = rho_l / rho_s)."""
+    from .lbm import Batch
+    grid = [(s, r) for s in stes for r in ratios]
+    cases = [inputs.stefan_strip(4, ny, h0=h0, Ste=s, rho_ratio_sl=r) for s, r in grid]
+    b = Batch(cases, precision=precision)
+    v0 = [b.field(k, "psi").clip(0, 1).sum() / 4 for k in range(len(grid))]
+    steps = 0
+    for _ in range(max_chunks):
+        b.step(chunk)
+        steps += chunk
+        if all(d["V_l"] < 1e-4 * d["V_l0"] for d in b.diag()):
+            break
+    ds = b.diag()
+    out = []
+    for k, (s, r) in enumerate(grid):
+        v1 = b.field(k, "psi").clip(0, 1).sum() / 4
+        out.append({"Ste": s, "rho_s_over_rho_l": r, "steps": steps,
+                    "liquid_left": ds[k]["V_l"] / ds[k]["V_l0"],
+                    "h_f_over_h_0": float(v1 / v0[k]), "closed_form": 1.0 / r})
+    return out
