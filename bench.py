@@ -295,10 +295,11 @@ def run_warm(steps=20, seed=6):
 
 
 def run_validation():
-    """The paper's validation problems (Sec. 4) as FP64 batches: the Fig. 5 deformation sweeps
-    (12 free drops, R0 = 20 in 160 x 160, 10,000 steps), the Neumann front at four Stefan
-    numbers and the final height of six freezing layers, with wall times and the largest
-    deviations from the closed forms."""
+    """The paper's validation problems (Sec. 4) and its electrofreezing study (Sec. 5) as FP64
+    batches: the Fig. 5 deformation sweeps (12 free drops, R0 = 20 in 160 x 160, 10,000 steps),
+    the Neumann front at four Stefan numbers, the final height of six freezing layers (with the
+    largest deviations from the closed forms), and 24 wetting drops frozen with and without
+    the field; wall time of each."""
     import torch
 
     from paper_2410_06657_amd import validation as v
@@ -327,6 +328,16 @@ def run_validation():
                            "max_rel_err": round(max(abs(r["h_f_over_h_0"] / r["closed_form"] - 1) for r in fh), 5)}
     print(f"[bench] validation: Stefan sweeps {out['neumann_front']['wall_s']}s + {out['final_height']['wall_s']}s",
           file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ps = v.parameter_study()
+    out["parameter_study"] = {
+        "workload": "24 sessile drops, R0=20 in 160x80, theta=120, modes none/PR+(2,0.5)/OB-(2,5)/PR-(5,9.5) at Ca_E=1, "
+                    "Ste in {0.05, 0.1, 0.2}, rho_s/rho_l in {0.9, 1.1}, each to its freezing time, FP64 batch",
+        "wall_s": round(time.perf_counter() - t0, 2),
+        "rows": [{"rho_s_over_rho_l": r["rho_s_over_rho_l"], "Ste": r["Ste"], "mode": r["mode"],
+                  "t_fre": round(r["t_fre"], 1), "H_m_over_H_0": round(r["H_m_over_H_0"], 4),
+                  "t_star": round(r["t_star"], 4)} for r in ps]}
+    print(f"[bench] validation: parameter study {out['parameter_study']['wall_s']}s", file=sys.stderr, flush=True)
     return out
 
 

@@ -7,8 +7,12 @@
   of a liquid at T_m on a substrate at -Ste, and the final height h_f = rho_l h_0 / rho_s of a
   layer that freezes completely.
 
-Freezing is off for the drops (T_w = T_g above T_m).  Inputs come from `inputs.free_drop` and
-`inputs.stefan_strip`.
+* The electrofreezing study of Sec. 5: a wetting drop (theta = 120 deg) frozen without a field
+  and in the PR+, OB- and PR- modes of its R-S diagram at several Stefan numbers and
+  solid/liquid density ratios: final heights and the relative change of the freezing time.
+
+Freezing is off for the free drops (T_w = T_g above T_m).  Inputs come from
+`inputs.free_drop`, `inputs.stefan_strip` and `inputs.sessile_drop`.
 """
 from __future__ import annotations
 
@@ -140,3 +144,42 @@ def final_height_sweep(stes=(0.2, 0.5), ratios=(0.9, 1.0, 1.1), h0: float = 16.0
                     "liquid_left": ds[k]["V_l"] / ds[k]["V_l0"],
                     "h_f_over_h_0": float(v1 / v0[k]), "closed_form": 1.0 / r})
     return out
+
+
+# Sec. 5: field modes of the wetting drop (R, S, Ca_E); "none" is the drop without a field
+MODES = {"none": (1.0, 1.0, 0.0), "PR+": (2.0, 0.5, 1.0), "OB-": (2.0, 5.0, 1.0), "PR-": (5.0, 9.5, 1.0)}
+
+
+def drop_height(psi: np.ndarray, case: dict) -> float:
+    """Height of the psi = 1/2 crossing on the drop's centre column above the substrate."""
+    col = psi[:, int(round(case["xc"]))]
+    b = int(np.where(col >= 0.5)[0][-1])
+    return b + (col[b] - 0.5) / (col[b] - col[b + 1]) + 0.5
+
+
+def parameter_study(stes=(0.05, 0.1, 0.2), ratios=(0.9, 1.1), nx: int = 160, ny: int = 80,
+                    R0: float = 20.0, theta: float = 120.0, precision: str = "fp64",
+                    max_steps: int = 100000) -> list[dict]:
+    """Sec. 5's electrofreezing study at theta = 120 deg, alpha_l/alpha_g = 0.2: every field
+    mode at every Stefan number and solid/liquid density ratio, run to its freezing time
+    (1% of the liquid left) as one batch.  Per case: t_fre, Fo = alpha_l t_fre / R0^2, the final
+    height H_m over the initial H_0, and t* = (t_fre - t_fre(no field)) / t_fre(no field)."""
+    from .lbm import Batch
+    keys = [(r, s, m) for r in ratios for s in stes for m in MODES]
+    cases = [inputs.sessile_drop(nx, ny, R0, theta, *MODES[m][:2], MODES[m][2], s, seed=None, rho_ratio_sl=r)
+             for r, s, m in keys]
+    b = Batch(cases, precision=precision)
+    h0 = [drop_height(b.field(k, "psi"), cases[k]) for k in range(len(keys))]
+    b.run_until_frozen(max_steps)
+    d = b.diag()
+    rows = []
+    for k, (r, s, m) in enumerate(keys):
+        alpha_l = cases[k]["k_l"] / (cases[k]["rho_l"] * cases[k]["cp_l"])
+        rows.append({"rho_s_over_rho_l": r, "Ste": s, "mode": m, "t_fre": d[k]["t_fre"],
+                     "Fo": alpha_l * d[k]["t_fre"] / R0 ** 2,
+                     "H_m_over_H_0": drop_height(b.field(k, "psi"), cases[k]) / h0[k]})
+    base = {(x["rho_s_over_rho_l"], x["Ste"]): x["t_fre"] for x in rows if x["mode"] == "none"}
+    for x in rows:
+        t0 = base[(x["rho_s_over_rho_l"], x["Ste"])]
+        x["t_star"] = (x["t_fre"] - t0) / t0
+    return rows

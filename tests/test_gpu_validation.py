@@ -88,3 +88,28 @@ def test_final_height_sweep():
               f"h_f/h_0 {r['h_f_over_h_0']:.4f} (closed form {r['closed_form']:.4f})")
         assert r["liquid_left"] < 1e-3, "layer did not freeze"
         assert r["h_f_over_h_0"] == pytest.approx(r["closed_form"], rel=0.01)
+
+
+def test_parameter_study():
+    """Sec. 5 at theta = 120 deg: no field, PR+ (2, 0.5), OB- (2, 5), PR- (5, 9.5) with Ca_E = 1,
+    Ste = 0.05, 0.1, 0.2, rho_s/rho_l = 0.9 and 1.1, each drop run to its freezing time.  What
+    the paper reports and this checks: without a field the drop ends taller than it started
+    when the solid is lighter and shorter when it is denser; the field makes the prolate PR+
+    drop end taller and the oblate drop shorter than without it; the oblate drop freezes
+    faster (t* < 0), by less as Ste grows, and the PR- drop slower (t* > 0).  Measured beside
+    it (not asserted): the PR+ time change is within 0.2% for rho_s/rho_l = 0.9."""
+    rows = validation.parameter_study()
+    by = {(x["rho_s_over_rho_l"], x["Ste"], x["mode"]): x for x in rows}
+    for x in rows:
+        print(f"rho {x['rho_s_over_rho_l']} Ste {x['Ste']} {x['mode']:>4}: t_fre {x['t_fre']:.0f} "
+              f"Fo {x['Fo']:.3f} H_m/H_0 {x['H_m_over_H_0']:.4f} t* {x['t_star']:+.4f}")
+    for r in (0.9, 1.1):
+        ob_mag = []
+        for s in (0.05, 0.1, 0.2):
+            h = {m: by[(r, s, m)]["H_m_over_H_0"] for m in validation.MODES}
+            assert (h["none"] > 1.0) if r < 1 else (h["none"] < 1.0)
+            assert h["PR+"] > h["none"] > h["OB-"]
+            assert by[(r, s, "OB-")]["t_star"] < 0
+            assert by[(r, s, "PR-")]["t_star"] > 0
+            ob_mag.append(-by[(r, s, "OB-")]["t_star"])
+        assert ob_mag[0] > ob_mag[-1]
