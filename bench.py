@@ -338,6 +338,13 @@ def run_validation():
                   "t_fre": round(r["t_fre"], 1), "H_m_over_H_0": round(r["H_m_over_H_0"], 4),
                   "t_star": round(r["t_star"], 4)} for r in ps]}
     print(f"[bench] validation: parameter study {out['parameter_study']['wall_s']}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    cw = v.cold_wall()
+    out["cold_wall"] = {
+        "workload": "water and hexadecane drops (Table 1 ratios), R0=20 in 160x80, theta=87, frozen completely, FP64 batch",
+        "wall_s": round(time.perf_counter() - t0, 2),
+        "rows": [{k: (round(float(x), 5) if isinstance(x, float) else x) for k, x in r.items()} for r in cw]}
+    print(f"[bench] validation: cold wall {out['cold_wall']['wall_s']}s", file=sys.stderr, flush=True)
     return out
 
 

@@ -7,6 +7,8 @@
   of a liquid at T_m on a substrate at -Ste, and the final height h_f = rho_l h_0 / rho_s of a
   layer that freezes completely.
 
+* Freezing of water and hexadecane drops on a cold wall with Table 1's property ratios (Sec. 4):
+  final volume against rho_l/rho_s, height, contact radius and apex shape.
 * The electrofreezing study of Sec. 5: a wetting drop (theta = 120 deg) frozen without a field
   and in the PR+, OB- and PR- modes of its R-S diagram at several Stefan numbers and
   solid/liquid density ratios: final heights and the relative change of the freezing time.
@@ -183,3 +185,63 @@ def parameter_study(stes=(0.05, 0.1, 0.2), ratios=(0.9, 1.1), nx: int = 160, ny:
         t0 = base[(x["rho_s_over_rho_l"], x["Ste"])]
         x["t_star"] = (x["t_fre"] - t0) / t0
     return rows
+
+
+# Table 1 (Sec. 4): water on a wall at -10 C and hexadecane on a wall 3 K below its melting
+# point, as the lattice groups they give: Stefan number, density, conductivity and heat
+# capacity ratios of solid to liquid
+COLD_WALL = {
+    "water": {"Ste": 4220 * 10 / 333400, "rho": 917 / 999, "k": 2.16 / 0.581, "cp": 2100 / 4220},
+    "hexadecane": {"Ste": 2310 * 3 / 230000, "rho": 833 / 774, "k": 0.15 / 0.15, "cp": 1800 / 2310},
+}
+
+
+def _apex_curvature(psi: np.ndarray, xc: float, half: int = 3) -> float:
+    """Second difference of the top surface h(x) at the drop's centre column (h from the
+    psi = 1/2 crossing of each column); a tip makes it large, a platform small."""
+    ic = int(round(xc))
+    hs = [drop_height(psi, {"xc": float(i)}) for i in range(ic - half, ic + half + 1, half)]
+    return (hs[0] - 2 * hs[1] + hs[2]) / half ** 2
+
+
+def contact_radius(psi: np.ndarray) -> float:
+    """Half the psi >= 1/2 extent of the first row above the substrate."""
+    return 0.5 * _span(psi[0, :])
+
+
+def cold_wall(nx: int = 160, ny: int = 80, R0: float = 20.0, theta: float = 87.0,
+              precision: str = "fp64", max_steps: int = 200000) -> list[dict]:
+    """Sec. 4's sessile-drop freezing with Table 1's property ratios (no experimental overlay:
+    those data are not available): each drop frozen completely as one batch; final material
+    volume, height, contact radius and apex curvature relative to the start."""
+    from .lbm import Batch
+    names = list(COLD_WALL)
+    cases = []
+    for n in names:
+        g = COLD_WALL[n]
+        c = inputs.sessile_drop(nx, ny, R0, theta, 1.0, 1.0, 0.0, g["Ste"], seed=None,
+                                rho_ratio_sl=g["rho"], k_ratio_sl=g["k"])
+        c["cp_s"] = g["cp"] * c["cp_l"]
+        cases.append(c)
+    b = Batch(cases, precision=precision)
+    start = []
+    for k, c in enumerate(cases):
+        psi = b.field(k, "psi")
+        start.append((psi.clip(0, 1).sum(), drop_height(psi, c), contact_radius(psi),
+                      _apex_curvature(psi, c["xc"])))
+    b.run_until_frozen(max_steps)
+    t_fre = [d["t_fre"] for d in b.diag()]
+    steps = 0
+    while steps < max_steps and not all(d["V_l"] < 1e-4 * d["V_l0"] for d in b.diag()):
+        b.step(500)
+        steps += 500
+    out = []
+    for k, (n, c) in enumerate(zip(names, cases)):
+        psi = b.field(k, "psi")
+        v0, h0, r0, a0 = start[k]
+        out.append({"liquid": n, "Ste": COLD_WALL[n]["Ste"], "rho_s_over_rho_l": COLD_WALL[n]["rho"],
+                    "t_fre": t_fre[k], "volume_ratio": float(psi.clip(0, 1).sum() / v0),
+                    "closed_form_volume_ratio": 1.0 / COLD_WALL[n]["rho"],
+                    "H_m_over_H_0": drop_height(psi, c) / h0, "R_tr_over_R_0": contact_radius(psi) / r0,
+                    "apex_curvature": _apex_curvature(psi, c["xc"]), "apex_curvature_start": a0})
+    return out

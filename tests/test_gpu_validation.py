@@ -113,3 +113,19 @@ def test_parameter_study():
             assert by[(r, s, "PR-")]["t_star"] > 0
             ob_mag.append(-by[(r, s, "OB-")]["t_star"])
         assert ob_mag[0] > ob_mag[-1]
+
+
+def test_cold_wall_freezing():
+    """Sec. 4's drop freezing on a cold wall with Table 1's ratios (theta = 87 deg; water:
+    Ste = 0.127, rho_s/rho_l = 0.918, k_s/k_l = 3.72; hexadecane: Ste = 0.030, rho_s/rho_l =
+    1.076), each frozen completely.  The material volume ends at rho_l/rho_s of its start within
+    1.5% (measured -1.1% and +0.7%); the water drop ends taller with a sharper apex (the tip the
+    paper describes) and the hexadecane drop shorter with a flatter top (its platform)."""
+    res = {r["liquid"]: r for r in validation.cold_wall()}
+    for r in res.values():
+        print({k: (round(float(x), 4) if isinstance(x, float) else x) for k, x in r.items()})
+        assert r["volume_ratio"] == pytest.approx(r["closed_form_volume_ratio"], rel=0.015)
+    w, h = res["water"], res["hexadecane"]
+    assert w["H_m_over_H_0"] > 1.05 and h["H_m_over_H_0"] < 0.95
+    assert abs(w["apex_curvature"]) > 1.15 * abs(w["apex_curvature_start"])
+    assert abs(h["apex_curvature"]) < abs(h["apex_curvature_start"])
