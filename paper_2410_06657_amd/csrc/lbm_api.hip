@@ -421,8 +421,7 @@ int one_step(lbm_handle* h) {
     // stages 3-4 and the volume sum, gated on the loop's end and reading its final buffer
     // from the control block; queued behind every test of the loop (see run_sweeps)
     const std::function<void()> tail = [&]() {
-        lbm::k_h_prep1<R><<<h->nb, NT, 0, st>>>(d, s, sp, -1);
-        lbm::k_h_prep2<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_h_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp, -1);
         lbm::k_h_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
         lbm::k_g_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
         lbm::k_vl_finalize<<<1, NT, 0, st>>>(d, h->partials, h->dctl, 0, 1);

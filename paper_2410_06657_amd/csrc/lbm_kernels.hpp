@@ -896,19 +896,30 @@ __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) 
 // Stage 3a: surface tension (Eqs. (3)-(5)) and electric force (Eq. (14)) with
 // psi^{n+1}; S = rho mdot + u . grad(rho) (Eq. (24)).
 template <typename R>
-__device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int sp, int lcur, int i, int j,
-                                           int64_t n, const R (&vp)[3][3], const R (&vf)[3][3], R& FxOut,
-                                           R& FyOut) {
+__device__ __forceinline__ void rho_mix3(const Dev& d, const R (&vp)[3][3], const R (&vf)[3][3], R (&vr)[3][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) vr[a][b] = mix<R>(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
+}
+// S = rho mdot + u . grad(rho) at node m, vr the density around it.
+template <typename R>
+__device__ __forceinline__ R source_S(const State<R>& s, int sp, int64_t m, const R (&vr)[3][3]) {
+    R grx, gry, dum;
+    grad_lap<R>(vr, grx, gry, dum);
+    return vr[1][1] * s.md[sp][m] + s.ux[sp][m] * grx + s.uy[sp][m] * gry;
+}
+// F = F_s + F_e at node (i, j) from psi, f_s and rho around it (written to Fx, Fy).
+template <typename R>
+__device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int lcur, int i, int j, int64_t n,
+                                           const R (&vp)[3][3], const R (&vf)[3][3], R& FxOut, R& FyOut) {
     const R* phi = s.phi[lcur];
-    R vph[3][3], ve[3][3], vr[3][3];
+    R vph[3][3], ve[3][3];
     load3<GPHI, R>(phi, d, i, j, vph);
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            ve[a][b] = mix<R>(d.eps_s, d.eps_l, d.eps_g, vp[a][b], vf[a][b]);
-            vr[a][b] = mix<R>(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
-        }
+        for (int b = 0; b < 3; b++) ve[a][b] = mix<R>(d.eps_s, d.eps_l, d.eps_g, vp[a][b], vf[a][b]);
     R gx, gy, lap;
     grad_lap<R>(vp, gx, gy, lap);
     R ps = vp[1][1];
@@ -927,9 +938,6 @@ __device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int 
     s.Fy[n] = Fy;
     FxOut = Fx;
     FyOut = Fy;
-    R grx, gry;
-    grad_lap<R>(vr, grx, gry, dum);
-    s.S[n] = vr[1][1] * s.md[sp][n] + s.ux[sp][n] * grx + s.uy[sp][n] * gry;
 }
 template <typename R>
 __device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
@@ -937,10 +945,12 @@ __device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int s
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    R vp[3][3], vf[3][3], Fx, Fy;
+    R vp[3][3], vf[3][3], vr[3][3], Fx, Fy;
     load3<GWET, R>(s.psi[sp ^ 1], d, i, j, vp);
     load3<GMIRROR, R>(s.fs[sp], d, i, j, vf);
-    h_prep1_at<R>(d, s, sp, lcur, i, j, n, vp, vf, Fx, Fy);
+    h_prep1_at<R>(d, s, lcur, i, j, n, vp, vf, Fx, Fy);
+    rho_mix3<R>(d, vp, vf, vr);
+    s.S[n] = source_S<R>(s, sp, n, vr);
 }
 // Stage kernels queued behind a potential loop before the host knows its outcome are gated:
 // they run only if the loop has ended (else the host queues them again once it has), and
@@ -955,23 +965,17 @@ __global__ void __launch_bounds__(NT) k_h_prep1(Dev d, State<R> s, int sp, int l
 }
 
 // Stage 3b: collision inputs of h: rho, F~, F + rho f_solid, 1/tau_h.
+// vs: S around the node (read only under the grad S reading).
 template <typename R>
 __device__ __forceinline__ void h_prep2_at(const Dev& d, const State<R>& s, int sp, int i, int j, int64_t n,
-                                           const R (&vp)[3][3], const R (&vf)[3][3], R Fx, R Fy) {
-    R vr[3][3], vpr[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-        for (int b = 0; b < 3; b++) vr[a][b] = mix<R>(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
+                                           const R (&vp)[3][3], const R (&vf)[3][3], const R (&vr)[3][3],
+                                           const R (&vs)[3][3], R Fx, R Fy) {
+    R vpr[3][3];
     load3<GMIRROR, R>(s.p[sp], d, i, j, vpr);
     R grx, gry, gpx, gpy, gsx = R(0), gsy = R(0), dum;
     grad_lap<R>(vr, grx, gry, dum);
     grad_lap<R>(vpr, gpx, gpy, dum);
-    if (d.readings & 1u) {
-        R vs[3][3];
-        load3<GMIRROR, R>(s.S, d, i, j, vs);
-        grad_lap<R>(vs, gsx, gsy, dum);
-    }
+    if (d.readings & 1u) grad_lap<R>(vs, gsx, gsy, dum);
     R rho = vr[1][1];
     R fsn = vf[1][1];
     s.rho[n] = rho;
@@ -988,16 +992,86 @@ __device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int s
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     int64_t n = at(d, i, j);
-    R vp[3][3], vf[3][3];
+    R vp[3][3], vf[3][3], vr[3][3], vs[3][3];
     load3<GWET, R>(s.psi[sp ^ 1], d, i, j, vp);
     load3<GMIRROR, R>(s.fs[sp], d, i, j, vf);
-    h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, s.Fx[n], s.Fy[n]);
+    rho_mix3<R>(d, vp, vf, vr);
+    if (d.readings & 1u) load3<GMIRROR, R>(s.S, d, i, j, vs);
+    h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, vr, vs, s.Fx[n], s.Fy[n]);
 }
 template <typename R>
 __global__ void __launch_bounds__(NT) k_h_prep2(Dev d, State<R> s, int sp, int gate) {
     if (gate && !s.ctl->done) return;
     b_h_prep2<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
+// Stages 3a and 3b in one pass.  The workgroup stages psi^{n+1}, f_s (wall ghosts applied) and
+// rho on its tile with a two-node ring (68 x 8) and S on the one-node ring (66 x 6) in LDS;
+// every node then takes its psi, f_s, rho and S neighbourhoods from there.  The arithmetic is
+// that of the two separate stages (the same expressions on the same values), so the results
+// are bitwise those of k_h_prep1 followed by k_h_prep2.
+constexpr int QX2 = TX + 4, QY2 = TY + 4, QN2 = QX2 * QY2;
+template <typename R>
+__device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
+    __shared__ R lps[QN2], lfs[QN2], lrho[QN2], lS[RN];
+    const int i0 = (tile % d.gx) * TX - 2, j0 = (tile / d.gx) * TY - 2;
+    const R* psi = s.psi[sp ^ 1];
+    const R* fs = s.fs[sp];
+    for (int k = threadIdx.x; k < QN2; k += NT) {
+        const int gj = j0 + k / QX2;
+        if (gj < -1 || gj > d.ny) continue;  // beyond the ghost rows: never read
+        int gi = (i0 + k % QX2) % d.nx;
+        if (gi < 0) gi += d.nx;
+        const R p = ghosted<GWET, R>(psi, d, gi, gj), f = ghosted<GMIRROR, R>(fs, d, gi, gj);
+        lps[k] = p;
+        lfs[k] = f;
+        lrho[k] = mix<R>(d.rho_s, d.rho_l, d.rho_g, p, f);
+    }
+    __syncthreads();
+    auto nb3 = [&](const R* a, int qx, int qy, R (&v)[3][3]) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+            for (int dx = -1; dx <= 1; dx++) v[dy + 1][dx + 1] = a[(qy + dy) * QX2 + qx + dx];
+    };
+    for (int k = threadIdx.x; k < RN; k += NT) {
+        const int rx = k % RX, ry = k / RX, gj = j0 + 1 + ry;
+        if (gj < 0 || gj >= d.ny) continue;
+        int gi = (i0 + 1 + rx) % d.nx;
+        if (gi < 0) gi += d.nx;
+        R vr[3][3];
+        nb3(lrho, rx + 1, ry + 1, vr);
+        lS[k] = source_S<R>(s, sp, at(d, gi, gj), vr);
+    }
+    __syncthreads();
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    const int64_t n = at(d, i, j);
+    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+    R vp[3][3], vf[3][3], vr[3][3], vs[3][3], Fx, Fy;
+    nb3(lps, tx + 2, ty + 2, vp);
+    nb3(lfs, tx + 2, ty + 2, vf);
+    nb3(lrho, tx + 2, ty + 2, vr);
+    // S around the node; beyond a wall the mirror ghost is the wall row's own value
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++) {
+        const int gj = j + dy, ry = (gj < 0 ? 0 : (gj >= d.ny ? d.ny - 1 : gj)) - (j0 + 1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) vs[dy + 1][dx + 1] = lS[ry * RX + tx + 1 + dx];
+    }
+    h_prep1_at<R>(d, s, lcur, i, j, n, vp, vf, Fx, Fy);
+    s.S[n] = lS[ring_self()];
+    h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, vr, vs, Fx, Fy);
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_h_prep(Dev d, State<R> s, int sp, int lcur) {
+    if (lcur < 0) {
+        if (!s.ctl->done) return;
+        lcur = s.ctl->final_buf;
+    }
+    b_h_prep<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 template <typename R>
 __device__ __forceinline__ HIn<R> h_inputs(const State<R>& s, int sp, int64_t m) {
     return HIn<R>{s.p[sp][m], s.rho[m], s.ux[sp][m], s.uy[sp][m], s.S[m],
