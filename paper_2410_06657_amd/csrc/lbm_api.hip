@@ -402,8 +402,7 @@ int one_step(lbm_handle* h) {
     State<R>& s = h->st<R>();
     const double tol = h->prm.poisson_tol;
     const int maxsw = h->prm.poisson_max_sweeps;
-    lbm::k_f_prep_arm<R><<<h->nb, NT, 0, st>>>(d, s, sp, tol, 1, maxsw);
-    lbm::k_f_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp);
+    lbm::k_f_fused_arm<R><<<h->nb, NT, 0, st>>>(d, s, sp, tol, 1, maxsw);
     LAUNCHCHK(h);
     if (h->wnn) {
         // warm start from the network: maps of the new psi (and f_s^n, as 1/tau_l uses)

@@ -183,6 +183,8 @@ __device__ __forceinline__ double fma_r(double a, double b, double c) { return _
 // origin (i0, j0), x wrapped (periodic); rows outside the grid stay unset (the pulls that
 // would read them take the wall conditions instead).  Every thread of the block takes part.
 constexpr int RX = TX + 2, RY = TY + 2, RN = RX * RY;
+// tile with a two-node ring (stencils of the one-node ring's nodes)
+constexpr int QX2 = TX + 4, QY2 = TY + 4, QN2 = QX2 * QY2;
 template <typename T, typename F>
 __device__ __forceinline__ void stage_ring(const Dev& d, int tile, T* ring, F&& load) {
     const int i0 = (tile % d.gx) * TX - 1, j0 = (tile / d.gx) * TY - 1;
@@ -432,15 +434,10 @@ __global__ void __launch_bounds__(NT) k_init(Dev d, State<R> s) {
 // ---------------------------------------------------------------------------
 // Stage 1a: A = d/dt(psi u) + c_s^2 lambda n at every node (Eqs. (19), (35)),
 // then remember psi^n u^n for the next step.
+// A at a node from psi^n around it (v), u^n and (psi u)^{n-1} there.  (psi u)^n itself is
+// stored for the next step by the g stage (k_g_stream), after every reader of the old value.
 template <typename R>
-__device__ __forceinline__ void b_f_prep(const Dev& d, const State<R>& s, int sp, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
-    int64_t n = at(d, i, j);
-    const R* psi = s.psi[sp];
-    R v[3][3];
-    load3<GWET, R>(psi, d, i, j, v);
+__device__ __forceinline__ void a_term(const Dev& d, const R (&v)[3][3], R ux, R uy, R pux, R puy, R& Ax, R& Ay) {
     R gx, gy, lap;
     grad_lap<R>(v, gx, gy, lap);
     R mag = sqrt(gx * gx + gy * gy);
@@ -451,35 +448,31 @@ __device__ __forceinline__ void b_f_prep(const Dev& d, const State<R>& s, int sp
     }
     R ps = v[1][1];
     R lam = R(4) * ps * (R(1) - ps) / R(d.W);
-    R ux = s.ux[sp][n], uy = s.uy[sp][n];
     R px = ps * ux, py = ps * uy;
-    s.Ax[n] = (px - s.pux[n]) + R(CS2) * lam * nx;
-    s.Ay[n] = (py - s.puy[n]) + R(CS2) * lam * ny;
-    s.pux[n] = px;
-    s.puy[n] = py;
+    Ax = (px - pux) + R(CS2) * lam * nx;
+    Ay = (py - puy) + R(CS2) * lam * ny;
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_f_prep(Dev d, State<R> s, int sp) {
-    b_f_prep<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
-}
-// The same, also arming the step's potential loop (one launch less per step).
-template <typename R>
-__global__ void __launch_bounds__(NT) k_f_prep_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
-                                                   int max_sweeps) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
-    b_f_prep<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+__device__ __forceinline__ void b_f_prep(const Dev& d, const State<R>& s, int sp, int tile) {
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    int64_t n = at(d, i, j);
+    R v[3][3];
+    load3<GWET, R>(s.psi[sp], d, i, j, v);
+    R Ax, Ay;
+    a_term<R>(d, v, s.ux[sp][n], s.uy[sp][n], s.pux[n], s.puy[n], Ax, Ay);
+    s.Ax[n] = Ax;
+    s.Ay[n] = Ay;
 }
 
 // Stage 1b: f pulled and collided at its source, half-way bounce-back at the
-// walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.
+// walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.  The collision
+// inputs of the tile and its ring are staged in LDS first (`ring`).
 template <typename R>
-__device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int sp, int tile) {
-    __shared__ FIn<R> ring[RN];
-    const R* psi = s.psi[sp];
-    const R* ux = s.ux[sp];
-    const R* uy = s.uy[sp];
+__device__ __forceinline__ void f_collide_stream(const Dev& d, const State<R>& s, int sp, int tile,
+                                                 const FIn<R>* ring) {
     const R* md = s.md[sp];
-    stage_ring(d, tile, ring, [&](int64_t m) { return FIn<R>{psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m]}; });
     int i, j;
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
@@ -510,8 +503,60 @@ __device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int 
     s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_f_stream(Dev d, State<R> s, int sp) {
-    b_f_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+__device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int sp, int tile) {
+    __shared__ FIn<R> ring[RN];
+    const R* psi = s.psi[sp];
+    const R* ux = s.ux[sp];
+    const R* uy = s.uy[sp];
+    const R* md = s.md[sp];
+    stage_ring(d, tile, ring, [&](int64_t m) { return FIn<R>{psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m]}; });
+    f_collide_stream<R>(d, s, sp, tile, ring);
+}
+
+// Stages 1a and 1b in one pass: psi^n (wall ghosts applied) is staged on the tile with a
+// two-node ring (68 x 8) in LDS, A is evaluated on the one-node ring from it (the same
+// expressions as k_f_prep), and the collision inputs of the ring go to LDS as in k_f_stream.
+// Bitwise the two-pass result.  The first block also arms the step's potential loop.
+template <typename R>
+__device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int sp, int tile) {
+    __shared__ R lps[QN2];
+    __shared__ FIn<R> ring[RN];
+    const int i0 = (tile % d.gx) * TX - 2, j0 = (tile / d.gx) * TY - 2;
+    const R* psi = s.psi[sp];
+    for (int k = threadIdx.x; k < QN2; k += NT) {
+        const int gj = j0 + k / QX2;
+        if (gj < -1 || gj > d.ny) continue;  // beyond the ghost rows: never read
+        int gi = (i0 + k % QX2) % d.nx;
+        if (gi < 0) gi += d.nx;
+        lps[k] = ghosted<GWET, R>(psi, d, gi, gj);
+    }
+    __syncthreads();
+    const R* ux = s.ux[sp];
+    const R* uy = s.uy[sp];
+    const R* md = s.md[sp];
+    for (int k = threadIdx.x; k < RN; k += NT) {
+        const int rx = k % RX, ry = k / RX, gj = j0 + 1 + ry;
+        if (gj < 0 || gj >= d.ny) continue;
+        int gi = (i0 + 1 + rx) % d.nx;
+        if (gi < 0) gi += d.nx;
+        const int64_t m = at(d, gi, gj);
+        R v[3][3];
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+            for (int dx = -1; dx <= 1; dx++) v[dy + 1][dx + 1] = lps[(ry + 1 + dy) * QX2 + rx + 1 + dx];
+        R Ax, Ay;
+        a_term<R>(d, v, ux[m], uy[m], s.pux[m], s.puy[m], Ax, Ay);
+        ring[k] = FIn<R>{v[1][1], ux[m], uy[m], Ax, Ay, md[m]};
+    }
+    __syncthreads();
+    f_collide_stream<R>(d, s, sp, tile, ring);
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
+                                                    int max_sweeps) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
+    b_f_fused<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // 1/tau_l = 1/(sigma/c_s^2 + 1/2) from the current psi and f_s (Sec. 3.4).
@@ -952,17 +997,6 @@ __device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int s
     rho_mix3<R>(d, vp, vf, vr);
     s.S[n] = source_S<R>(s, sp, n, vr);
 }
-// Stage kernels queued behind a potential loop before the host knows its outcome are gated:
-// they run only if the loop has ended (else the host queues them again once it has), and
-// take the final potential buffer from the control block (lcur < 0).
-template <typename R>
-__global__ void __launch_bounds__(NT) k_h_prep1(Dev d, State<R> s, int sp, int lcur) {
-    if (lcur < 0) {
-        if (!s.ctl->done) return;
-        lcur = s.ctl->final_buf;
-    }
-    b_h_prep1<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
-}
 
 // Stage 3b: collision inputs of h: rho, F~, F + rho f_solid, 1/tau_h.
 // vs: S around the node (read only under the grad S reading).
@@ -999,17 +1033,11 @@ __device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int s
     if (d.readings & 1u) load3<GMIRROR, R>(s.S, d, i, j, vs);
     h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, vr, vs, s.Fx[n], s.Fy[n]);
 }
-template <typename R>
-__global__ void __launch_bounds__(NT) k_h_prep2(Dev d, State<R> s, int sp, int gate) {
-    if (gate && !s.ctl->done) return;
-    b_h_prep2<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
-}
 // Stages 3a and 3b in one pass.  The workgroup stages psi^{n+1}, f_s (wall ghosts applied) and
 // rho on its tile with a two-node ring (68 x 8) and S on the one-node ring (66 x 6) in LDS;
 // every node then takes its psi, f_s, rho and S neighbourhoods from there.  The arithmetic is
 // that of the two separate stages (the same expressions on the same values), so the results
 // are bitwise those of k_h_prep1 followed by k_h_prep2.
-constexpr int QX2 = TX + 4, QY2 = TY + 4, QN2 = QX2 * QY2;
 template <typename R>
 __device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     __shared__ R lps[QN2], lfs[QN2], lrho[QN2], lS[RN];
@@ -1063,6 +1091,9 @@ __device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp
     s.S[n] = lS[ring_self()];
     h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, vr, vs, Fx, Fy);
 }
+// Stage kernels queued behind a potential loop before the host knows its outcome are gated:
+// they run only if the loop has ended (else the host queues them again once it has), and
+// take the final potential buffer from the control block (lcur < 0).
 template <typename R>
 __global__ void __launch_bounds__(NT) k_h_prep(Dev d, State<R> s, int sp, int lcur) {
     if (lcur < 0) {
@@ -1194,6 +1225,10 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
             s.hb[n] = hn;
         }
         R fsn = clamp01(ps) * (R(1) - fl);
+        // (psi u)^n for the next step's A (its readers in this step have all run)
+        const R pn = s.psi[sp][n];
+        s.pux[n] = pn * s.ux[sp][n];
+        s.puy[n] = pn * s.uy[sp][n];
         s.H[sp ^ 1][n] = Hn;
         s.T[sp ^ 1][n] = T;
         s.fl[n] = fl;
