@@ -515,7 +515,7 @@ __device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int 
 
 // Stages 1a and 1b in one pass: psi^n (wall ghosts applied) is staged on the tile with a
 // two-node ring (68 x 8) in LDS, A is evaluated on the one-node ring from it (the same
-// expressions as k_f_prep), and the collision inputs of the ring go to LDS as in k_f_stream.
+// expressions as b_f_prep), and the collision inputs of the ring go to LDS as in b_f_stream.
 // Bitwise the two-pass result.  The first block also arms the step's potential loop.
 template <typename R>
 __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int sp, int tile) {
@@ -1037,7 +1037,7 @@ __device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int s
 // rho on its tile with a two-node ring (68 x 8) and S on the one-node ring (66 x 6) in LDS;
 // every node then takes its psi, f_s, rho and S neighbourhoods from there.  The arithmetic is
 // that of the two separate stages (the same expressions on the same values), so the results
-// are bitwise those of k_h_prep1 followed by k_h_prep2.
+// are bitwise those of b_h_prep1 followed by b_h_prep2 (the batched form runs those).
 template <typename R>
 __device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     __shared__ R lps[QN2], lfs[QN2], lrho[QN2], lS[RN];
