@@ -558,46 +558,60 @@ R* pop_ptr(lbm_handle* h, int set, int* nq, Offset* off) {
 }
 
 // Offset added to stored values of plane q to give raw values (base: per node).
+// Host copies of pitched planes go through one contiguous block (rows x pitch elements, the
+// planes follow each other without gaps): the stream is drained, then a blocking 1-D copy.
+// (Pitched 2-D copies returned zeros while a kernel tracer was attached.)
+template <typename R>
+int block_to_host(lbm_handle* h, std::vector<R>& blk, const R* dev, size_t elems) {
+    blk.resize(elems);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(blk.data(), dev, elems * sizeof(R), hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+template <typename R>
+int block_to_dev(lbm_handle* h, R* dev, const std::vector<R>& blk) {
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(dev, blk.data(), blk.size() * sizeof(R), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
 template <typename R>
 int copy_planes(lbm_handle* h, R* dev, double* host, int planes, bool to_host, Offset off) {
     const Dev& d = h->dev;
-    size_t w = (size_t)d.nx * sizeof(R);
-    size_t dp = (size_t)d.pitch * sizeof(R);
-    size_t rows = (size_t)d.ny * planes;
-    size_t per = (size_t)d.nx * d.ny;
-    std::vector<R> stage(per * planes);
+    const size_t nx = (size_t)d.nx, pitch = (size_t)d.pitch, ny = (size_t)d.ny;
+    const size_t per = nx * ny;
     // OFF_G: one enthalpy base plane (applies to H and to the rest link of g);
     // OFF_BASE: one base plane per potential link
     std::vector<R> base;
-    size_t bplanes = off == OFF_BASE ? (size_t)planes : 1;
+    const size_t bplanes = off == OFF_BASE ? (size_t)planes : 1;
     R* bp = off == OFF_BASE ? h->st<R>().lb : h->st<R>().hb;
     if (off == OFF_G || (off == OFF_BASE && to_host)) {
-        base.resize(per * bplanes);
-        HIPCHK(h, hipMemcpy2DAsync(base.data(), w, bp, dp, w, (size_t)d.ny * bplanes, hipMemcpyDeviceToHost,
-                                   h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
+        int rc = block_to_host<R>(h, base, bp, ny * pitch * bplanes);
+        if (rc) return rc;
     }
+    // element k = (plane, j, i) of the host array -> pitched index
+    auto pidx = [&](size_t k) { return (k / nx) * pitch + k % nx; };
     auto offset = [&](size_t k) -> double {
-        if (off == OFF_G) return (planes == 1 || k < per) ? (double)base[k % per] : 0.0;
-        if (off == OFF_BASE) return (double)base[k];
+        if (off == OFF_G) return (planes == 1 || k < per) ? (double)base[pidx(k % per)] : 0.0;
+        if (off == OFF_BASE) return (double)base[pidx(k)];
         return 0.0;
     };
+    std::vector<R> blk;
+    int rc = block_to_host<R>(h, blk, dev, ny * pitch * planes);
+    if (rc) return rc;
     if (to_host) {
-        HIPCHK(h, hipMemcpy2DAsync(stage.data(), w, dev, dp, w, rows, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        for (size_t k = 0; k < per * planes; k++) host[k] = (double)stage[k] + offset(k);
-    } else {
-        if (off == OFF_BASE) {
-            // a written link becomes the pair (fl(v), fl(v - fl(v)))
-            base.resize(per * bplanes);
-            for (size_t k = 0; k < per * planes; k++) base[k] = (R)host[k];
-            HIPCHK(h, hipMemcpy2DAsync(bp, dp, base.data(), w, w, rows, hipMemcpyHostToDevice, h->stream));
-        }
-        for (size_t k = 0; k < per * planes; k++) stage[k] = (R)(host[k] - offset(k));
-        HIPCHK(h, hipMemcpy2DAsync(dev, dp, stage.data(), w, w, rows, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (size_t k = 0; k < per * planes; k++) host[k] = (double)blk[pidx(k)] + offset(k);
+        return LBM_OK;
     }
-    return LBM_OK;
+    if (off == OFF_BASE) {
+        // a written link becomes the pair (fl(v), fl(v - fl(v)))
+        base.assign(ny * pitch * bplanes, R(0));
+        for (size_t k = 0; k < per * planes; k++) base[pidx(k)] = (R)host[k];
+        rc = block_to_dev<R>(h, bp, base);
+        if (rc) return rc;
+    }
+    for (size_t k = 0; k < per * planes; k++) blk[pidx(k)] = (R)(host[k] - offset(k));
+    return block_to_dev<R>(h, dev, blk);
 }
 
 template <typename R>
@@ -809,8 +823,8 @@ int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
         std::memcpy(out, &w, sizeof w);
         out += sizeof w;
     }
-    HIPCHK(h, hipMemcpyAsync(out, h->ws, hd.ws_bytes, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(out, h->ws, hd.ws_bytes, hipMemcpyDeviceToHost));
     *bytes = need;
     return LBM_OK;
 }
@@ -833,8 +847,8 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
         in += sizeof w;
         log[k] = w;
     }
-    HIPCHK(h, hipMemcpyAsync(h->ws, in, ws, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(h->ws, in, ws, hipMemcpyHostToDevice));
     h->sp = hd.sp;
     h->lcur = hd.lcur;
     h->kprev = hd.kprev;

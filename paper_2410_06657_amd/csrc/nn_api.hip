@@ -245,7 +245,9 @@ int lbm_nn_set_params(lbm_nn* nnh, const float* host) {
         for (int o = 0; o < nn::CH; o++)
             if (!nn::b_real(l, o)) v[nn::WTOTAL + l * nn::CH + o] = 0.f;
     }
-    NNCHK(nnh, hipMemcpyAsync(nnh->p, v.data(), sizeof(float) * nn::PTOTAL, hipMemcpyHostToDevice, nnh->stream));
+    // pageable source that ends with this call: drain the stream, then a blocking copy
+    NNCHK(nnh, hipStreamSynchronize(nnh->stream));
+    NNCHK(nnh, hipMemcpy(nnh->p, v.data(), sizeof(float) * nn::PTOTAL, hipMemcpyHostToDevice));
     NNCHK(nnh, hipMemsetAsync(nnh->mo, 0, sizeof(float) * nn::PTOTAL, nnh->stream));
     NNCHK(nnh, hipMemsetAsync(nnh->ve, 0, sizeof(float) * nn::PTOTAL, nnh->stream));
     nn::k_to_half<<<(nn::WTOTAL + 255) / 256, 256, 0, nnh->stream>>>(nnh->p, nnh->wh);
@@ -258,8 +260,9 @@ int lbm_nn_set_params(lbm_nn* nnh, const float* host) {
 int lbm_nn_get_params(lbm_nn* nnh, float* host) {
     if (!nnh) return LBM_ESTATE;
     if (!host) return LBM_EINVAL;
-    NNCHK(nnh, hipMemcpyAsync(host, nnh->p, sizeof(float) * nn::PTOTAL, hipMemcpyDeviceToHost, nnh->stream));
+    // pageable destination: drain the stream, then a blocking copy
     NNCHK(nnh, hipStreamSynchronize(nnh->stream));
+    NNCHK(nnh, hipMemcpy(host, nnh->p, sizeof(float) * nn::PTOTAL, hipMemcpyDeviceToHost));
     return LBM_OK;
 }
 
@@ -275,7 +278,8 @@ int lbm_nn_gradient(lbm_nn* nnh, const float* x, const float* t, int n, int h, i
     int rc = run_forward(nnh, x, nnh->y, n, h, w, nnh->stream);
     if (!rc) rc = run_backward(nnh, t, n, h, w, nnh->stream);
     if (rc) return rc;
-    NNCHK(nnh, hipMemcpyAsync(grad, nnh->g, sizeof(float) * nn::PTOTAL, hipMemcpyDeviceToHost, nnh->stream));
+    NNCHK(nnh, hipStreamSynchronize(nnh->stream));
+    NNCHK(nnh, hipMemcpy(grad, nnh->g, sizeof(float) * nn::PTOTAL, hipMemcpyDeviceToHost));
     return fetch_loss(nnh, loss ? loss : nnh->hloss);
 }
 
