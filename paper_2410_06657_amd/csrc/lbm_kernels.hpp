@@ -236,27 +236,30 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
         for (int w = 0; w < NT / 64; w++) r += sh[w];
     return r;
 }
-// N sums over a block of NW waves with one pair of barriers (sh holds NW * N doubles); each sum is
-// formed in the same order as block_sum.  Results are valid in thread 0, in v.
-template <int N, int NW = NT / 64>
-__device__ __forceinline__ void block_sum_n(double* v, double* sh) {
+// N sums over a block of NTH threads in a fixed order: every thread parks its N values in
+// sh[N][NTH]; G threads per value add fixed strided subsets, a butterfly over the G lanes
+// combines them, and the N sums land in thread 0's v.  sh holds N * NTH + N doubles.  (Cheaper
+// than N shuffle trees per wave: one LDS store per value and thread, one short butterfly.)
+template <int N, int NTH>
+__device__ __forceinline__ void block_sums_parked(double (&v)[N], double* sh) {
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < N; k++)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < N; k++) sh[k * NTH + t] = v[k];
     __syncthreads();
-    if (lane == 0)
+    constexpr int G0 = NTH / N, G = G0 < 64 ? G0 : 64;
+    static_assert((G & (G - 1)) == 0 && N * G <= NTH, "G lanes per value, within a wave");
+    if (t < N * G) {
+        const int k = t / G, p = t % G;
+        double sum = 0.0;
+        for (int q = p; q < NTH; q += G) sum += sh[k * NTH + q];
 #pragma unroll
-        for (int k = 0; k < N; k++) sh[wid * N + k] = v[k];
+        for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        if (p == 0) sh[N * NTH + k] = sum;
+    }
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (t == 0)
 #pragma unroll
-        for (int k = 0; k < N; k++) {
-            double r = 0.0;
-            for (int w = 0; w < NW; w++) r += sh[w * N + k];
-            v[k] = r;
-        }
+        for (int k = 0; k < N; k++) v[k] = sh[N * NTH + k];
 }
 __device__ __forceinline__ double block_max(double v, double* sh) {
 #pragma unroll
@@ -629,7 +632,7 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
                 acc[2 * m] += pv[((int64_t)m * nbt + b) * 2];
                 acc[2 * m + 1] += pv[((int64_t)m * nbt + b) * 2 + 1];
             }
-    block_sum_n<2 * M, NW>(acc, sh);
+    block_sums_parked<2 * M, 64 * NW>(acc, sh);
     if (threadIdx.x != 0) return;
     Ctl* c = s.ctl;
     for (int m = 0; m < a.prev_nsw && m < M; m++) {
@@ -651,15 +654,20 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
 
 // The test of the previous launch (a.prev_*) is not made here: the launches carry extra
 // blocks for it (k_sweep_tb, kb_sweep).
+// Shared doubles a sweep workgroup (or the test block beside it) uses for its sums.
+template <int M, int WV>
+constexpr int SWEEP_SHM = 2 * M * 64 * WV + 2 * M;
+
 template <int M, typename R, int WV>
-__device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& ain, int tile) {
+__device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& ain, int tile,
+                                           double* accs) {
     // no implicit contraction: the fused operations are written out, so the result does not
     // depend on how the compiler unrolls the M sweeps (bitwise equal for every launch shape)
 #pragma clang fp contract(off)
     __shared__ R bup[2][WV][64], bdn[2][WV][64];
-    // each thread's FP64 residual sums of every sweep, parked here at the end of the sweep
+    // accs: each thread's FP64 residual sums of every sweep, parked at the end of the sweep
     // instead of in registers (16 accumulators would cost the kernel a wave per SIMD)
-    __shared__ double accs[2 * M][64 * WV];
+    constexpr int NTH = 64 * WV;
     const Ctl* c = s.ctl;
     SweepLaunch a = ain;
     if (a.devfix) {
@@ -783,8 +791,8 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                 accp = __builtin_fma(pr * rw[k], pr, accp);
                 PH[k] = ph;
             }
-            accs[2 * m][threadIdx.x] = ownx ? accd : 0.0;
-            accs[2 * m + 1][threadIdx.x] = ownx ? accp : 0.0;
+            accs[(2 * m) * NTH + threadIdx.x] = ownx ? accd : 0.0;
+            accs[(2 * m + 1) * NTH + threadIdx.x] = ownx ? accp : 0.0;
         }
         R* ld = s.l[a.dst];
         R* pd = s.phi[a.dst];
@@ -804,13 +812,13 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
         // block sums of the 2M parked values: G threads per value, each adding a fixed
         // strided subset, then a butterfly over the G lanes (a fixed order: reproducible)
         double* pw = s.partials + part_sweep(d.gx * d.gy, nbt, a.slot);
-        constexpr int NTH = 64 * WV, G0 = NTH / (2 * M), G = G0 < 64 ? G0 : 64;
+        constexpr int G0 = NTH / (2 * M), G = G0 < 64 ? G0 : 64;
         __syncthreads();
         const int t = threadIdx.x;
         if (t < 2 * M * G) {
             const int v = t / G, p = t % G;
             double sum = 0.0;
-            for (int q = p; q < NTH; q += G) sum += accs[v][q];
+            for (int q = p; q < NTH; q += G) sum += accs[v * NTH + q];
 #pragma unroll
             for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
             if (p == 0 && v / 2 < a.nsw) pw[((int64_t)(v / 2) * nbt + tile) * 2 + (v & 1)] = sum;
@@ -829,13 +837,13 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
 template <int M, typename R, int WV, int Tag = 0>
 __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)))
 k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
+    __shared__ double shm[SWEEP_SHM<M, WV>];
     const int nb = gridDim.x - 1;
     if ((int)blockIdx.x == nb) {
-        __shared__ double sh[WV * 2 * M];
-        if (a.prev_nsw > 0 && !a.devfix && !s.ctl->done) sweep_test<M, R, WV>(d, s, a, sh);
+        if (a.prev_nsw > 0 && !a.devfix && !s.ctl->done) sweep_test<M, R, WV>(d, s, a, shm);
         return;
     }
-    b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, nb));
+    b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, nb), shm);
 }
 
 // FP32 form: renormalise every link pair (b, l) by Knuth's two-sum, b' = fl(b + l) and
@@ -907,7 +915,7 @@ __global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s) {
 
 // One block: the convergence test of the last launch of a batch (same rule as above), with
 // 1024 threads so the partial sums of every tile are read in few rounds.
-constexpr int TEST_NT = 1024;
+constexpr int TEST_NT = 256;
 // The outcome is published to host memory the caller polls: two 64-bit words, each carrying
 // the sequence number `seq` in its upper half (the host waits for both), written with
 // system-scope atomic stores: word 0 = count, word 1 = fix_launch << 6 | fix_n << 2 |
@@ -915,7 +923,7 @@ constexpr int TEST_NT = 1024;
 template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a,
                                                         unsigned long long* word, unsigned seq) {
-    __shared__ double sh[TEST_NT / 64 * 2 * M];
+    __shared__ double sh[2 * M * TEST_NT + 2 * M];
     if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
     if (threadIdx.x != 0) return;
     // a.src: the solve's first buffer; the stage kernels that follow a loop read its final
@@ -1477,11 +1485,11 @@ __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)
     // the last ncases blocks test each case's previous launch while the others sweep (as
     // in the single-case launch: the test is off the critical path)
     const int ntiles = gridDim.x - ncases;
+    __shared__ double shm[SWEEP_SHM<M, WV>];
     if ((int)blockIdx.x >= ntiles) {
-        __shared__ double sh[WV * 2 * M];
         const BatchCase<R>& bc = cases[blockIdx.x - ntiles];
         SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x - ntiles], t);
-        if (a.nsw > 0 && a.prev_nsw > 0 && !bc.s.ctl->done) sweep_test<M, R, WV>(bc.d, bc.s, a, sh);
+        if (a.nsw > 0 && a.prev_nsw > 0 && !bc.s.ctl->done) sweep_test<M, R, WV>(bc.d, bc.s, a, shm);
         return;
     }
     int b = xcd_tile(blockIdx.x, ntiles);
@@ -1489,7 +1497,7 @@ __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)
     const BatchCase<R>& bc = cases[c];
     SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t);
     if (a.nsw == 0) return;
-    b_sweep_tb<M, R, WV>(bc.d, bc.s, a, b - first[c]);
+    b_sweep_tb<M, R, WV>(bc.d, bc.s, a, b - first[c], shm);
 }
 
 // Recomputation of each finished case's last launch up to its final sweep (fix[c].nsw = 0:
@@ -1499,17 +1507,18 @@ __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)
                                                         int ncases, const SweepLaunch* __restrict__ fix) {
     int b = xcd_tile(blockIdx.x, gridDim.x);
     int c = find_case(first, ncases, b);
+    __shared__ double shm[SWEEP_SHM<M, WV>];
     SweepLaunch a = fix[c];
     if (a.nsw == 0) return;
     const BatchCase<R>& bc = cases[c];
-    b_sweep_tb<M, R, WV>(bc.d, bc.s, a, b - first[c]);
+    b_sweep_tb<M, R, WV>(bc.d, bc.s, a, b - first[c], shm);
 }
 
 // One block per case: test the case's launch t (the last of a batch).
 template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) kb_sweep_test(const BatchCase<R>* __restrict__ cases,
                                                          const int* __restrict__ lcur0, int t) {
-    __shared__ double sh[TEST_NT / 64 * 2 * M];
+    __shared__ double sh[2 * M * TEST_NT + 2 * M];
     const BatchCase<R>& bc = cases[blockIdx.x];
     if (bc.s.ctl->done) return;
     SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x], t + 1);
