@@ -226,9 +226,9 @@ void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
 }
 
 template <typename R>
-void launch_test(lbm_handle* h, const lbm::SweepLaunch& a, unsigned seq) {
+void launch_test(lbm_handle* h, const lbm::SweepLaunch& a, unsigned seq, bool publish = true) {
     State<R>& s = h->st<R>();
-    unsigned long long* w = h->hword;
+    unsigned long long* w = publish ? h->hword : nullptr;
     switch (h->swm) {
         case 1: lbm::k_sweep_test<1, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
         case 2: lbm::k_sweep_test<2, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
@@ -282,8 +282,8 @@ template <typename R>
 int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid,
                bool armed = false, const std::function<void()>* tail = nullptr) {
     if (std::is_same<R, float>::value) {
-        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
-        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
+        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur, 0);
+        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), 0);
     }
     // armed: an earlier kernel of the step already reset the loop with these tol/min/max
     if (!armed) lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
@@ -304,9 +304,24 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     const bool rebasing = std::is_same<R, float>::value;
     for (;;) {
         for (int c = 0; c < nlaunch && next <= max_sweeps; c++) {
-            // FP32 batches end on rebase points, which sit at the same sweep counts for
-            // every sweeps-per-launch choice
-            if (rebasing && c > 0 && (next - 1) % lbm::REBASE_SWEEPS == 0) break;
+            // FP32 rebase points (the same sweep counts for every sweeps-per-launch choice):
+            // inside a batch, the launch just queued is tested first (nothing published) and
+            // the renormalisation and its constants run only if the loop goes on, so a rebase
+            // costs no host round trip; at the start of a later batch the loop is known to go on
+            if (rebasing && next > 1 && (next - 1) % lbm::REBASE_SWEEPS == 0) {
+                if (c > 0) {
+                    const lbm::SweepLaunch& last = plan.back();
+                    lbm::SweepLaunch mid{};
+                    mid.prev_k0 = last.k0;
+                    mid.prev_nsw = last.nsw;
+                    mid.prev_slot = last.slot;
+                    mid.launch = (int)plan.size();
+                    mid.src = lcur0;
+                    launch_test<R>(h, mid, 0, false);
+                }
+                lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), buf, 1);
+                lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), 1);
+            }
             lbm::SweepLaunch a{};
             int t = (int)plan.size();
             a.nsw = std::min(h->swm, max_sweeps + 1 - next);
@@ -349,11 +364,6 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
         int rc = wait_test(h, seq, &ls);
         if (rc) return rc;
         if (ls.done || next > max_sweeps) break;
-        // FP32: keep the stored links small during long solves
-        if (rebasing && (next - 1) % lbm::REBASE_SWEEPS == 0) {
-            lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), buf);
-            lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
-        }
         nlaunch = grow;
         grow = std::min(grow * 2, 256);
     }
@@ -480,8 +490,8 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
     HIPCHK(h, hipEventCreate(&a));
     HIPCHK(h, hipEventCreate(&b));
     if (std::is_same<R, float>::value) {
-        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur);
-        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>());
+        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur, 0);
+        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), 0);
     }
     lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, -1.0, 1, n);
     HIPCHK(h, hipEventRecord(a, h->stream));

@@ -870,7 +870,8 @@ __device__ __forceinline__ void b_rebase(const Dev& d, const State<R>& s, int lc
     }
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_rebase(Dev d, State<R> s, int lcur) {
+__global__ void __launch_bounds__(NT) k_rebase(Dev d, State<R> s, int lcur, int gate) {
+    if (gate && s.ctl->done) return;  // inside a loop: only while it runs
     b_rebase<R>(d, s, lcur, xcd_tile(blockIdx.x, gridDim.x));
 }
 
@@ -909,7 +910,8 @@ __device__ __forceinline__ void b_sweep_prep(const Dev& d, const State<R>& s, in
     s.pbp[n] = R(((b1 + b2) + (b3 + b4)) * INV_1MW0);
 }
 template <typename R>
-__global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s) {
+__global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s, int gate) {
+    if (gate && s.ctl->done) return;
     b_sweep_prep<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
@@ -925,7 +927,7 @@ __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, Sweep
                                                         unsigned long long* word, unsigned seq) {
     __shared__ double sh[2 * M * TEST_NT + 2 * M];
     if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0 || !word) return;  // no word: a test inside a batch, nothing published
     // a.src: the solve's first buffer; the stage kernels that follow a loop read its final
     // buffer from here
     if (s.ctl->done) {
