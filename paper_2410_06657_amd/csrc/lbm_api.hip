@@ -53,6 +53,7 @@ struct lbm_handle {
     unsigned long long* hword = nullptr;  // pinned coherent words the loop test publishes to
     unsigned seq = 0;         // sequence number of the last published test
     bool resid_stale = false; // last_resid not yet read back from the control block
+    bool vl_pending = false;  // the last step's liquid-volume sum not yet folded into the control block
     Ctl* dctl = nullptr;      // device control block
     double* partials = nullptr;
     std::string err;
@@ -205,7 +206,20 @@ size_t carve_bytes(const lbm_params* p, const Dev& d) {
 
 __global__ void k_ctl_zero(Ctl* c) { *c = Ctl{}; }
 
+// The last step's liquid-volume sum and freezing-time detector are folded into the control
+// block by the next step's first kernel; a reader of the control block before that gets them
+// from here.
+int flush_vl(lbm_handle* h) {
+    if (!h->vl_pending) return LBM_OK;
+    lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(h->dev, h->partials, h->dctl, 0, 0);
+    LAUNCHCHK(h);
+    h->vl_pending = false;
+    return LBM_OK;
+}
+
 int fetch_ctl(lbm_handle* h) {
+    int frc = flush_vl(h);
+    if (frc) return frc;
     HIPCHK(h, hipMemcpyAsync(h->hctl, h->dctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (h->resid_stale) {
@@ -412,7 +426,9 @@ int one_step(lbm_handle* h) {
     State<R>& s = h->st<R>();
     const double tol = h->prm.poisson_tol;
     const int maxsw = h->prm.poisson_max_sweeps;
-    lbm::k_f_fused_arm<R><<<h->nb, NT, 0, st>>>(d, s, sp, tol, 1, maxsw);
+    const int fin = h->vl_pending ? 1 : 0;
+    lbm::k_f_fused_arm<R><<<h->nb + fin, NT, 0, st>>>(d, s, sp, tol, 1, maxsw, fin);
+    h->vl_pending = false;
     LAUNCHCHK(h);
     if (h->wnn) {
         // warm start from the network: maps of the new psi (and f_s^n, as 1/tau_l uses)
@@ -433,7 +449,6 @@ int one_step(lbm_handle* h) {
         lbm::k_h_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp, -1);
         lbm::k_h_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
         lbm::k_g_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
-        lbm::k_vl_finalize<<<1, NT, 0, st>>>(d, h->partials, h->dctl, 0, 1);
     };
     int rc = run_sweeps<R>(h, tol, 1, maxsw, nullptr, nullptr, true, &tail);
     if (rc == LBM_ENOCONV)
@@ -441,6 +456,7 @@ int one_step(lbm_handle* h) {
     else if (rc)
         return rc;
     LAUNCHCHK(h);
+    h->vl_pending = true;
     h->sp ^= 1;
     h->step++;
     return LBM_OK;
@@ -478,6 +494,8 @@ int solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps, doub
 
 template <typename R>
 int diagnostics(lbm_handle* h) {
+    int frc = flush_vl(h);
+    if (frc) return frc;
     lbm::k_diag<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, h->lcur);
     lbm::k_diag_finalize<R><<<1, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp);
     LAUNCHCHK(h);
@@ -798,6 +816,10 @@ size_t ckpt_bytes(const lbm_handle* h) {
 int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
     if (!h) return LBM_ESTATE;
     if (!bytes) return LBM_EINVAL;
+    if (host) {
+        int frc = flush_vl(h);  // the image carries the control block complete
+        if (frc) return frc;
+    }
     if (h->resid_stale) {
         int rc = fetch_ctl(h);
         if (rc) return rc;
@@ -867,6 +889,7 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
     h->step = hd.step;
     h->last_resid = hd.last_resid;
     h->resid_stale = false;
+    h->vl_pending = false;
     h->log = std::move(log);
     return fetch_ctl(h);
 }

@@ -434,6 +434,34 @@ __global__ void __launch_bounds__(NT) k_init(Dev d, State<R> s) {
     b_init<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// The liquid volume of the state the g stage just wrote (its block partials, added in block
+// order) and the freezing-time detector: mode 1 records V_l0 after initialisation; mode 0
+// advances the step counter, and t_fre is the first step with V_l <= 1% of V_l0, interpolated
+// linearly.  sh: NT / 64 doubles.
+__device__ __forceinline__ void vl_finalize_body(const Dev& d, const double* partials, Ctl* c, int mode, double* sh) {
+    int nb = d.gx * d.gy;
+    const double* pv = partials + part_vl(nb);
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += NT) a += pv[k];
+    a = block_sum(a, sh);
+    if (threadIdx.x != 0) return;
+    if (mode == 1) {
+        c->V_l0 = a;
+        c->V_prev = a;
+        c->t_fre = -1.0;
+        c->step = 0;
+        return;
+    }
+    long long st = c->step + 1;
+    c->step = st;
+    double thr = 0.01 * c->V_l0;
+    if (c->t_fre < 0.0 && c->V_l0 > 0.0 && a <= thr) {
+        double dv = c->V_prev - a;
+        c->t_fre = (double)(st - 1) + (dv > 0.0 ? (c->V_prev - thr) / dv : 1.0);
+    }
+    c->V_prev = a;
+}
+
 // ---------------------------------------------------------------------------
 // Stage 1a: A = d/dt(psi u) + c_s^2 lambda n at every node (Eqs. (19), (35)),
 // then remember psi^n u^n for the next step.
@@ -555,11 +583,20 @@ __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int s
     __syncthreads();
     f_collide_stream<R>(d, s, sp, tile, ring);
 }
+// fin = 1: one extra block finishes the previous step's liquid-volume sum and freezing-time
+// detector meanwhile (a launch less per step; its fields of the control block are not the
+// loop's).
 template <typename R>
 __global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
-                                                    int max_sweeps) {
+                                                    int max_sweeps, int fin) {
+    const int nb = gridDim.x - fin;
+    if ((int)blockIdx.x >= nb) {
+        __shared__ double sh[NT / 64];
+        vl_finalize_body(d, s.partials, s.ctl, 0, sh);
+        return;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
-    b_f_fused<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+    b_f_fused<R>(d, s, sp, xcd_tile(blockIdx.x, nb));
 }
 
 // 1/tau_l = 1/(sigma/c_s^2 + 1/2) from the current psi and f_s (Sec. 3.4).
@@ -1262,27 +1299,7 @@ __global__ void __launch_bounds__(NT) k_g_stream(Dev d, State<R> s, int sp, int 
 __global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, const double* partials, Ctl* c, int mode, int gate) {
     __shared__ double sh[NT / 64];
     if (gate && !c->done) return;
-    int nb = d.gx * d.gy;
-    const double* pv = partials + part_vl(nb);
-    double a = 0.0;
-    for (int k = threadIdx.x; k < nb; k += NT) a += pv[k];
-    a = block_sum(a, sh);
-    if (threadIdx.x != 0) return;
-    if (mode == 1) {
-        c->V_l0 = a;
-        c->V_prev = a;
-        c->t_fre = -1.0;
-        c->step = 0;
-        return;
-    }
-    long long st = c->step + 1;
-    c->step = st;
-    double thr = 0.01 * c->V_l0;
-    if (c->t_fre < 0.0 && c->V_l0 > 0.0 && a <= thr) {
-        double dv = c->V_prev - a;
-        c->t_fre = (double)(st - 1) + (dv > 0.0 ? (c->V_prev - thr) / dv : 1.0);
-    }
-    c->V_prev = a;
+    vl_finalize_body(d, partials, c, mode, sh);
 }
 
 // Per-block liquid volume of the initial state (finalized by k_vl_finalize, mode 1).
