@@ -145,7 +145,12 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream,
    wetting) -> psi, rho, F_s -> potential swept to convergence -> phi, F_e ->
    h (collide, stream, bounce-back) -> u, p -> g (collide, stream, substrate at T_w)
    -> T, f_l, f_s.  Kernels run on the handle's stream; the host reads the
-   potential's convergence flag once per batch of sweeps.  A solve that hits the
+   potential's convergence flag once per batch of sweeps, and the rest of the step is
+   queued behind each batch's test before that read (it runs only once the loop has
+   ended), so the call returns with the last step's h and g stages possibly still
+   running.  The last step's liquid volume and freezing-time detector are folded in by
+   the next step's first kernel, or by any call that reads the control block
+   (lbm_diagnostics, lbm_run_until_frozen, lbm_checkpoint).  A solve that hits the
    sweep cap leaves a valid state and is counted in lbm_diag.noconv. */
 int lbm_step(lbm_handle* h, int n);
 
