@@ -1260,11 +1260,9 @@ void batch_stage(lbm_batch* b, int which, int sp) {
     auto tb = btable<R>(b);
     int nc = b->ncases;
     if (which == 0) {
-        lbm::kb_f_prep<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
-        lbm::kb_f_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_f_fused<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
     } else {
-        lbm::kb_h_prep1<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
-        lbm::kb_h_prep2<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_h_prep<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
         lbm::kb_h_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
         lbm::kb_g_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
         lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 0);

@@ -483,19 +483,6 @@ __device__ __forceinline__ void a_term(const Dev& d, const R (&v)[3][3], R ux, R
     Ax = (px - pux) + R(CS2) * lam * nx;
     Ay = (py - puy) + R(CS2) * lam * ny;
 }
-template <typename R>
-__device__ __forceinline__ void b_f_prep(const Dev& d, const State<R>& s, int sp, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
-    int64_t n = at(d, i, j);
-    R v[3][3];
-    load3<GWET, R>(s.psi[sp], d, i, j, v);
-    R Ax, Ay;
-    a_term<R>(d, v, s.ux[sp][n], s.uy[sp][n], s.pux[n], s.puy[n], Ax, Ay);
-    s.Ax[n] = Ax;
-    s.Ay[n] = Ay;
-}
 
 // Stage 1b: f pulled and collided at its source, half-way bounce-back at the
 // walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.  The collision
@@ -533,21 +520,11 @@ __device__ __forceinline__ void f_collide_stream(const Dev& d, const State<R>& s
     R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, pn, s.fs[sp][n]);
     s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
 }
-template <typename R>
-__device__ __forceinline__ void b_f_stream(const Dev& d, const State<R>& s, int sp, int tile) {
-    __shared__ FIn<R> ring[RN];
-    const R* psi = s.psi[sp];
-    const R* ux = s.ux[sp];
-    const R* uy = s.uy[sp];
-    const R* md = s.md[sp];
-    stage_ring(d, tile, ring, [&](int64_t m) { return FIn<R>{psi[m], ux[m], uy[m], s.Ax[m], s.Ay[m], md[m]}; });
-    f_collide_stream<R>(d, s, sp, tile, ring);
-}
 
 // Stages 1a and 1b in one pass: psi^n (wall ghosts applied) is staged on the tile with a
-// two-node ring (68 x 8) in LDS, A is evaluated on the one-node ring from it (the same
-// expressions as b_f_prep), and the collision inputs of the ring go to LDS as in b_f_stream.
-// Bitwise the two-pass result.  The first block also arms the step's potential loop.
+// two-node ring (68 x 8) in LDS, A (a_term) is evaluated on the one-node ring from it, and the
+// collision inputs of the ring go to LDS for f_collide_stream (the same arithmetic as
+// evaluating A at every node in a pass of its own; kept bitwise when it was fused).
 template <typename R>
 __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int sp, int tile) {
     __shared__ R lps[QN2];
@@ -1031,19 +1008,6 @@ __device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int 
     FxOut = Fx;
     FyOut = Fy;
 }
-template <typename R>
-__device__ __forceinline__ void b_h_prep1(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
-    int64_t n = at(d, i, j);
-    R vp[3][3], vf[3][3], vr[3][3], Fx, Fy;
-    load3<GWET, R>(s.psi[sp ^ 1], d, i, j, vp);
-    load3<GMIRROR, R>(s.fs[sp], d, i, j, vf);
-    h_prep1_at<R>(d, s, lcur, i, j, n, vp, vf, Fx, Fy);
-    rho_mix3<R>(d, vp, vf, vr);
-    s.S[n] = source_S<R>(s, sp, n, vr);
-}
 
 // Stage 3b: collision inputs of h: rho, F~, F + rho f_solid, 1/tau_h.
 // vs: S around the node (read only under the grad S reading).
@@ -1067,24 +1031,11 @@ __device__ __forceinline__ void h_prep2_at(const Dev& d, const State<R>& s, int 
     R mu = mix<R>(d.mu_s, d.mu_l, d.mu_g, vp[1][1], fsn);
     s.omh[n] = R(1) / (mu / (rho * R(CS2)) + R(0.5));
 }
-template <typename R>
-__device__ __forceinline__ void b_h_prep2(const Dev& d, const State<R>& s, int sp, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
-    int64_t n = at(d, i, j);
-    R vp[3][3], vf[3][3], vr[3][3], vs[3][3];
-    load3<GWET, R>(s.psi[sp ^ 1], d, i, j, vp);
-    load3<GMIRROR, R>(s.fs[sp], d, i, j, vf);
-    rho_mix3<R>(d, vp, vf, vr);
-    if (d.readings & 1u) load3<GMIRROR, R>(s.S, d, i, j, vs);
-    h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, vr, vs, s.Fx[n], s.Fy[n]);
-}
 // Stages 3a and 3b in one pass.  The workgroup stages psi^{n+1}, f_s (wall ghosts applied) and
 // rho on its tile with a two-node ring (68 x 8) and S on the one-node ring (66 x 6) in LDS;
 // every node then takes its psi, f_s, rho and S neighbourhoods from there.  The arithmetic is
-// that of the two separate stages (the same expressions on the same values), so the results
-// are bitwise those of b_h_prep1 followed by b_h_prep2 (the batched form runs those).
+// that of the two stages run one after the other (the same expressions on the same values;
+// bitwise equal to that when it was fused).
 template <typename R>
 __device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     __shared__ R lps[QN2], lfs[QN2], lrho[QN2], lS[RN];
@@ -1454,12 +1405,10 @@ __device__ __forceinline__ int find_case(const int* __restrict__ first, int ncas
 
 LBM_BATCHED(kb_init, b_init)
 LBM_BATCHED(kb_oml, b_oml, sp)
-LBM_BATCHED(kb_f_prep, b_f_prep, sp)
-LBM_BATCHED(kb_f_stream, b_f_stream, sp)
+LBM_BATCHED(kb_f_fused, b_f_fused, sp)
 LBM_BATCHED(kb_rebase, b_rebase, lcur[c])
 LBM_BATCHED(kb_sweep_prep, b_sweep_prep)
-LBM_BATCHED(kb_h_prep1, b_h_prep1, sp, lcur[c])
-LBM_BATCHED(kb_h_prep2, b_h_prep2, sp)
+LBM_BATCHED(kb_h_prep, b_h_prep, sp, lcur[c])
 LBM_BATCHED(kb_h_stream, b_h_stream, sp)
 LBM_BATCHED(kb_g_stream, b_g_stream, sp)
 LBM_BATCHED(kb_vl0, b_vl0)
