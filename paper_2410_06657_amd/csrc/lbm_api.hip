@@ -284,14 +284,15 @@ int wait_test(lbm_handle* h, unsigned seq, LoopState* out) {
     return LBM_OK;
 }
 
-// Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; block 0 of
+// Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; an extra block of
 // each launch tests every sweep of the previous launch, and each batch of launches ends
-// with a one-block test of its last launch, after which the host reads the flag.  The
+// with a one-block test of its last launch, after which the host reads the outcome.  The
 // first batch covers the previous solve's count, later batches double from one launch.
 // Launches queued after a test ended the loop exit at once.  If the final sweep is not
-// the last of its launch, that launch's sweeps up to it are
-// recomputed from its input (three buffers keep that input intact past the launches
-// that follow it in the batch, which all exit at once).
+// the last of its launch, that launch's sweeps up to it are recomputed from its input
+// (three buffers keep that input intact past the launches that follow it in the batch,
+// which all exit at once): by the host after it read the outcome, or, with `tail` (the
+// rest of a time step), on the device, queued with the tail behind every batch's test.
 template <typename R>
 int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid,
                bool armed = false, const std::function<void()>* tail = nullptr) {
@@ -309,8 +310,8 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     const int lcur0 = h->lcur;
     // first batch: enough launches for the previous solve's count, at most 256 (after a
     // solve that stopped at its cap the count says little about the next one).  A stop in
-    // the batch's last launch is seen by the batch-end test; a stop earlier is seen only at
-    // the end of the launch after it (the lagged test), which then ran in vain, so no spare
+    // the batch's last launch is seen by the batch-end test; a stop earlier is seen only
+    // during the launch after it (the lagged test), which then ran in vain, so no spare
     // launch is queued: a solve that needs more sweeps than the previous one pays a host
     // round trip and one more launch instead
     int nlaunch = h->kprev > 0 ? std::min(256, (h->kprev + h->swm - 1) / h->swm) : 1;
