@@ -603,9 +603,9 @@ __global__ void __launch_bounds__(NT) k_oml(Dev d, State<R> s, int sp) {
 // half-way anti-bounce-back at the electrodes; x is periodic (region columns wrap).
 // After m sweeps the outer m columns/rows of the region are stale, so a block writes only
 // its inner (64 - 2M) x (WV*SW_NPT - 2M) nodes.  For every sweep the block stores FP64 partial
-// sums of |phi^k - phi^{k-1}|^2 and |phi^k|^2 over the nodes it writes; block 0 of the next
-// launch adds them in block order and ends the loop at the first sweep that passes the
-// test (the host then recomputes that launch's sweeps up to it if it was not the last).
+// sums of |phi^k - phi^{k-1}|^2 and |phi^k|^2 over the nodes it writes; an extra block of
+// the next launch adds them in block order and ends the loop at the first sweep that passes
+// the test (that launch's sweeps up to it are then recomputed if it was not the last).
 constexpr int SW_NPT = 8;
 constexpr double INV_1MW0 = 1.0 / (1.0 - LW0);  // phi = (l_1 + l_2 + l_3 + l_4) / (1 - w_0), Eq. (34)
 
