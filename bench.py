@@ -23,11 +23,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # 1/tau_l and writes 4 links and phi (11 s); a step outside the sweeps moves 27 + 27
 # populations and 13 + 13 fields (80 s)
 SWEEP_ELEMS, STEP_ELEMS = 11, 80
-ELEM = {"fp64": 8, "fp32": 4}
+ELEM = {"fp64": 8, "fp32": 4, "fp16store": 4}
+# bytes per node of a step outside the sweeps; the FP16-storage form moves its 54 populations
+# as binary16 and its 26 field values as floats
+STEP_BYTES = {"fp64": STEP_ELEMS * 8, "fp32": STEP_ELEMS * 4, "fp16store": 54 * 2 + 26 * 4}
 # compulsory HBM bytes per node of one blocked launch (read once, written once, whatever the
 # number of sweeps): FP64 reads 4 links and 1/tau_l and writes 4 links and phi; FP32 reads 4
 # link remainders, 1/tau_l, the 4 pulled base increments and phi_B and writes 4 remainders and phi
-SWEEP_COMPULSORY = {"fp64": 10 * 8, "fp32": 15 * 4}
+SWEEP_COMPULSORY = {"fp64": 10 * 8, "fp32": 15 * 4, "fp16store": 15 * 4}
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_cfg2_counters.md")
@@ -157,7 +160,7 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name="cfg2
                 "avg_launch_us": round(launch_s * 1e6, 3), "sweeps_per_launch": m,
                 "algorithmic_bytes_per_launch": per_launch,
                 "compulsory_hbm_bytes_per_launch": SWEEP_COMPULSORY[precision] * n}
-    coupled_bytes = (STEP_ELEMS + SWEEP_ELEMS * kmean) * es * n
+    coupled_bytes = (STEP_BYTES[precision] + SWEEP_ELEMS * kmean * es) * n
     coupled_gbs = coupled_bytes / (ms_step * 1e-3) / 1e9
     return {
         "value": round(n * steps / dt / 1e6, 3), "ms_per_step": round(ms_step, 4),
@@ -350,7 +353,7 @@ def run_validation():
 
 def run_time_to_freeze(nbatch=8, max_steps=100000):
     """Time to freeze (R30) of the 128 x 64 sessile drop (R0 = 24, theta = 90, R = 3, S = 1,
-    Ca_E = 0.1, Ste = 0.1): FP64, FP32, FP64 with the learned warm start of the initial
+    Ca_E = 0.1, Ste = 0.1): FP64, FP32, FP32 with FP16 population storage, FP64 with the learned warm start of the initial
     potential, and `nbatch` seeds (centre jitter) in one FP32 batch against the same seeds one
     at a time.  Speedups are quoted with the freezing times they reach."""
     import torch
@@ -375,15 +378,19 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
     out = {"workload": "128x64 sessile drop, R0=24, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"}
     t64, f64, k64 = one(c, "fp64")
     t32, f32, _ = one(c, "fp32")
+    t16, f16, _ = one(c, "fp16store")
     f = warm.factor_for(64)
     net = warm.load((128 // f) * (64 // f))
     tw, fw, _ = one(c, "fp64", net, f)
     out["fp64"] = {"wall_s": round(t64, 3), "t_fre": f64, "steps": k64}
     out["fp32"] = {"wall_s": round(t32, 3), "t_fre": f32, "t_fre_rel_diff": abs(f32 - f64) / f64,
                    "speedup_vs_fp64": round(t64 / t32, 3)}
+    out["fp16store"] = {"wall_s": round(t16, 3), "t_fre": f16, "t_fre_rel_diff": abs(f16 - f64) / f64,
+                        "speedup_vs_fp64": round(t64 / t16, 3)}
     out["warm_fp64"] = {"wall_s": round(tw, 3), "t_fre": fw, "t_fre_rel_diff": abs(fw - f64) / f64,
                         "speedup_vs_fp64": round(t64 / tw, 3)}
-    print(f"[bench] time to freeze: fp64 {t64:.2f}s, fp32 {t32:.2f}s, warm {tw:.2f}s", file=sys.stderr, flush=True)
+    print(f"[bench] time to freeze: fp64 {t64:.2f}s, fp32 {t32:.2f}s, fp16 storage {t16:.2f}s, warm {tw:.2f}s",
+          file=sys.stderr, flush=True)
     cases = [inputs.cfg1(sd) for sd in range(nbatch)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -444,7 +451,7 @@ def main():
     ap.add_argument("--sweep-launches", type=int, default=100,
                     help="blocked sweep launches timed with HIP events for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 forms (FP32 and FP16 storage)")
     ap.add_argument("--sweep-block", type=int, default=0,
                     help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
@@ -488,6 +495,9 @@ def main():
         f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches, args.workload)
         f32["speedup_vs_fp64"] = round(f32["value"] / f64["value"], 3)
         line["forms"] = {"fp32": f32}
+        f16 = run_form(case, "fp16store", args.steps, args.warmup, args.sweep_launches, args.workload)
+        f16["speedup_vs_fp64"] = round(f16["value"] / f64["value"], 3)
+        line["forms"]["fp16store"] = f16
     if not args.no_time_to_freeze:
         line["time_to_freeze"] = run_time_to_freeze()
     if not args.no_validation:

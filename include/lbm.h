@@ -57,10 +57,17 @@ extern "C" {
    link and H stored relative to the liquid's latent heat rho_s L and the D2Q5 links and
    phi stored relative to the linear electrode ramp (their increments are below an FP32
    ulp of the raw values); FP64 is kept for the potential residual, the liquid and solid
-   volume sums, the freezing-time detector and the front search.  The ABI always
-   exchanges raw FP64 values. */
+   volume sums, the freezing-time detector and the front search.  FP32_FP16STORE: the
+   FP32 form with the f, h and g populations stored in binary16 as deviations from the
+   zero-velocity equilibria of their nodes' stored moments (Eqs. (18), (22), (29)), each set
+   scaled by a power of two that follows its largest deviation one step earlier; the
+   potential links keep the FP32 base/remainder pairs (a binary16 link could not resolve the
+   1e-8 stopping rule).  Single-case handles only (lbm_batch_init returns LBM_EINVAL), and
+   lbm_get_pop / lbm_set_pop return LBM_EINVAL for it.  The ABI always exchanges raw FP64
+   values. */
 #define LBM_FP64 0
 #define LBM_FP32 1
+#define LBM_FP32_FP16STORE 2
 
 /* Reading switches (bits of lbm_params.readings). */
 #define LBM_R_GRAD_S 1u /* F~ of Eq. (24) contains c_s^2 grad(S) (the printed "div S") */
@@ -69,7 +76,7 @@ extern "C" {
    Eq. (1) with psi clamped to [0, 1]. */
 typedef struct lbm_params {
     int nx, ny;
-    int precision;              /* LBM_FP64 or LBM_FP32 */
+    int precision;              /* LBM_FP64, LBM_FP32 or LBM_FP32_FP16STORE */
     double W, M, gamma;         /* interface width, mobility (Eq. (2a)), surface tension */
     double rho_l, rho_g, rho_s; /* densities */
     double mu_l, mu_g, mu_s;    /* dynamic viscosities */

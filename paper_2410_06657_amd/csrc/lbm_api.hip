@@ -72,7 +72,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int validate(const lbm_params* p) {
     if (!p) return LBM_EINVAL;
     if (p->nx < 2 || p->ny < 3 || (int64_t)p->nx * p->ny > (int64_t)1 << 31) return LBM_EINVAL;
-    if (p->precision != LBM_FP64 && p->precision != LBM_FP32) return LBM_EINVAL;
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP32_FP16STORE) return LBM_EINVAL;
     if (!(p->W > 0) || !(p->M > 0) || !(p->gamma >= 0)) return LBM_EINVAL;
     if (!(p->rho_l > 0) || !(p->rho_g > 0) || !(p->rho_s > 0)) return LBM_EINVAL;
     if (!(p->mu_l > 0) || !(p->mu_g > 0) || !(p->mu_s > 0)) return LBM_EINVAL;
@@ -157,16 +157,16 @@ struct Carver {
     }
 };
 
+// h16: the f, h and g sets in binary16 (the FP16-storage form; R = float).
 template <typename R>
-size_t carve(const Dev& d, char* base, State<R>* s) {
+size_t carve(const Dev& d, char* base, State<R>* s, bool h16 = false) {
     int nb = d.gx * d.gy, nbt = d.tbx * d.tby;
     Carver c{base};
     State<R> t{};
     size_t P = (size_t)d.plane;
     for (int b = 0; b < 2; b++) {
-        t.f[b] = c.take<R>(9 * P);
-        t.h[b] = c.take<R>(9 * P);
-        t.g[b] = c.take<R>(9 * P);
+        R** sets[] = {&t.f[b], &t.h[b], &t.g[b]};
+        for (R** q : sets) *q = h16 ? reinterpret_cast<R*>(c.take<lbm::half_t>(9 * P)) : c.take<R>(9 * P);
         t.psi[b] = c.take<R>(P); t.ux[b] = c.take<R>(P); t.uy[b] = c.take<R>(P); t.p[b] = c.take<R>(P);
         t.H[b] = c.take<R>(P); t.T[b] = c.take<R>(P); t.fs[b] = c.take<R>(P); t.md[b] = c.take<R>(P);
     }
@@ -190,7 +190,8 @@ size_t carve(const Dev& d, char* base, State<R>* s) {
 }
 
 size_t carve_bytes(const lbm_params* p, const Dev& d) {
-    return p->precision == LBM_FP32 ? carve<float>(d, nullptr, nullptr) : carve<double>(d, nullptr, nullptr);
+    return p->precision == LBM_FP64 ? carve<double>(d, nullptr, nullptr)
+                                    : carve<float>(d, nullptr, nullptr, p->precision == LBM_FP32_FP16STORE);
 }
 
 #define HIPCHK(h, x)                                      \
@@ -419,7 +420,7 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     return LBM_OK;
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int one_step(lbm_handle* h) {
     const Dev& d = h->dev;
     int sp = h->sp;
@@ -428,7 +429,7 @@ int one_step(lbm_handle* h) {
     const double tol = h->prm.poisson_tol;
     const int maxsw = h->prm.poisson_max_sweeps;
     const int fin = h->vl_pending ? 1 : 0;
-    lbm::k_f_fused_arm<R><<<h->nb + fin, NT, 0, st>>>(d, s, sp, tol, 1, maxsw, fin);
+    lbm::k_f_fused_arm<R, H><<<h->nb + fin, NT, 0, st>>>(d, s, sp, tol, 1, maxsw, fin);
     h->vl_pending = false;
     LAUNCHCHK(h);
     if (h->wnn) {
@@ -448,8 +449,8 @@ int one_step(lbm_handle* h) {
     // from the control block; queued behind every test of the loop (see run_sweeps)
     const std::function<void()> tail = [&]() {
         lbm::k_h_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp, -1);
-        lbm::k_h_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
-        lbm::k_g_stream<R><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_h_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_g_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
     };
     int rc = run_sweeps<R>(h, tol, 1, maxsw, nullptr, nullptr, true, &tail);
     if (rc == LBM_ENOCONV)
@@ -463,12 +464,12 @@ int one_step(lbm_handle* h) {
     return LBM_OK;
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int init_state(lbm_handle* h) {
     const Dev& d = h->dev;
     State<R>& s = h->st<R>();
     k_ctl_zero<<<1, 1, 0, h->stream>>>(h->dctl);
-    lbm::k_init<R><<<h->nb, NT, 0, h->stream>>>(d, s);
+    lbm::k_init<R, H><<<h->nb, NT, 0, h->stream>>>(d, s);
     lbm::k_oml<R><<<h->nb, NT, 0, h->stream>>>(d, s, 0);
     LAUNCHCHK(h);
     if (h->prm.skip_initial_solve) {
@@ -493,11 +494,11 @@ int solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps, doub
     return run_sweeps<R>(h, tol, 1, max_sweeps, sweeps, resid);
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int diagnostics(lbm_handle* h) {
     int frc = flush_vl(h);
     if (frc) return frc;
-    lbm::k_diag<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, h->lcur);
+    lbm::k_diag<R, H><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp, h->lcur);
     lbm::k_diag_finalize<R><<<1, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->sp);
     LAUNCHCHK(h);
     return fetch_ctl(h);
@@ -562,7 +563,7 @@ R* field_ptr(lbm_handle* h, int field, Offset* off) {
         case LBM_USY: return s.usy;
         case LBM_P: return s.p[sp];
         case LBM_T: return s.T[sp];
-        case LBM_H: *off = h->prec == LBM_FP32 ? OFF_G : OFF_NONE; return s.H[sp];
+        case LBM_H: *off = h->prec != LBM_FP64 ? OFF_G : OFF_NONE; return s.H[sp];
         case LBM_FS: return s.fs[sp];
         case LBM_MDOT: return s.md[sp];
         case LBM_PSIU_X: return s.pux;
@@ -691,8 +692,8 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
     h->ws_bytes = bytes;
     h->swm = sweep_m(p);
     h->swv = sweep_w(p);
-    if (h->prec == LBM_FP32) {
-        carve<float>(d, h->ws, &h->sf);
+    if (h->prec != LBM_FP64) {
+        carve<float>(d, h->ws, &h->sf, h->prec == LBM_FP32_FP16STORE);
         h->dctl = h->sf.ctl;
         h->partials = h->sf.partials;
     } else {
@@ -711,7 +712,9 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
         return LBM_EHIP;
     }
     std::memset(h->hctl, 0, sizeof(Ctl));
-    rc = h->prec == LBM_FP32 ? init_state<float>(h) : init_state<double>(h);
+    rc = h->prec == LBM_FP32_FP16STORE ? init_state<float, true>(h)
+         : h->prec == LBM_FP32          ? init_state<float>(h)
+                                        : init_state<double>(h);
     if (rc) {
         lbm_destroy(h);
         return rc;
@@ -724,7 +727,9 @@ int lbm_step(lbm_handle* h, int n) {
     if (!h) return LBM_ESTATE;
     if (n < 0) return LBM_EINVAL;
     for (int k = 0; k < n; k++) {
-        int rc = h->prec == LBM_FP32 ? one_step<float>(h) : one_step<double>(h);
+        int rc = h->prec == LBM_FP32_FP16STORE ? one_step<float, true>(h)
+                 : h->prec == LBM_FP32          ? one_step<float>(h)
+                                                : one_step<double>(h);
         if (rc) return rc;
     }
     return LBM_OK;
@@ -733,14 +738,16 @@ int lbm_step(lbm_handle* h, int n) {
 int lbm_solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps, double* resid) {
     if (!h) return LBM_ESTATE;
     if (max_sweeps < 1) return LBM_EINVAL;
-    return h->prec == LBM_FP32 ? solve_potential<float>(h, tol, max_sweeps, sweeps, resid)
+    return h->prec != LBM_FP64 ? solve_potential<float>(h, tol, max_sweeps, sweeps, resid)
                                : solve_potential<double>(h, tol, max_sweeps, sweeps, resid);
 }
 
 int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
     if (!h) return LBM_ESTATE;
     if (!out) return LBM_EINVAL;
-    int rc = h->prec == LBM_FP32 ? diagnostics<float>(h) : diagnostics<double>(h);
+    int rc = h->prec == LBM_FP32_FP16STORE ? diagnostics<float, true>(h)
+             : h->prec == LBM_FP32          ? diagnostics<float>(h)
+                                            : diagnostics<double>(h);
     if (rc) return rc;
     const Ctl& c = *h->hctl;
     std::memset(out, 0, sizeof *out);
@@ -764,25 +771,27 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
 
 int lbm_get_field(lbm_handle* h, int field, double* dst) {
     if (!h) return LBM_ESTATE;
-    return h->prec == LBM_FP32 ? get_set_field<float>(h, field, dst, true)
+    return h->prec != LBM_FP64 ? get_set_field<float>(h, field, dst, true)
                                : get_set_field<double>(h, field, dst, true);
 }
 
 int lbm_set_field(lbm_handle* h, int field, const double* src) {
     if (!h) return LBM_ESTATE;
     double* s = const_cast<double*>(src);
-    return h->prec == LBM_FP32 ? get_set_field<float>(h, field, s, false)
+    return h->prec != LBM_FP64 ? get_set_field<float>(h, field, s, false)
                                : get_set_field<double>(h, field, s, false);
 }
 
 int lbm_get_pop(lbm_handle* h, int set, double* dst) {
     if (!h) return LBM_ESTATE;
+    if (h->prec == LBM_FP32_FP16STORE) return LBM_EINVAL;  // binary16 deviations: not exported
     return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, dst, true) : get_set_pop<double>(h, set, dst, true);
 }
 
 int lbm_set_pop(lbm_handle* h, int set, const double* src) {
     if (!h) return LBM_ESTATE;
     double* s = const_cast<double*>(src);
+    if (h->prec == LBM_FP32_FP16STORE) return LBM_EINVAL;
     return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, s, false) : get_set_pop<double>(h, set, s, false);
 }
 
@@ -915,7 +924,7 @@ int lbm_run_until_frozen(lbm_handle* h, int max_steps, int check_every, int* ste
 int lbm_time_sweeps(lbm_handle* h, int n, float* ms) {
     if (!h) return LBM_ESTATE;
     if (n < 1 || !ms) return LBM_EINVAL;
-    return h->prec == LBM_FP32 ? time_sweeps<float, 1>(h, n, ms) : time_sweeps<double, 1>(h, n, ms);
+    return h->prec != LBM_FP64 ? time_sweeps<float, 1>(h, n, ms) : time_sweeps<double, 1>(h, n, ms);
 }
 
 int lbm_destroy(lbm_handle* h) {
@@ -991,7 +1000,7 @@ int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune*
             // launches tagged 2: a profile shows them apart from lbm_time_sweeps' (tag 1)
             float t0 = 0.f, t1 = 0.f;
             auto timed = [&](float* ms) {
-                return h->prec == LBM_FP32 ? time_sweeps<float, 2>(h, launches * m, ms)
+                return h->prec != LBM_FP64 ? time_sweeps<float, 2>(h, launches * m, ms)
                                            : time_sweeps<double, 2>(h, launches * m, ms);
             };
             rc = timed(&t0);  // the first pass warms caches and code
@@ -1095,6 +1104,7 @@ int batch_validate(int ncases, const lbm_params* cases) {
     for (int c = 0; c < ncases; c++) {
         int rc = validate(&cases[c]);
         if (rc) return rc;
+        if (cases[c].precision == LBM_FP32_FP16STORE) return LBM_EINVAL;  // single-case form only
         if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]) ||
             sweep_w(&cases[c]) != sweep_w(&cases[0]) || cases[c].skip_initial_solve)
             return LBM_EINVAL;
@@ -1553,19 +1563,19 @@ extern "C" {
 int lbm_nn_features(lbm_handle* h, int factor, float* x) {
     if (!h) return LBM_ESTATE;
     if (!x || !coarse_ok(h, factor)) return LBM_EINVAL;
-    return h->prec == LBM_FP32 ? nn_features<float>(h, factor, x) : nn_features<double>(h, factor, x);
+    return h->prec != LBM_FP64 ? nn_features<float>(h, factor, x) : nn_features<double>(h, factor, x);
 }
 
 int lbm_nn_target(lbm_handle* h, int factor, float* t) {
     if (!h) return LBM_ESTATE;
     if (!t || !coarse_ok(h, factor)) return LBM_EINVAL;
-    return h->prec == LBM_FP32 ? nn_target<float>(h, factor, t) : nn_target<double>(h, factor, t);
+    return h->prec != LBM_FP64 ? nn_target<float>(h, factor, t) : nn_target<double>(h, factor, t);
 }
 
 int lbm_nn_seed(lbm_handle* h, int factor, const float* y) {
     if (!h) return LBM_ESTATE;
     if (!y || !coarse_ok(h, factor)) return LBM_EINVAL;
-    return h->prec == LBM_FP32 ? nn_seed<float>(h, factor, y) : nn_seed<double>(h, factor, y);
+    return h->prec != LBM_FP64 ? nn_seed<float>(h, factor, y) : nn_seed<double>(h, factor, y);
 }
 
 int lbm_warm_start(lbm_handle* h, lbm_nn* nnh, int factor) {

@@ -19,7 +19,8 @@
 // two-sum) at the start of every potential solve and between batches of sweeps, so the
 // sweeps work on remainders that hold only the change since then; the constant base terms
 // of a launch are evaluated in FP64.  The FP64 form keeps no base: its arithmetic is the
-// raw scheme.
+// raw scheme.  The stages that move f, h and g also take a flag H: the FP32 form with those
+// three sets stored in binary16 (see the FP16 storage section below).
 //
 // Blocks are 256 threads (4 waves of 64) covering a 64 x 4 tile.  The 1-D grid is
 // remapped so that each of the 8 XCDs (which receive workgroups round-robin) works
@@ -76,6 +77,10 @@ struct Ctl {
     int final_buf;                   // potential buffer holding the last loop's final state
     double dsum[6];                  // sum psi, sum f, sum g, V_l, V_s, max |u|
     double front, height;
+    // FP16 population storage: per set (f, h, g) and buffer, the scale exponent the buffer was
+    // written with and the largest |deviation| (FP32 bits) written into it
+    int hexp[3][2];
+    unsigned hmax[3][2];
 };
 
 // Arms the potential loop: clears its outcome and sets its stopping rule.
@@ -349,6 +354,69 @@ __device__ __forceinline__ void invert(const Dev& d, R Hs, R G, R psi, R& T, R& 
 }
 
 // ---------------------------------------------------------------------------
+// FP16 population storage (FP32 arithmetic, template flag H of the stages that move f, h
+// and g).  A population is stored as its deviation from the zero-velocity equilibrium of
+// its node's stored moments (w_i psi for f, Eq. (18); the pressure part of Eq. (22) for h;
+// Eq. (29) at u = 0 for g, with H the stored enthalpy) times a power-of-two scale of its
+// set, rounded to binary16.  The stage that writes a set evaluates the base from the
+// moments it stores beside it, and the stage that reads the set a step later from those
+// stored moments, so the base cancels exactly and only the deviation is rounded.  The
+// scale of a write follows the largest deviation of the same set's write one step earlier
+// (it puts that maximum in [2^11, 2^12), sixteen times below the binary16 limit); a value
+// beyond the limit saturates instead of overflowing.
+using half_t = _Float16;
+enum PopSet { PS_F = 0, PS_H = 1, PS_G = 2 };
+constexpr int HS_TOP = 12, HS_EMIN = -16, HS_EMAX = 16;
+constexpr float HALF_MAX = 65504.f;
+
+// Scale exponent of a write whose set's previous maximum has the FP32 bits mbits (0: none).
+__host__ __device__ constexpr int h16_exp(unsigned mbits) {
+    if (mbits == 0) return HS_EMAX;
+    const int e = (int)((mbits >> 23) & 0xff) - 127;  // maximum < 2^(e + 1)
+    const int es = HS_TOP - 1 - e;
+    return es < HS_EMIN ? HS_EMIN : (es > HS_EMAX ? HS_EMAX : es);
+}
+__device__ __forceinline__ float h16_get(const half_t* p, int64_t k, float base, float inv) {
+    return base + (float)p[k] * inv;
+}
+__device__ __forceinline__ void h16_put(half_t* p, int64_t k, float dev, float sc) {
+    float x = dev * sc;
+    if (fabsf(x) > HALF_MAX) x = copysignf(HALF_MAX, x);  // NaN stays NaN
+    p[k] = (half_t)x;
+}
+// Zero-velocity equilibria the deviations are taken from.
+template <typename R>
+__device__ __forceinline__ R f_rest(int q, R psi) { return R(QW[q]) * psi; }
+template <typename R>
+__device__ __forceinline__ R h_rest(int q, R p) { return R(q == 0 ? (QW[q] - 1.0) : QW[q]) * R(3) * p; }
+template <typename R>
+__device__ __forceinline__ R g_rest(int q, R H, R T, R Cref) {
+#pragma clang fp contract(off)
+    return q == 0 ? (H - Cref * T) + R(W0) * (Cref * T) : R(QW[q]) * (Cref * T);
+}
+// Largest |deviation| of a block's write into *word (FP32 bits; every thread of the block
+// calls it, with 0 where it wrote nothing): wave maxima, and an atomic only where a wave's
+// exceeds what the word already holds.
+__device__ __forceinline__ void h16_note_max(unsigned* word, float m) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) {
+        const unsigned b = __float_as_uint(m);
+        if (b > __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(word, b);
+    }
+}
+// Scales of one stage's read (buffer sp) and write (buffer sp ^ 1) of a set; thread 0 of
+// block 0 records the write's exponent.
+struct H16Scales {
+    float inv, sc;
+};
+__device__ __forceinline__ H16Scales h16_scales(Ctl* c, int set, int sp) {
+    const int eo = h16_exp(c->hmax[set][sp]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->hexp[set][sp ^ 1] = eo;
+    return H16Scales{ldexpf(1.f, -c->hexp[set][sp]), ldexpf(1.f, eo)};
+}
+
+// ---------------------------------------------------------------------------
 // Pointers of one stage.
 
 template <typename R>
@@ -379,9 +447,11 @@ struct State {
 // ---------------------------------------------------------------------------
 // Initialisation (Algorithm 1, first block): fields, equilibria in buffer 0.
 
-template <typename R>
+template <typename R, bool H = false>
 __device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile) {
 #pragma clang fp contract(off)
+    if (H && blockIdx.x == 0 && threadIdx.x == 0)
+        for (int k = 0; k < 3; k++) s.ctl->hexp[k][0] = HS_EMAX;  // the deviations written here are 0
     int i, j;
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
@@ -415,9 +485,19 @@ __device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile
     GIn<R> gin{Hn, T, C, 0, 0, R(1), 0};
 #pragma unroll
     for (int q = 0; q < 9; q++) {
-        s.f[0][q * d.plane + n] = R(QW[q]) * psi;
-        s.h[0][q * d.plane + n] = coll_h<R>(q, R(0), hin);  // omega = 1 returns h_eq
-        s.g[0][q * d.plane + n] = coll_g<R>(q, R(0), gin, R(d.Cref));
+        const R fq = R(QW[q]) * psi;
+        const R hq = coll_h<R>(q, R(0), hin);  // omega = 1 returns h_eq
+        const R gq = coll_g<R>(q, R(0), gin, R(d.Cref));
+        if constexpr (H) {
+            const float sc = ldexpf(1.f, HS_EMAX);
+            h16_put((half_t*)s.f[0], q * d.plane + n, fq - f_rest<R>(q, psi), sc);
+            h16_put((half_t*)s.h[0], q * d.plane + n, hq - h_rest<R>(q, R(0)), sc);
+            h16_put((half_t*)s.g[0], q * d.plane + n, gq - g_rest<R>(q, Hn, T, R(d.Cref)), sc);
+        } else {
+            s.f[0][q * d.plane + n] = fq;
+            s.h[0][q * d.plane + n] = hq;
+            s.g[0][q * d.plane + n] = gq;
+        }
     }
     double leq = LWA * phi0;
     R lbase = based ? R(leq) : R(0);
@@ -429,9 +509,9 @@ __device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile
     }
     s.phi[0][n] = based ? R(phi0) : (l + l + l + l) * R(1.0 / (1.0 - LW0));
 }
-template <typename R>
+template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_init(Dev d, State<R> s) {
-    b_init<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
+    b_init<R, H>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // The liquid volume of the state the g stage just wrote (its block partials, added in block
@@ -487,18 +567,24 @@ __device__ __forceinline__ void a_term(const Dev& d, const R (&v)[3][3], R ux, R
 // Stage 1b: f pulled and collided at its source, half-way bounce-back at the
 // walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.  The collision
 // inputs of the tile and its ring are staged in LDS first (`ring`).
-template <typename R>
-__device__ __forceinline__ void f_collide_stream(const Dev& d, const State<R>& s, int sp, int tile,
-                                                 const FIn<R>* ring) {
+// H: FP16 storage; returns the largest |deviation| the thread wrote (0 otherwise).
+template <typename R, bool H = false>
+__device__ __forceinline__ float f_collide_stream(const Dev& d, const State<R>& s, int sp, int tile,
+                                                  const FIn<R>* ring, H16Scales hs = {}) {
     const R* md = s.md[sp];
     int i, j;
     node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
+    if (i >= d.nx || j >= d.ny) return 0.f;
     int64_t n = at(d, i, j);
     const R* fsrc = s.f[sp];
     R* fdst = s.f[sp ^ 1];
+    auto src = [&](int q, int64_t m, R base) -> R {
+        if constexpr (H) return h16_get((const half_t*)fsrc, q * d.plane + m, base, hs.inv);
+        else return fsrc[q * d.plane + m];
+    };
     const int me = ring_self();
     R sum = R(0);
+    R vals[H ? 9 : 1];
 #pragma unroll
     for (int q = 0; q < 9; q++) {
         int jj = j - QY[q];
@@ -506,26 +592,38 @@ __device__ __forceinline__ void f_collide_stream(const Dev& d, const State<R>& s
         if (jj < 0 || jj >= d.ny) {
             int o = QOPP[q];
             const FIn<R>& a = ring[me];
-            val = coll_f<R>(o, fsrc[o * d.plane + n], a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            val = coll_f<R>(o, src(o, n, f_rest<R>(o, a.psi)), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
         } else {
             int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
             const FIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
-            val = coll_f<R>(q, fsrc[q * d.plane + m], a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            val = coll_f<R>(q, src(q, m, f_rest<R>(q, a.psi)), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
         }
-        fdst[q * d.plane + n] = val;
+        if constexpr (H) vals[q] = val;
+        else fdst[q * d.plane + n] = val;
         sum += val;
     }
     R pn = sum / (R(1) - R(0.5) * md[n]);
     s.psi[sp ^ 1][n] = pn;
     R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, pn, s.fs[sp][n]);
     s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
+    float mx = 0.f;
+    if constexpr (H) {
+        // deviations from the equilibrium of the psi stored beside them
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            const float dv = vals[q] - f_rest<R>(q, pn);
+            mx = fmaxf(mx, fabsf(dv));
+            h16_put((half_t*)fdst, q * d.plane + n, dv, hs.sc);
+        }
+    }
+    return mx;
 }
 
 // Stages 1a and 1b in one pass: psi^n (wall ghosts applied) is staged on the tile with a
 // two-node ring (68 x 8) in LDS, A (a_term) is evaluated on the one-node ring from it, and the
 // collision inputs of the ring go to LDS for f_collide_stream (the same arithmetic as
 // evaluating A at every node in a pass of its own; kept bitwise when it was fused).
-template <typename R>
+template <typename R, bool H = false>
 __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int sp, int tile) {
     __shared__ R lps[QN2];
     __shared__ FIn<R> ring[RN];
@@ -558,12 +656,19 @@ __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int s
         ring[k] = FIn<R>{v[1][1], ux[m], uy[m], Ax, Ay, md[m]};
     }
     __syncthreads();
-    f_collide_stream<R>(d, s, sp, tile, ring);
+    if constexpr (H) {
+        const H16Scales hs = h16_scales(s.ctl, PS_F, sp);
+        h16_note_max(&s.ctl->hmax[PS_F][sp ^ 1], f_collide_stream<R, true>(d, s, sp, tile, ring, hs));
+    } else {
+        f_collide_stream<R>(d, s, sp, tile, ring);
+    }
 }
 // fin = 1: one extra block finishes the previous step's liquid-volume sum and freezing-time
 // detector meanwhile (a launch less per step; its fields of the control block are not the
 // loop's).
-template <typename R>
+// H (FP16 storage): block 0 also clears the maxima the h and g stages of this step collect
+// (their last readers were those stages one step earlier).
+template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
                                                     int max_sweeps, int fin) {
     const int nb = gridDim.x - fin;
@@ -572,8 +677,14 @@ __global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, d
         vl_finalize_body(d, s.partials, s.ctl, 0, sh);
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
-    b_f_fused<R>(d, s, sp, xcd_tile(blockIdx.x, nb));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
+        if (H) {
+            s.ctl->hmax[PS_H][sp ^ 1] = 0u;
+            s.ctl->hmax[PS_G][sp ^ 1] = 0u;
+        }
+    }
+    b_f_fused<R, H>(d, s, sp, xcd_tile(blockIdx.x, nb));
 }
 
 // 1/tau_l = 1/(sigma/c_s^2 + 1/2) from the current psi and f_s (Sec. 3.4).
@@ -1109,31 +1220,37 @@ __device__ __forceinline__ HIn<R> h_inputs(const State<R>& s, int sp, int64_t m)
 
 // Stage 3c: h pulled and collided at its source, bounce-back at the walls;
 // u* (Eq. (25)), u (Eq. (26) with u_s = 0), p (Eq. (27)).
-template <typename R>
-__device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int sp, int tile) {
-    __shared__ HIn<R> ring[RN];
-    stage_ring(d, tile, ring, [&](int64_t m) { return h_inputs<R>(s, sp, m); });
+template <typename R, bool H = false>
+__device__ __forceinline__ float h_stream_node(const Dev& d, const State<R>& s, int sp, int tile,
+                                               const HIn<R>* ring, H16Scales hs) {
     int i, j;
     node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
+    if (i >= d.nx || j >= d.ny) return 0.f;
     int64_t n = at(d, i, j);
     const R* hsrc = s.h[sp];
     R* hdst = s.h[sp ^ 1];
+    auto src = [&](int q, int64_t m, R base) -> R {
+        if constexpr (H) return h16_get((const half_t*)hsrc, q * d.plane + m, base, hs.inv);
+        else return hsrc[q * d.plane + m];
+    };
     const int me = ring_self();
     const HIn<R> self = ring[me];
     R sx = R(0), sy = R(0), s0 = R(0);
+    R vals[H ? 9 : 1];
 #pragma unroll
     for (int q = 0; q < 9; q++) {
         int jj = j - QY[q];
         R val;
         if (jj < 0 || jj >= d.ny) {
             int o = QOPP[q];
-            val = coll_h<R>(o, hsrc[o * d.plane + n], self);
+            val = coll_h<R>(o, src(o, n, h_rest<R>(o, self.p)), self);
         } else {
             int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            val = coll_h<R>(q, hsrc[q * d.plane + m], ring[ring_from(me, QX[q], QY[q])]);
+            const HIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
+            val = coll_h<R>(q, src(q, m, h_rest<R>(q, a.p)), a);
         }
-        hdst[q * d.plane + n] = val;
+        if constexpr (H) vals[q] = val;
+        else hdst[q * d.plane + n] = val;
         sx += R(QX[q]) * val;
         sy += R(QY[q]) * val;
         if (q) s0 += val;
@@ -1152,12 +1269,35 @@ __device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int 
     R R0 = R(W0) * (self.S - R(3) * uF);
     R uu = ux * ux + uy * uy;
     R s0u = R(W0) * (R(-1.5) * uu);
-    s.p[sp ^ 1][n] = R(CS2 / (1.0 - W0)) * (s0 + R(0.5) * self.S + (R(1) / self.om) * R0 + rho * s0u);
+    const R pn = R(CS2 / (1.0 - W0)) * (s0 + R(0.5) * self.S + (R(1) / self.om) * R0 + rho * s0u);
+    s.p[sp ^ 1][n] = pn;
+    float mx = 0.f;
+    if constexpr (H) {
+        // deviations from the equilibrium of the pressure stored beside them
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            const float dv = vals[q] - h_rest<R>(q, pn);
+            mx = fmaxf(mx, fabsf(dv));
+            h16_put((half_t*)hdst, q * d.plane + n, dv, hs.sc);
+        }
+    }
+    return mx;
 }
-template <typename R>
+template <typename R, bool H = false>
+__device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int sp, int tile) {
+    __shared__ HIn<R> ring[RN];
+    stage_ring(d, tile, ring, [&](int64_t m) { return h_inputs<R>(s, sp, m); });
+    if constexpr (H) {
+        const H16Scales hs = h16_scales(s.ctl, PS_H, sp);
+        h16_note_max(&s.ctl->hmax[PS_H][sp ^ 1], h_stream_node<R, true>(d, s, sp, tile, ring, hs));
+    } else {
+        h_stream_node<R>(d, s, sp, tile, ring, H16Scales{});
+    }
+}
+template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_h_stream(Dev d, State<R> s, int sp, int gate) {
     if (gate && !s.ctl->done) return;
-    b_h_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+    b_h_stream<R, H>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename R>
@@ -1174,10 +1314,18 @@ __device__ __forceinline__ GIn<R> g_inputs(const Dev& d, const State<R>& s, int 
 // Stage 4: g pulled and collided at its source; substrate anti-bounce-back at T_w,
 // adiabatic top; H^{n+1} = sum g + Q/2 (Eq. (30)); Eq. (7) gives T, f_l; new f_s
 // and mdot.  Per-block FP64 liquid volume for the freezing-time detector.
-template <typename R>
+template <typename R, bool H = false>
 __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int sp, int tile) {
     __shared__ GIn<R> ring[RN];
     stage_ring(d, tile, ring, [&](int64_t m) { return g_inputs<R>(d, s, sp, m); });
+    H16Scales hs{};
+    if constexpr (H) {
+        hs = h16_scales(s.ctl, PS_G, sp);
+        // the f stage of the next step collects into this word; its last reader was this
+        // step's f stage
+        if (blockIdx.x == 0 && threadIdx.x == 0) s.ctl->hmax[PS_F][sp] = 0u;
+    }
+    float mx = 0.f;
     int i, j;
     node_of(d, tile, i, j);
     double vl = 0.0;
@@ -1186,24 +1334,31 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
         const R* gsrc = s.g[sp];
         R* gdst = s.g[sp ^ 1];
         const R Cref = R(d.Cref);
+        auto src = [&](int q, int64_t m, const GIn<R>& a) -> R {
+            if constexpr (H) return h16_get((const half_t*)gsrc, q * d.plane + m, g_rest<R>(q, a.H, a.T, Cref), hs.inv);
+            else return gsrc[q * d.plane + m];
+        };
         const int me = ring_self();
         const GIn<R> self = ring[me];
         R sum = R(0), g0 = R(0);
+        R vals[H ? 9 : 1];
 #pragma unroll
         for (int q = 0; q < 9; q++) {
             int jj = j - QY[q];
             int o = QOPP[q];
             R val;
             if (jj < 0) {
-                val = -coll_g<R>(o, gsrc[o * d.plane + n], self, Cref) + R(2.0 * QW[q] * d.Cref * d.T_w);
+                val = -coll_g<R>(o, src(o, n, self), self, Cref) + R(2.0 * QW[q] * d.Cref * d.T_w);
             } else if (jj >= d.ny) {
-                val = coll_g<R>(o, gsrc[o * d.plane + n], self, Cref);
+                val = coll_g<R>(o, src(o, n, self), self, Cref);
             } else {
                 int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-                val = coll_g<R>(q, gsrc[q * d.plane + m], ring[ring_from(me, QX[q], QY[q])], Cref);
+                const GIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
+                val = coll_g<R>(q, src(q, m, a), a, Cref);
             }
             if (q == 0) g0 = val;
-            gdst[q * d.plane + n] = val;
+            if constexpr (H) vals[q] = val;
+            else gdst[q * d.plane + n] = val;
             sum += val;
         }
         R Hn = sum + R(0.5) * self.Q;
@@ -1218,9 +1373,19 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
 #pragma clang fp contract(off)
             R hn = clamp01(ps) * R(d.Lvol);
             R shift = hb - hn;
-            gdst[n] = g0 + shift;
+            if constexpr (H) vals[0] = g0 + shift;
+            else gdst[n] = g0 + shift;
             Hn = Hn + shift;
             s.hb[n] = hn;
+        }
+        if constexpr (H) {
+            // deviations from the equilibrium of the H and T stored beside them
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                const float dv = vals[q] - g_rest<R>(q, Hn, T, Cref);
+                mx = fmaxf(mx, fabsf(dv));
+                h16_put((half_t*)gdst, q * d.plane + n, dv, hs.sc);
+            }
         }
         R fsn = clamp01(ps) * (R(1) - fl);
         // (psi u)^n for the next step's A (its readers in this step have all run)
@@ -1234,14 +1399,15 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
         s.fs[sp ^ 1][n] = fsn;
         vl = (double)(clamp01(ps) * fl);
     }
+    if constexpr (H) h16_note_max(&s.ctl->hmax[PS_G][sp ^ 1], mx);
     __shared__ double sh[NT / 64];
     double bv = block_sum(vl, sh);
     if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + tile] = bv;
 }
-template <typename R>
+template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_g_stream(Dev d, State<R> s, int sp, int gate) {
     if (gate && !s.ctl->done) return;
-    b_g_stream<R>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+    b_g_stream<R, H>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // One block: liquid volume of the new state (block partials in order).  mode 1 records
@@ -1276,7 +1442,7 @@ __global__ void __launch_bounds__(NT) k_vl0(Dev d, State<R> s) {
 // Diagnostics: per-block FP64 sums, max |u| and a non-finite count; k_diag_finalize
 // adds them in block order and scans the centre column for the droplet height
 // (psi = 1/2) and the freezing front (f_l = 1/2).
-template <typename R>
+template <typename R, bool H = false>
 __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     int i, j;
     node_of(d, tile, i, j);
@@ -1289,8 +1455,16 @@ __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, 
         v[0] = ps;
         double sf = 0.0, sg = 0.0;
         for (int q = 0; q < 9; q++) {
-            sf += (double)s.f[sp][q * d.plane + n];
-            sg += (double)s.g[sp][q * d.plane + n];
+            if constexpr (H) {
+                const float fi = ldexpf(1.f, -s.ctl->hexp[PS_F][sp]), gi = ldexpf(1.f, -s.ctl->hexp[PS_G][sp]);
+                const R psn = s.psi[sp][n];
+                sf += (double)h16_get((const half_t*)s.f[sp], q * d.plane + n, f_rest<R>(q, psn), fi);
+                sg += (double)h16_get((const half_t*)s.g[sp], q * d.plane + n,
+                                      g_rest<R>(q, s.H[sp][n], s.T[sp][n], R(d.Cref)), gi);
+            } else {
+                sf += (double)s.f[sp][q * d.plane + n];
+                sg += (double)s.g[sp][q * d.plane + n];
+            }
         }
         v[1] = sf;
         v[2] = std::is_same<R, float>::value ? sg + (double)s.hb[n] : sg;
@@ -1310,9 +1484,9 @@ __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, 
         for (int k = 0; k < 7; k++) pw[k] = r[k];
     }
 }
-template <typename R>
+template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_diag(Dev d, State<R> s, int sp, int lcur) {
-    b_diag<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
+    b_diag<R, H>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename R>

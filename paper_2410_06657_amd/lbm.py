@@ -18,7 +18,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOCONV, LBM_ENONFINITE, LBM_EHIP, LBM_ESTATE, LBM_ESPAC
 FIELDS = ["psi", "ux", "uy", "usx", "usy", "p", "T", "H", "fs", "mdot",
           "psiu_x", "psiu_y", "phi", "fl"]
 POPS = {"f": (0, 9), "h": (1, 9), "g": (2, 9), "l": (3, 4)}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16store": 2}
 
 # every exported symbol of include/lbm.h
 SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
@@ -229,9 +229,10 @@ class Solver:
     current stream on `device` at construction."""
 
     def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0", workspace=None):
-        """`workspace`: optional caller-owned uint8 device tensor of at least
-        `workspace_bytes(case, precision)` bytes (its contents do not matter); by default one
-        is allocated."""
+        """`precision`: "fp64", "fp32" or "fp16store" (FP32 arithmetic with the f, h and g
+        populations stored in binary16).  `workspace`: optional caller-owned uint8 device
+        tensor of at least `workspace_bytes(case, precision)` bytes (its contents do not
+        matter); by default one is allocated."""
         import torch
 
         if not torch.cuda.is_available():

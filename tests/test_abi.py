@@ -46,6 +46,9 @@ def test_workspace_size_and_validation(liblbm):
     # the sweep constants (4 pulled base increments, 1 base potential)
     n32 = liblbm.workspace_bytes(c, "fp32")
     assert 112 * 128 * 64 * 4 <= n32 < 112 * 128 * 64 * 4 + 65536
+    # FP16 storage: the 54 planes of f, h and g in binary16, the rest as in FP32
+    n16 = liblbm.workspace_bytes(c, "fp16store")
+    assert n16 == pytest.approx(n32 - 54 * 128 * 64 * 2, abs=4096)
     big = liblbm.workspace_bytes(inputs.cfg3())
     assert big > 6e9
     for bad in (dict(c, nx=1), dict(c, ny=2), dict(c, M=0.0), dict(c, sig_l=-1.0),
@@ -74,6 +77,10 @@ def test_batch_validation(liblbm):
         arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in bad])
         n = C.c_size_t()
         assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_EINVAL
+    # the FP16-storage form is single-case only
+    arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c, "fp16store") for c in (a, a)])
+    n = C.c_size_t()
+    assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_EINVAL
     arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in (a, inputs.scaled(a, 64, 32))])
     n = C.c_size_t()
     assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_OK and n.value > 0
