@@ -78,7 +78,7 @@ struct Ctl {
     double dsum[6];                  // sum psi, sum f, sum g, V_l, V_s, max |u|
     double front, height;
     // FP16 population storage: per set (f, h, g) and buffer, the scale exponent the buffer was
-    // written with and the largest |deviation| (FP32 bits) written into it
+    // last written with and the largest |deviation| (FP32 bits) ever written into it
     int hexp[3][2];
     unsigned hmax[3][2];
 };
@@ -361,9 +361,10 @@ __device__ __forceinline__ void invert(const Dev& d, R Hs, R G, R psi, R& T, R& 
 // set, rounded to binary16.  The stage that writes a set evaluates the base from the
 // moments it stores beside it, and the stage that reads the set a step later from those
 // stored moments, so the base cancels exactly and only the deviation is rounded.  The
-// scale of a write follows the largest deviation of the same set's write one step earlier
-// (it puts that maximum in [2^11, 2^12), sixteen times below the binary16 limit); a value
-// beyond the limit saturates instead of overflowing.
+// scale of a write puts the largest deviation ever written into the buffer it reads in
+// [2^11, 2^12), sixteen times below the binary16 limit (binary16's relative precision does
+// not depend on the scale; the scale only keeps values clear of overflow and of the
+// subnormal range); a value beyond the limit saturates instead of overflowing.
 using half_t = _Float16;
 enum PopSet { PS_F = 0, PS_H = 1, PS_G = 2 };
 constexpr int HS_TOP = 12, HS_EMIN = -16, HS_EMAX = 16;
@@ -394,19 +395,29 @@ __device__ __forceinline__ R g_rest(int q, R H, R T, R Cref) {
 #pragma clang fp contract(off)
     return q == 0 ? (H - Cref * T) + R(W0) * (Cref * T) : R(QW[q]) * (Cref * T);
 }
-// Largest |deviation| of a block's write into *word (FP32 bits; every thread of the block
-// calls it, with 0 where it wrote nothing): wave maxima, and an atomic only where a wave's
-// exceeds what the word already holds.
+// Folds the largest |deviation| of a block's write into *word, the running maximum (FP32
+// bits) of every write into that buffer of the set.  Every thread of the block calls it, with
+// 0 where it wrote nothing.  The word only grows, so a block whose maximum does not exceed a
+// (possibly stale) cached read of it skips the atomic: after the first steps nearly every
+// block does.
 __device__ __forceinline__ void h16_note_max(unsigned* word, float m) {
+    __shared__ float wm[NT / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) {
-        const unsigned b = __float_as_uint(m);
-        if (b > __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(word, b);
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = wm[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; w++) b = fmaxf(b, wm[w]);
+        const unsigned u = __float_as_uint(b);
+        if (u > *word) atomicMax(word, u);
     }
 }
 // Scales of one stage's read (buffer sp) and write (buffer sp ^ 1) of a set; thread 0 of
-// block 0 records the write's exponent.
+// block 0 records the write's exponent.  The write's exponent follows the running maximum of
+// the writes into buffer sp, which no block of this launch changes (they fold into the other
+// buffer's word), so every block derives the same exponent.
 struct H16Scales {
     float inv, sc;
 };
@@ -666,8 +677,6 @@ __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int s
 // fin = 1: one extra block finishes the previous step's liquid-volume sum and freezing-time
 // detector meanwhile (a launch less per step; its fields of the control block are not the
 // loop's).
-// H (FP16 storage): block 0 also clears the maxima the h and g stages of this step collect
-// (their last readers were those stages one step earlier).
 template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
                                                     int max_sweeps, int fin) {
@@ -677,13 +686,7 @@ __global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, d
         vl_finalize_body(d, s.partials, s.ctl, 0, sh);
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
-        if (H) {
-            s.ctl->hmax[PS_H][sp ^ 1] = 0u;
-            s.ctl->hmax[PS_G][sp ^ 1] = 0u;
-        }
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
     b_f_fused<R, H>(d, s, sp, xcd_tile(blockIdx.x, nb));
 }
 
@@ -1319,12 +1322,7 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
     __shared__ GIn<R> ring[RN];
     stage_ring(d, tile, ring, [&](int64_t m) { return g_inputs<R>(d, s, sp, m); });
     H16Scales hs{};
-    if constexpr (H) {
-        hs = h16_scales(s.ctl, PS_G, sp);
-        // the f stage of the next step collects into this word; its last reader was this
-        // step's f stage
-        if (blockIdx.x == 0 && threadIdx.x == 0) s.ctl->hmax[PS_F][sp] = 0u;
-    }
+    if constexpr (H) hs = h16_scales(s.ctl, PS_G, sp);
     float mx = 0.f;
     int i, j;
     node_of(d, tile, i, j);
