@@ -173,6 +173,46 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name="cfg2
     }
 
 
+def run_precision_full_size(steps=10, sweeps=8, compare_after=2):
+    """The precision forms on the 4096 x 2048 drop (R0 = 640, theta = 90, R = 3, S = 1,
+    Ca_E = 0.1) with a fixed number of potential sweeps per step: relative L2 error per field
+    against the FP64 form after `compare_after` steps, then the time of `steps` more steps."""
+    import numpy as np
+    import torch
+
+    from paper_2410_06657_amd import inputs
+    from paper_2410_06657_amd.lbm import Solver
+
+    c = inputs.cfg3()
+    c.update(poisson_tol=-1.0, poisson_max_sweeps=sweeps)
+    n = c["nx"] * c["ny"]
+    fields = ("psi", "ux", "uy", "p", "T", "H", "fs", "phi")
+    out = {"workload": f"4096x2048 sessile drop, R0=640, theta=90, R=3, S=1, Ca_E=0.1, {sweeps} potential sweeps "
+                       f"per step (fixed), fields compared after {compare_after} steps, {steps} steps timed"}
+    ref = None
+    for prec in ("fp64", "fp32", "fp16store"):
+        s = Solver(c, prec)
+        s.step(compare_after)
+        cur = {k: s.field(k) for k in fields}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 4)}
+        if ref is None:
+            ref = cur
+        else:
+            r["rel_l2_error_vs_fp64"] = {k: float(np.linalg.norm(cur[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-300))
+                                         for k in fields}
+            r["speedup_vs_fp64"] = round(r["value"] / out["fp64"]["value"], 3)
+        out[prec] = r
+        del s
+        torch.cuda.empty_cache()
+        print(f"[bench] 4096x2048 {prec}: {r['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+    return out
+
+
 def run_batched(steps, warmup, cap, seed=4, ncases=96):
     """The batched form on the 96-case sweep (uneven grids 256x128 .. 1536x768, FP32): the
     whole batch advanced `steps` steps with one launch per stage, against the same cases run
@@ -498,6 +538,7 @@ def main():
         f16 = run_form(case, "fp16store", args.steps, args.warmup, args.sweep_launches, args.workload)
         f16["speedup_vs_fp64"] = round(f16["value"] / f64["value"], 3)
         line["forms"]["fp16store"] = f16
+        line["forms"]["precision_4096x2048"] = run_precision_full_size()
     if not args.no_time_to_freeze:
         line["time_to_freeze"] = run_time_to_freeze()
     if not args.no_validation:
