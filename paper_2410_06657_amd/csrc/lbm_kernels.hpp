@@ -746,21 +746,47 @@ __device__ __forceinline__ bool stop_recompute(const Ctl* c) {
     return c->fix_n != min(M, c->max_sweeps + 1 - k0);
 }
 
-template <int M, typename R, int NW = NT / 64>
+// U: tiles fetched ahead (2 inside the sweep kernels, whose register budget it must fit; 4 in
+// the one-workgroup test kernels).
+template <int M, typename R, int NW = NT / 64, int U = 2>
 __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh) {
     int nbt = d.tbx * d.tby, nb = d.gx * d.gy;
     const double* pv = s.partials + part_sweep(nb, nbt, a.prev_slot);
     double acc[2 * M];
 #pragma unroll
     for (int m = 0; m < 2 * M; m++) acc[m] = 0.0;
-    for (int b = threadIdx.x; b < nbt; b += 64 * NW)
+    // U tiles' partials are fetched before any is added (one memory latency per U tiles, not
+    // per tile); the additions keep the order b, b + NTH, ..., so the sums are bitwise those
+    // of one tile at a time
+    constexpr int NTH = 64 * NW;
+    int b = threadIdx.x;
+    for (; b + (U - 1) * NTH < nbt; b += U * NTH) {
+        double v[U][2 * M];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                const double* q = pv + ((int64_t)m * nbt + b + u * NTH) * 2;
+                v[u][2 * m] = m < a.prev_nsw ? q[0] : 0.0;
+                v[u][2 * m + 1] = m < a.prev_nsw ? q[1] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int m = 0; m < M; m++)
+                if (m < a.prev_nsw) {
+                    acc[2 * m] += v[u][2 * m];
+                    acc[2 * m + 1] += v[u][2 * m + 1];
+                }
+    }
+    for (; b < nbt; b += NTH)
 #pragma unroll
         for (int m = 0; m < M; m++)
             if (m < a.prev_nsw) {
                 acc[2 * m] += pv[((int64_t)m * nbt + b) * 2];
                 acc[2 * m + 1] += pv[((int64_t)m * nbt + b) * 2 + 1];
             }
-    block_sums_parked<2 * M, 64 * NW>(acc, sh);
+    block_sums_parked<2 * M, NTH>(acc, sh);
     if (threadIdx.x != 0) return;
     Ctl* c = s.ctl;
     for (int m = 0; m < a.prev_nsw && m < M; m++) {
@@ -1054,7 +1080,7 @@ template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a,
                                                         unsigned long long* word, unsigned seq) {
     __shared__ double sh[2 * M * TEST_NT + 2 * M];
-    if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64>(d, s, a, sh);
+    if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64, 4>(d, s, a, sh);
     if (threadIdx.x != 0 || !word) return;  // no word: a test inside a batch, nothing published
     // a.src: the solve's first buffer; the stage kernels that follow a loop read its final
     // buffer from here
@@ -1663,7 +1689,7 @@ __global__ void __launch_bounds__(TEST_NT) kb_sweep_test(const BatchCase<R>* __r
     if (bc.s.ctl->done) return;
     SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x], t + 1);
     if (a.prev_nsw <= 0) return;
-    sweep_test<M, R, TEST_NT / 64>(bc.d, bc.s, a, sh);
+    sweep_test<M, R, TEST_NT / 64, 4>(bc.d, bc.s, a, sh);
 }
 
 template <typename R>
