@@ -69,7 +69,8 @@ def measured_traffic(precision, workload_name):
     sha = sweep_source_digest()
     if sha is None or table.get("kernel_source_sha256") != sha:
         return None
-    v = table.get(f"traffic_bytes_per_launch_{precision}")
+    # the FP16-storage form runs the FP32 sweep kernel (its potential links are FP32)
+    v = table.get(f"traffic_bytes_per_launch_{'fp32' if precision == 'fp16store' else precision}")
     return int(v) if v else None
 
 
