@@ -1,0 +1,46 @@
+"""Host logic of bench.py (no GPU): the one-GPU guard, the byte models of the roofline
+figures and the rule that measured traffic is reported only for the kernel source it was
+taken from."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_byte_models():
+    # a potential sweep moves 4 links, phi and 1/tau_l in and 4 links and phi out
+    assert bench.SWEEP_ELEMS * bench.ELEM["fp64"] == 88
+    assert bench.SWEEP_ELEMS * bench.ELEM["fp32"] == 44
+    # outside the sweeps: 27 + 27 populations and 13 + 13 fields per node and step
+    assert bench.STEP_BYTES["fp64"] == 640 and bench.STEP_BYTES["fp32"] == 320
+    # FP16 storage: the populations in 2 bytes, the fields in 4
+    assert bench.STEP_BYTES["fp16store"] == 54 * 2 + 26 * 4 == 212
+    # the FP16-storage form sweeps FP32 links
+    assert bench.ELEM["fp16store"] == 4 and bench.SWEEP_COMPULSORY["fp16store"] == bench.SWEEP_COMPULSORY["fp32"]
+
+
+def test_traffic_only_for_the_profiled_source(monkeypatch):
+    t64, t32 = bench.measured_traffic("fp64", "cfg2"), bench.measured_traffic("fp32", "cfg2")
+    if t64 is None:
+        pytest.skip("the committed counter summary was taken from another kernel source")
+    # above the compulsory bytes of a launch at 1024 x 512, below twice them
+    n = 1024 * 512
+    assert bench.SWEEP_COMPULSORY["fp64"] * n <= t64 < 2 * bench.SWEEP_COMPULSORY["fp64"] * n
+    assert bench.SWEEP_COMPULSORY["fp32"] * n <= t32 < 2 * bench.SWEEP_COMPULSORY["fp32"] * n
+    assert bench.measured_traffic("fp16store", "cfg2") == t32
+    assert bench.measured_traffic("fp64", "cfg1") is None
+    monkeypatch.setattr(bench, "sweep_source_digest", lambda: "0" * 64)
+    assert bench.measured_traffic("fp64", "cfg2") is None
