@@ -581,8 +581,8 @@ R* pop_ptr(lbm_handle* h, int set, int* nq, Offset* off) {
     switch (set) {
         case LBM_POP_F: *nq = 9; return s.f[h->sp];
         case LBM_POP_H: *nq = 9; return s.h[h->sp];
-        case LBM_POP_G: *nq = 9; *off = h->prec == LBM_FP32 ? OFF_G : OFF_NONE; return s.g[h->sp];
-        case LBM_POP_L: *nq = 4; *off = h->prec == LBM_FP32 ? OFF_BASE : OFF_NONE; return s.l[h->lcur];
+        case LBM_POP_G: *nq = 9; *off = h->prec != LBM_FP64 ? OFF_G : OFF_NONE; return s.g[h->sp];
+        case LBM_POP_L: *nq = 4; *off = h->prec != LBM_FP64 ? OFF_BASE : OFF_NONE; return s.l[h->lcur];
         default: return nullptr;
     }
 }
@@ -659,6 +659,50 @@ int get_set_pop(lbm_handle* h, int set, double* buf, bool get) {
     R* p = pop_ptr<R>(h, set, &nq, &off);
     if (!p || !buf) return LBM_EINVAL;
     return copy_planes<R>(h, p, buf, nq, get, off);
+}
+
+// FP16-storage form: the binary16 deviations of f, h or g decoded on the host with the bases
+// the kernels use (the zero-velocity equilibria of the node's stored moments, evaluated in
+// float by the same operations) and the exponent the current buffer was written with; the
+// enthalpy base is added to the g rest link as for the FP32 form.  The D2Q5 links are FP32
+// pairs, read as in that form.
+float rest16(int set, int q, float a, float b, float cref) {
+    const double w = q == 0 ? lbm::W0 : (q < 5 ? lbm::WA : lbm::WD);
+    if (set == LBM_POP_F) return (float)w * a;
+    if (set == LBM_POP_H) return ((float)(q == 0 ? w - 1.0 : w) * 3.0f) * a;
+    return q == 0 ? (a - cref * b) + (float)lbm::W0 * (cref * b) : (float)w * (cref * b);
+}
+
+int get_pop16(lbm_handle* h, int set, double* host) {
+    if (set == LBM_POP_L) return get_set_pop<float>(h, set, host, true);
+    if (set < LBM_POP_F || set > LBM_POP_G || !host) return LBM_EINVAL;
+    int rc = fetch_ctl(h);
+    if (rc) return rc;
+    const float inv = std::ldexp(1.f, -h->hctl->hexp[set][h->sp]);
+    const Dev& d = h->dev;
+    State<float>& s = h->sf;
+    const int sp = h->sp;
+    const size_t nx = (size_t)d.nx, pitch = (size_t)d.pitch, per = nx * (size_t)d.ny;
+    const size_t plane = (size_t)d.plane;
+    const float* sets[] = {s.f[sp], s.h[sp], s.g[sp]};
+    std::vector<lbm::half_t> blk(9 * plane);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(blk.data(), sets[set], blk.size() * sizeof(lbm::half_t), hipMemcpyDeviceToHost));
+    const float* moment = set == LBM_POP_F ? s.psi[sp] : (set == LBM_POP_H ? s.p[sp] : s.H[sp]);
+    std::vector<float> a, b, hb;
+    rc = block_to_host<float>(h, a, moment, plane);
+    if (!rc && set == LBM_POP_G) rc = block_to_host<float>(h, b, s.T[sp], plane);
+    if (!rc && set == LBM_POP_G) rc = block_to_host<float>(h, hb, s.hb, plane);
+    if (rc) return rc;
+    const float cref = (float)d.Cref;
+    for (int q = 0; q < 9; q++)
+        for (size_t k = 0; k < per; k++) {
+            const size_t n = (k / nx) * pitch + k % nx;
+            const float base = rest16(set, q, a[n], set == LBM_POP_G ? b[n] : 0.f, cref);
+            const float v = base + (float)blk[q * plane + n] * inv;
+            host[q * per + k] = (double)v + (set == LBM_POP_G && q == 0 ? (double)hb[n] : 0.0);
+        }
+    return LBM_OK;
 }
 
 }  // namespace
@@ -784,15 +828,16 @@ int lbm_set_field(lbm_handle* h, int field, const double* src) {
 
 int lbm_get_pop(lbm_handle* h, int set, double* dst) {
     if (!h) return LBM_ESTATE;
-    if (h->prec == LBM_FP32_FP16STORE) return LBM_EINVAL;  // binary16 deviations: not exported
+    if (h->prec == LBM_FP32_FP16STORE) return get_pop16(h, set, dst);
     return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, dst, true) : get_set_pop<double>(h, set, dst, true);
 }
 
 int lbm_set_pop(lbm_handle* h, int set, const double* src) {
     if (!h) return LBM_ESTATE;
     double* s = const_cast<double*>(src);
-    if (h->prec == LBM_FP32_FP16STORE) return LBM_EINVAL;
-    return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, s, false) : get_set_pop<double>(h, set, s, false);
+    // FP16 storage: a write of f, h or g would have to be encoded against the running scales
+    if (h->prec == LBM_FP32_FP16STORE && set != LBM_POP_L) return LBM_EINVAL;
+    return h->prec != LBM_FP64 ? get_set_pop<float>(h, set, s, false) : get_set_pop<double>(h, set, s, false);
 }
 
 int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count) {
