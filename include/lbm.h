@@ -270,7 +270,8 @@ const char* lbm_last_error(const lbm_handle* h);
 /* ---- Learned warm start of the potential ------------------------------------------
    A network maps coarse maps of the state to the coarse deviation of the potential from the
    linear electrode ramp; its prediction seeds the potential links, after which the plain
-   sweeps of Eqs. (31)-(34) run to the same stopping rule (they remain the judge).  The
+   sweeps of Eqs. (31)-(34) run to the same stopping rule (they, not the network, decide the
+   result).  The
    network: six 3x3 convolutions, 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 channels, dilations
    1, 2, 4, 8, 4, 1, tanh between layers, zero padding; FP16 weights and activations with
    FP32 accumulation on the matrix cores; FP32 master parameters and Adam (beta 0.9, 0.999,
