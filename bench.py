@@ -33,7 +33,7 @@ STEP_BYTES = {"fp64": STEP_ELEMS * 8, "fp32": STEP_ELEMS * 4, "fp16store": 54 * 
 SWEEP_COMPULSORY = {"fp64": 10 * 8, "fp32": 15 * 4, "fp16store": 15 * 4}
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_cfg2_counters.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_1024x512_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2410_06657_amd", "csrc", "lbm_kernels.hpp")
 
 
@@ -57,7 +57,7 @@ def measured_traffic(precision, workload_name):
     (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel), or None when the summary
     is missing, covers another workload, or was taken from a different kernel source."""
     import hashlib
-    if workload_name != "cfg2" or not os.path.exists(COUNTERS_FILE):
+    if workload_name != "1024x512" or not os.path.exists(COUNTERS_FILE):
         return None
     table = {}
     with open(COUNTERS_FILE) as f:
@@ -76,14 +76,14 @@ def measured_traffic(precision, workload_name):
 
 def workload(name):
     from paper_2410_06657_amd import inputs
-    if name == "cfg2":
-        c = inputs.cfg2(90.0, "prolate", 0.1)
+    if name == "1024x512":
+        c = inputs.drop_1024x512(90.0, "prolate", 0.1)
         desc = "1024x512 sessile drop, R0=160, theta=90, R=3, S=1 (prolate), Ca_E=0.1, Ste=0.1, rho_l/rho_g=10, k_s/k_l=2"
-    elif name == "cfg1":
-        c = inputs.cfg1(0)
+    elif name == "128x64":
+        c = inputs.drop_128x64(0)
         desc = "128x64 sessile drop, R0=24, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"
-    elif name == "cfg3":
-        c = inputs.cfg3()
+    elif name == "4096x2048":
+        c = inputs.drop_4096x2048()
         desc = "4096x2048 sessile drop, R0=640, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1"
     else:
         raise SystemExit(f"unknown workload {name}")
@@ -118,7 +118,7 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
             "step_s": step_s}
 
 
-def run_form(case, precision, steps, warmup, sweep_launches, workload_name="cfg2"):
+def run_form(case, precision, steps, warmup, sweep_launches, workload_name="1024x512"):
     """Time `steps` coupled steps of one precision form, then the dominant kernel."""
     import numpy as np
     import torch
@@ -184,7 +184,7 @@ def run_precision_full_size(steps=10, sweeps=8, compare_after=2):
     from paper_2410_06657_amd import inputs
     from paper_2410_06657_amd.lbm import Solver
 
-    c = inputs.cfg3()
+    c = inputs.drop_4096x2048()
     c.update(poisson_tol=-1.0, poisson_max_sweeps=sweeps)
     n = c["nx"] * c["ny"]
     fields = ("psi", "ux", "uy", "p", "T", "H", "fs", "phi")
@@ -226,7 +226,7 @@ def run_batched(steps, warmup, cap, seed=4, ncases=96):
     from paper_2410_06657_amd import inputs
     from paper_2410_06657_amd.lbm import Batch, Solver, autotune
 
-    cases = inputs.cfg4(seed, ncases)
+    cases = inputs.drop_batch(seed, ncases)
     big = max(cases, key=lambda c: c["nx"] * c["ny"])
     tune = autotune(dict(big, poisson_max_sweeps=cap), "fp32", launches=10, persist=False)
     shape = {"sweep_block": tune["sweep_block"], "sweep_waves": tune["sweep_waves"]}
@@ -415,7 +415,7 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, s.diag()["t_fre"], k
 
-    c = inputs.cfg1(0)
+    c = inputs.drop_128x64(0)
     out = {"workload": "128x64 sessile drop, R0=24, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"}
     t64, f64, k64 = one(c, "fp64")
     t32, f32, _ = one(c, "fp32")
@@ -432,7 +432,7 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
                         "speedup_vs_fp64": round(t64 / tw, 3)}
     print(f"[bench] time to freeze: fp64 {t64:.2f}s, fp32 {t32:.2f}s, fp16 storage {t16:.2f}s, warm {tw:.2f}s",
           file=sys.stderr, flush=True)
-    cases = [inputs.cfg1(sd) for sd in range(nbatch)]
+    cases = [inputs.drop_128x64(sd) for sd in range(nbatch)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b = Batch(cases, precision="fp32")
@@ -488,7 +488,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="1024x512")
     ap.add_argument("--sweep-launches", type=int, default=100,
                     help="blocked sweep launches timed with HIP events for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -138,36 +138,36 @@ def stefan_strip(nx: int, ny: int, h0: float, Ste: float, rho_ratio_sl: float = 
 
 # ---- the five workloads -------------------------------------------------------------------
 
-def cfg1(seed: int = 0) -> dict:
+def drop_128x64(seed: int = 0) -> dict:
     """128x64 FP64 sessile drop: R0 = 24, theta = 90, W = 4, Ste = 0.1, R = 3, S = 1 (prolate),
     Ca_E = 0.1, potential to 1e-8 every step, centre jitter from the seed."""
     return sessile_drop(128, 64, 24.0, 90.0, 3.0, 1.0, 0.1, 0.1, seed=seed)
 
 
-CFG2_THETAS = (60.0, 90.0, 120.0)
-CFG2_PAIRS = {"prolate": (3.0, 1.0), "oblate": (0.5, 2.0)}
-CFG2_CAE = (0.0, 0.1, 0.3)
+DROP_1024_THETAS = (60.0, 90.0, 120.0)
+DROP_1024_PAIRS = {"prolate": (3.0, 1.0), "oblate": (0.5, 2.0)}
+DROP_1024_CAE = (0.0, 0.1, 0.3)
 
 
-def cfg2(theta_deg: float = 90.0, kind: str = "prolate", Ca_E: float = 0.1) -> dict:
+def drop_1024x512(theta_deg: float = 90.0, kind: str = "prolate", Ca_E: float = 0.1) -> dict:
     """1024x512, R0 = 160; prolate (R=3, S=1) or oblate (R=0.5, S=2); Ca_E in {0, 0.1, 0.3};
     liquid/gas density 10, ice/liquid conductivity 2, Ste = 0.1."""
-    R, S = CFG2_PAIRS[kind]
+    R, S = DROP_1024_PAIRS[kind]
     return sessile_drop(1024, 512, 160.0, theta_deg, R, S, Ca_E, 0.1, seed=0)
 
 
-def cfg3() -> dict:
+def drop_4096x2048() -> dict:
     """4096x2048, R0 = 640, theta = 90, R = 3, S = 1, Ca_E = 0.1, Ste = 0.1."""
     return sessile_drop(4096, 2048, 640.0, 90.0, 3.0, 1.0, 0.1, 0.1, seed=0)
 
 
-def cfg3_strip(ny: int = 4096, h0: float | None = None, Ste: float = 0.1,
+def strip_4x4096(ny: int = 4096, h0: float | None = None, Ste: float = 0.1,
                rho_ratio_sl: float = 1.0) -> dict:
     """The 4 x 4096 Stefan strip (periodic in x, freezing along y)."""
     return stefan_strip(4, ny, h0 if h0 is not None else ny - 8, Ste, rho_ratio_sl)
 
 
-def cfg4(seed: int = 4, ncases: int = 96) -> list:
+def drop_batch(seed: int = 4, ncases: int = 96) -> list:
     """The batched sweep: ncases sessile drops with N_y ~ U{128, 144, ..., 768}, N_x = 2 N_y,
     R0 = 0.3125 N_y, Ca_E ~ U[0, 0.4], theta ~ U[45, 135] deg, R ~ logU[0.3, 5],
     S ~ logU[0.5, 3], Ste = 0.1, FP32.  Case c uses uniforms 5c .. 5c+4 of SplitMix64(seed)

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(liblbm):
 
 def test_workspace_size_and_validation(liblbm):
     from paper_2410_06657_amd import inputs
-    c = inputs.cfg1(0)
+    c = inputs.drop_128x64(0)
     n = liblbm.workspace_bytes(c)
     # 66 population planes + 36 field planes of 128 x 64 doubles, plus a small tail
     assert 102 * 128 * 64 * 8 <= n < 102 * 128 * 64 * 8 + 65536
@@ -49,7 +49,7 @@ def test_workspace_size_and_validation(liblbm):
     # FP16 storage: the 54 planes of f, h and g in binary16, the rest as in FP32
     n16 = liblbm.workspace_bytes(c, "fp16store")
     assert n16 == pytest.approx(n32 - 54 * 128 * 64 * 2, abs=4096)
-    big = liblbm.workspace_bytes(inputs.cfg3())
+    big = liblbm.workspace_bytes(inputs.drop_4096x2048())
     assert big > 6e9
     for bad in (dict(c, nx=1), dict(c, ny=2), dict(c, M=0.0), dict(c, sig_l=-1.0),
                 dict(c, poisson_max_sweeps=0), dict(c, shape=3), dict(c, sweep_block=3),
@@ -72,7 +72,7 @@ def test_error_strings(liblbm):
 def test_batch_validation(liblbm):
     import ctypes as C
     from paper_2410_06657_amd import inputs
-    a = inputs.cfg1(0)
+    a = inputs.drop_128x64(0)
     for bad in ([a, dict(a, skip_initial_solve=1)], [a, dict(a, sweep_block=4)], [a, dict(a, sweep_waves=8)]):
         arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in bad])
         n = C.c_size_t()

@@ -33,14 +33,14 @@ def test_byte_models():
 
 
 def test_traffic_only_for_the_profiled_source(monkeypatch):
-    t64, t32 = bench.measured_traffic("fp64", "cfg2"), bench.measured_traffic("fp32", "cfg2")
+    t64, t32 = bench.measured_traffic("fp64", "1024x512"), bench.measured_traffic("fp32", "1024x512")
     if t64 is None:
         pytest.skip("the committed counter summary was taken from another kernel source")
     # above the compulsory bytes of a launch at 1024 x 512, below twice them
     n = 1024 * 512
     assert bench.SWEEP_COMPULSORY["fp64"] * n <= t64 < 2 * bench.SWEEP_COMPULSORY["fp64"] * n
     assert bench.SWEEP_COMPULSORY["fp32"] * n <= t32 < 2 * bench.SWEEP_COMPULSORY["fp32"] * n
-    assert bench.measured_traffic("fp16store", "cfg2") == t32
-    assert bench.measured_traffic("fp64", "cfg1") is None
+    assert bench.measured_traffic("fp16store", "1024x512") == t32
+    assert bench.measured_traffic("fp64", "128x64") is None
     monkeypatch.setattr(bench, "sweep_source_digest", lambda: "0" * 64)
-    assert bench.measured_traffic("fp64", "cfg2") is None
+    assert bench.measured_traffic("fp64", "1024x512") is None

@@ -49,7 +49,7 @@ def errors(g, ref):
 def test_fp16_first_hundred_steps_against_oracle():
     """128 x 64 sessile drop: every field within U16 of the oracle after 10, 20 and 100
     steps (measured at most 1.7e-4, in u), and the sweep counts within 1%."""
-    c = inputs.cfg1(0)
+    c = inputs.drop_128x64(0)
     g, o = solver16(c), ob.Oracle(c)
     t = 0
     for n in (10, 20, 100):
@@ -70,7 +70,7 @@ def test_fp16_thousand_steps_tracks_fp32():
     / 1000 steps); the total sweep count stays within 1% and the phase-field mass within
     1e-4 of the FP64 run's."""
     from paper_2410_06657_amd.lbm import Solver
-    c = inputs.cfg1(0)
+    c = inputs.drop_128x64(0)
     g, f, d = solver16(c), Solver(c, "fp32"), Solver(c)
     t = 0
     for n in (200, 500, 1000):
@@ -122,7 +122,7 @@ def test_fp16_stefan_strip_matches_neumann():
 def test_fp16_full_size():
     """4096 x 2048 with FP16 storage, fixed sweep count, two steps, against the FP64 oracle:
     every field within U16 (measured at most 1.5e-4, in u)."""
-    c = inputs.cfg3()
+    c = inputs.drop_4096x2048()
     c.update(poisson_tol=-1.0, poisson_max_sweeps=8)
     g = solver16(c)
     o = ob.Oracle(c)
@@ -137,7 +137,7 @@ def test_fp16_populations_read_back():
     f, h and g populations are within U16 of the oracle's (relative L2) and the D2Q5 links
     (FP32 pairs) within 1e-6; writing populations is refused in this form."""
     from paper_2410_06657_amd import lbm
-    c = inputs.scaled(inputs.cfg1(2), 64, 32)
+    c = inputs.scaled(inputs.drop_128x64(2), 64, 32)
     g, o = solver16(c), ob.Oracle(c)
     g.step(10)
     o.step(10)
@@ -154,7 +154,7 @@ def test_fp16_populations_read_back():
 def test_fp16_checkpoint_restore():
     """A checkpoint carries the scale exponents and maxima with the binary16 sets: a run
     restored from it continues bitwise like the uninterrupted run."""
-    c = inputs.scaled(inputs.cfg1(3), 96, 48)
+    c = inputs.scaled(inputs.drop_128x64(3), 96, 48)
     a = solver16(c)
     a.step(7)
     img = a.checkpoint()

@@ -55,7 +55,7 @@ def perturbed(solver, seed=1):
 ROUNDINGS = 4
 
 
-def test_fp32_thousand_steps_cfg1():
+def test_fp32_thousand_steps_128x64():
     """The 128 x 64 sessile drop, 1000 steps, FP32 against the FP64 oracle.
 
     The coupled freezing problem amplifies perturbations: the FP64 method itself, restarted
@@ -66,7 +66,7 @@ def test_fp32_thousand_steps_cfg1():
     direct rounding (2e-5 covers it: the first 20 steps are held to that) plus the sum of the
     responses, 4 n max_{m <= n} G(m); that bound is the test."""
     from paper_2410_06657_amd.lbm import Solver
-    c = inputs.cfg1(0)
+    c = inputs.drop_128x64(0)
     g, o = solver32(c), ob.Oracle(c)
     a, b = Solver(c), Solver(c)
     perturbed(b)
@@ -114,7 +114,7 @@ def test_fp32_freezing_time():
 def test_fp32_population_round_trip():
     """Deviation storage is invisible through the ABI: populations and fields read back as
     raw values that match the oracle's initial state to FP32 rounding."""
-    c = inputs.scaled(inputs.cfg1(2), 64, 32)
+    c = inputs.scaled(inputs.drop_128x64(2), 64, 32)
     c.update(poisson_tol=-1.0, poisson_max_sweeps=6)
     g, o = solver32(c), ob.Oracle(c)
     for k in ("f", "h", "g"):
@@ -129,7 +129,7 @@ def test_fp32_population_round_trip():
 
 
 def test_fp32_sweep_block_invariance():
-    c = inputs.scaled(inputs.cfg1(1), 96, 48)
+    c = inputs.scaled(inputs.drop_128x64(1), 96, 48)
     ref = None
     for m, w in ((1, 4), (2, 4), (4, 4), (8, 4), (2, 8), (8, 8)):
         g = solver32(dict(c, sweep_block=m, sweep_waves=w))
@@ -160,7 +160,7 @@ def test_fp32_stefan_strip_matches_neumann():
 
 def test_fp32_full_size_sampled():
     """4096 x 2048 in FP32, fixed sweep count, two steps, against the FP64 oracle."""
-    c = inputs.cfg3()
+    c = inputs.drop_4096x2048()
     c.update(poisson_tol=-1.0, poisson_max_sweeps=8)
     g = solver32(c)
     o = ob.Oracle(c)

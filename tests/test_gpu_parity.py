@@ -49,22 +49,22 @@ def compare(g, o, fields=FIELDS, tol=TOL, pops=True):
     return errs
 
 
-def small_cfg1(seed=0, nx=128, ny=64):
-    c = inputs.cfg1(seed)
+def small_drop(seed=0, nx=128, ny=64):
+    c = inputs.drop_128x64(seed)
     if (nx, ny) != (128, 64):
         c = inputs.scaled(c, nx, ny)
     return c
 
 
 def test_init_matches_oracle():
-    c = small_cfg1(0)
+    c = small_drop(0)
     g, o = solver(c), ob.Oracle(c)
     assert list(g.sweep_log()) == list(o.sweep_log())
     compare(g, o)
 
 
 def test_fixed_sweep_count_matches():
-    c = small_cfg1(1)
+    c = small_drop(1)
     c.update(poisson_max_sweeps=37, poisson_tol=-1.0)
     g, o = solver(c), ob.Oracle(c)
     for _ in range(3):
@@ -77,8 +77,8 @@ def test_fixed_sweep_count_matches():
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_ten_steps_cfg1(seed):
-    c = small_cfg1(seed)
+def test_ten_steps_128x64(seed):
+    c = small_drop(seed)
     g, o = solver(c), ob.Oracle(c)
     g.step(10)
     o.step(10)
@@ -86,9 +86,9 @@ def test_ten_steps_cfg1(seed):
     compare(g, o)
 
 
-def test_thousand_steps_cfg1():
+def test_thousand_steps_128x64():
     """The 128 x 64 sessile-drop workload, 1000 steps, potential to 1e-8 every step."""
-    c = small_cfg1(0)
+    c = small_drop(0)
     g, o = solver(c), ob.Oracle(c)
     for chunk in range(10):
         g.step(100)
@@ -133,7 +133,7 @@ def test_contact_angles_and_volume_change(ratio, theta):
 
 
 def test_without_grad_s_reading():
-    c = small_cfg1(2)
+    c = small_drop(2)
     c["readings"] = 0
     g, o = solver(c), ob.Oracle(c)
     g.step(10)
@@ -144,7 +144,7 @@ def test_without_grad_s_reading():
 def test_set_state_then_step():
     """Inject a state into both sides (set_field / set_pop) and step: the library honours
     externally supplied fields and populations."""
-    c = small_cfg1(0, 64, 32)
+    c = small_drop(0, 64, 32)
     g, o = solver(c), ob.Oracle(c)
     o.step(5)
     for k in ("psi", "ux", "uy", "usx", "usy", "p", "T", "H", "fs", "mdot", "psiu_x", "psiu_y"):
@@ -175,7 +175,7 @@ def test_diagnostics_and_freezing_time():
 
 def test_error_paths():
     from paper_2410_06657_amd import lbm
-    c = small_cfg1(0, 64, 32)
+    c = small_drop(0, 64, 32)
     bad = dict(c, mu_l=-1.0)
     with pytest.raises(lbm.LbmError) as e:
         lbm.Solver(bad)
@@ -193,7 +193,7 @@ def test_error_paths():
 def test_full_size_sampled():
     """The 4096 x 2048 workload in the benchmark's launch configuration: initialise and run
     two steps with a fixed sweep count on both sides, compare every field."""
-    c = inputs.cfg3()
+    c = inputs.drop_4096x2048()
     c.update(poisson_tol=-1.0, poisson_max_sweeps=8)
     g = solver(c)
     o = ob.Oracle(c)
@@ -206,7 +206,7 @@ def test_sweep_block_invariance():
     """Every launch shape (sweeps per launch x waves per workgroup) gives bitwise the same
     state (the per-node arithmetic of a sweep does not depend on the blocking) and the same
     sweep counts as the oracle."""
-    c = small_cfg1(1, 96, 48)
+    c = small_drop(1, 96, 48)
     o = ob.Oracle(c)
     o.step(12)
     ref = None
@@ -229,7 +229,7 @@ def test_checkpoint_restore_continues_bitwise(precision):
     """A checkpoint taken mid-run, restored into a fresh handle of the same case, continues
     bitwise as the original run (fields, populations, sweep log, freezing detector)."""
     from paper_2410_06657_amd.lbm import LbmError, Solver, LBM_EINVAL
-    c = small_cfg1(4, 96, 48)
+    c = small_drop(4, 96, 48)
     a = Solver(c, precision)
     a.step(15)
     img = a.checkpoint()
@@ -245,7 +245,7 @@ def test_checkpoint_restore_continues_bitwise(precision):
     da, db = a.diag(), b.diag()
     assert da["step"] == db["step"] == 25 and da["V_s"] == db["V_s"]
     # an image of another grid is refused
-    other = Solver(small_cfg1(4, 64, 32), precision)
+    other = Solver(small_drop(4, 64, 32), precision)
     with pytest.raises(LbmError) as e:
         other.restore(img)
     assert e.value.code == LBM_EINVAL

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 def test_autotune_choice_cache_and_invariance(precision, tmp_path, monkeypatch):
     from paper_2410_06657_amd import lbm
     monkeypatch.setenv("LBM_TUNE_CACHE", str(tmp_path / "shapes.json"))
-    c = inputs.scaled(inputs.cfg1(3), 256, 128)
+    c = inputs.scaled(inputs.drop_128x64(3), 256, 128)
     r = lbm.autotune(c, precision, launches=10, force=True)
     print(r)
     cands = {(k["sweep_block"], k["sweep_waves"]): k["us_per_sweep"] for k in r["candidates"]}

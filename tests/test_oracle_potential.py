@@ -64,7 +64,7 @@ def test_circular_inclusion_field(R):
 
 
 def test_stop_rule_and_cap():
-    c = inputs.cfg1(0)
+    c = inputs.drop_128x64(0)
     c.update(nx=32, ny=16, R0=6.0, xc=16.0)
     o = Oracle(c, init=False)
     o.init()
