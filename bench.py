@@ -457,7 +457,7 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
 def counters_probe(case, launches=20):
     """Short run for hardware-counter passes (rocprofv3 --pmc): a plain copy kernel of known
     size (the calibration of the byte counters), then `launches` blocked sweep launches and
-    three steps per precision on the workload's grid.  The initial potential solve is capped at 16 sweeps so
+    three steps per precision (FP64, FP32, FP16 storage) on the workload's grid.  The initial potential solve is capped at 16 sweeps so
     the run stays short; a launch's memory traffic does not depend on convergence."""
     import torch
 
@@ -473,7 +473,7 @@ def counters_probe(case, launches=20):
     del src, dst
     c = dict(case, poisson_max_sweeps=16, poisson_tol=-1.0)
     m = c.get("sweep_block") or 8
-    for precision in ("fp64", "fp32"):
+    for precision in ("fp64", "fp32", "fp16store"):
         s = Solver(c, precision=precision)
         s.time_sweeps(launches * m)
         s.step(3)  # the stage kernels of a step (with 16-sweep solves)
