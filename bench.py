@@ -380,7 +380,13 @@ def run_validation():
         "wall_s": round(time.perf_counter() - t0, 2),
         "rows": [{"rho_s_over_rho_l": r["rho_s_over_rho_l"], "Ste": r["Ste"], "mode": r["mode"],
                   "t_fre": round(r["t_fre"], 1), "H_m_over_H_0": round(r["H_m_over_H_0"], 4),
-                  "t_star": round(r["t_star"], 4)} for r in ps]}
+                  "t_star": round(r["t_star"], 4),
+                  "substrate_flux": {"first": {"Fo": round(r["substrate_flux"][0][0], 3),
+                                               "flux": float(f"{r['substrate_flux'][0][1]:.4g}")},
+                                     "last": {"Fo": round(r["substrate_flux"][-1][0], 3),
+                                              "flux": float(f"{r['substrate_flux'][-1][1]:.4g}")}}}
+                 for r in ps],
+        "ste_fo_law": {k: round(v, 4) for k, v in v.ste_fo_law(ps).items()}}
     print(f"[bench] validation: parameter study {out['parameter_study']['wall_s']}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     cw = v.cold_wall()

@@ -11,7 +11,8 @@
   final volume against rho_l/rho_s, height, contact radius and apex shape.
 * The electrofreezing study of Sec. 5: a wetting drop (theta = 120 deg) frozen without a field
   and in the PR+, OB- and PR- modes of its R-S diagram at several Stefan numbers and
-  solid/liquid density ratios: final heights and the relative change of the freezing time.
+  solid/liquid density ratios: final heights, the relative change of the freezing time, the
+  heat flux into the substrate over time, and the H_m/R_0 ~ (Ste Fo)^(1/2) law of Sec. 5.
 
 Freezing is off for the free drops (T_w = T_g above T_m).  Inputs come from
 `inputs.free_drop`, `inputs.stefan_strip` and `inputs.sessile_drop`.
@@ -159,27 +160,68 @@ def drop_height(psi: np.ndarray, case: dict) -> float:
     return b + (col[b] - 0.5) / (col[b] - col[b + 1]) + 0.5
 
 
+def substrate_heat_flux(T: np.ndarray, psi: np.ndarray, fs: np.ndarray, case: dict) -> np.ndarray:
+    """Heat flux into the substrate along x, lambda dT/dy at the bottom row (Sec. 5: Fourier's
+    law with the second-order one-sided difference (4 T_1 - T_2 - 3 T_0) / (2 dy) on the rows
+    j = 0, 1, 2 above the wall, R31); lambda of the bottom row mixed by Eq. (1) with psi clamped.
+    Positive when heat leaves the drop into the cold substrate (the paper's Qdot is its
+    negative)."""
+    pc = np.clip(psi[0], 0.0, 1.0)
+    f = fs[0]
+    lam = f * case["k_s"] + (1 - f) * pc * case["k_l"] + (1 - f) * (1 - pc) * case["k_g"]
+    return lam * (4.0 * T[1] - T[2] - 3.0 * T[0]) / 2.0
+
+
+def ste_fo_law(rows: list[dict]) -> dict:
+    """Sec. 5's freezing-time law H_m / R_0 ~ (Ste Fo)^(1/2) over the study's cases: the slope
+    of log(H_m/R_0) against log(Ste Fo) (least squares) and the spread of the coefficient
+    (H_m/R_0) / (Ste Fo)^(1/2) (max over min)."""
+    x = np.log([r["Ste"] * r["Fo"] for r in rows])
+    y = np.log([r["H_m_over_R_0"] for r in rows])
+    slope = float(np.polyfit(x, y, 1)[0])
+    c = np.exp(y - 0.5 * x)
+    return {"slope": slope, "coefficient_spread": float(c.max() / c.min()), "coefficient_mean": float(c.mean())}
+
+
 def parameter_study(stes=(0.05, 0.1, 0.2), ratios=(0.9, 1.1), nx: int = 160, ny: int = 80,
                     R0: float = 20.0, theta: float = 120.0, precision: str = "fp64",
-                    max_steps: int = 100000) -> list[dict]:
+                    max_steps: int = 100000, sample_every: int = 1000) -> list[dict]:
     """Sec. 5's electrofreezing study at theta = 120 deg, alpha_l/alpha_g = 0.2: every field
     mode at every Stefan number and solid/liquid density ratio, run to its freezing time
     (1% of the liquid left) as one batch.  Per case: t_fre, Fo = alpha_l t_fre / R0^2, the final
-    height H_m over the initial H_0, and t* = (t_fre - t_fre(no field)) / t_fre(no field)."""
+    height H_m over the initial H_0 and over R_0, t* = (t_fre - t_fre(no field)) / t_fre(no
+    field), and the mean heat flux into the substrate under the drop (contact region: bottom-row
+    psi >= 1/2) every `sample_every` steps until the case freezes, as (Fo, flux) pairs."""
     from .lbm import Batch
     keys = [(r, s, m) for r in ratios for s in stes for m in MODES]
     cases = [inputs.sessile_drop(nx, ny, R0, theta, *MODES[m][:2], MODES[m][2], s, seed=None, rho_ratio_sl=r)
              for r, s, m in keys]
     b = Batch(cases, precision=precision)
     h0 = [drop_height(b.field(k, "psi"), cases[k]) for k in range(len(keys))]
-    b.run_until_frozen(max_steps)
+    alpha = [c["k_l"] / (c["rho_l"] * c["cp_l"]) for c in cases]
+    flux = [[] for _ in keys]
+    done = 0
+    while done < max_steps:
+        n = b.run_until_frozen(min(sample_every, max_steps - done))
+        done += n
+        d = b.diag()
+        for k in range(len(keys)):
+            if flux[k] and flux[k][-1][0] == alpha[k] * d[k]["step"] / R0 ** 2:
+                continue  # frozen: no new sample
+            psi = b.field(k, "psi")
+            q = substrate_heat_flux(b.field(k, "T"), psi, b.field(k, "fs"), cases[k])
+            foot = psi[0] >= 0.5
+            flux[k].append((alpha[k] * d[k]["step"] / R0 ** 2, float(q[foot].mean()) if foot.any() else 0.0))
+        if n < sample_every:
+            break
     d = b.diag()
     rows = []
     for k, (r, s, m) in enumerate(keys):
-        alpha_l = cases[k]["k_l"] / (cases[k]["rho_l"] * cases[k]["cp_l"])
+        hm = drop_height(b.field(k, "psi"), cases[k])
         rows.append({"rho_s_over_rho_l": r, "Ste": s, "mode": m, "t_fre": d[k]["t_fre"],
-                     "Fo": alpha_l * d[k]["t_fre"] / R0 ** 2,
-                     "H_m_over_H_0": drop_height(b.field(k, "psi"), cases[k]) / h0[k]})
+                     "Fo": alpha[k] * d[k]["t_fre"] / R0 ** 2,
+                     "H_m_over_H_0": hm / h0[k], "H_m_over_R_0": hm / R0,
+                     "substrate_flux": flux[k]})
     base = {(x["rho_s_over_rho_l"], x["Ste"]): x["t_fre"] for x in rows if x["mode"] == "none"}
     for x in rows:
         t0 = base[(x["rho_s_over_rho_l"], x["Ste"])]

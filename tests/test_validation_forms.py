@@ -38,3 +38,26 @@ def test_measurement_helpers():
     # the wall at -1/2
     fl = np.clip((np.arange(32) - 6.75) / 4.0 + 0.5, 0, 1)
     assert validation.front(fl) == pytest.approx(7.25, abs=1e-12)
+
+
+def test_substrate_heat_flux_and_freezing_time_law():
+    import numpy as np
+    # the second-order one-sided difference is exact for a quadratic profile in y:
+    # T = 1 + 0.3 j + 0.05 j^2 has dT/dy = 0.3 at j = 0
+    ny, nx = 8, 6
+    j = np.arange(ny, dtype=float)[:, None] * np.ones((1, nx))
+    T = 1.0 + 0.3 * j + 0.05 * j ** 2
+    case = {"k_l": 2.0, "k_g": 0.5, "k_s": 4.0}
+    psi = np.zeros((ny, nx))
+    psi[0, :3] = 1.0            # liquid over the first three columns, gas beyond
+    fs = np.zeros((ny, nx))
+    fs[0, 1] = 1.0              # one solid column
+    q = validation.substrate_heat_flux(T, psi, fs, case)
+    assert q == pytest.approx(0.3 * np.array([2.0, 4.0, 2.0, 0.5, 0.5, 0.5]), rel=1e-12)
+    # rows that follow H_m/R_0 = C (Ste Fo)^(1/2) exactly: slope 1/2, no spread
+    rows = [{"Ste": s, "Fo": fo, "H_m_over_R_0": 1.7 * math.sqrt(s * fo)}
+            for s, fo in ((0.05, 4.0), (0.1, 1.5), (0.2, 3.0), (0.5, 0.4))]
+    law = validation.ste_fo_law(rows)
+    assert law["slope"] == pytest.approx(0.5, abs=1e-12)
+    assert law["coefficient_spread"] == pytest.approx(1.0, abs=1e-12)
+    assert law["coefficient_mean"] == pytest.approx(1.7, rel=1e-12)
