@@ -19,6 +19,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coupled MLUPS + % HBM roofline; time-to-freeze, plain FP64 vs FP32/batched/warm"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+INFINITY_CACHE_BYTES = 256 << 20  # MI355X last-level (Infinity) cache in front of HBM
 # algorithmic bytes per node (element size s): a potential sweep reads 4 links, phi and
 # 1/tau_l and writes 4 links and phi (11 s); a step outside the sweeps moves 27 + 27
 # populations and 13 + 13 fields (80 s)
@@ -154,18 +155,26 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name="1024
     es = ELEM[precision]
     per_launch = SWEEP_ELEMS * es * n * m
     achieved = per_launch / launch_s / 1e9
+    compulsory = SWEEP_COMPULSORY[precision] * n
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(precision, workload_name) if m == 8 else None,
                 "kernel": f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>",
                 "avg_launch_us": round(launch_s * 1e6, 3), "sweeps_per_launch": m,
                 "algorithmic_bytes_per_launch": per_launch,
-                "compulsory_hbm_bytes_per_launch": SWEEP_COMPULSORY[precision] * n}
+                "compulsory_hbm_bytes_per_launch": compulsory,
+                # a launch whose compulsory bytes fit the Infinity Cache may be served from it, so
+                # its byte counters (L2 misses) and "% HBM" are not HBM-only figures
+                "working_set_fits_infinity_cache": compulsory <= INFINITY_CACHE_BYTES}
     coupled_bytes = (STEP_BYTES[precision] + SWEEP_ELEMS * kmean * es) * n
     coupled_gbs = coupled_bytes / (ms_step * 1e-3) / 1e9
+    q = np.percentile(sweeps, [0, 10, 50, 90, 100])
     return {
         "value": round(n * steps / dt / 1e6, 3), "ms_per_step": round(ms_step, 4),
         "sweeps_per_step": round(kmean, 2),
+        "sweeps_per_step_distribution": {"min": int(q[0]), "p10": float(q[1]), "p50": float(q[2]),
+                                         "p90": float(q[3]), "max": int(q[4])},
+        "sweep_mlups": round(n * m / launch_s / 1e6, 1),
         "sweep_time_share": round(min(1.0, kmean / m * launch_s * 1e3 / ms_step), 4),
         "coupled_algorithmic_GBs": round(coupled_gbs, 1),
         "coupled_hbm_roofline_frac": round(coupled_gbs / HBM_PEAK_GBS, 4),
@@ -201,6 +210,13 @@ def run_precision_full_size(steps=10, sweeps=8, compare_after=2):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         r = {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 4)}
+        # the sweep kernel at this size (its working set is far beyond the Infinity Cache)
+        launches = 10
+        launch_s = s.time_sweeps(launches * 8) * 1e-3 / launches
+        achieved = SWEEP_ELEMS * ELEM[prec] * n * 8 / launch_s / 1e9
+        r["sweep_roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(launch_s * 1e6, 2),
+                               "sweep_mlups": round(n * 8 / launch_s / 1e6, 1)}
         if ref is None:
             ref = cur
         else:
@@ -531,6 +547,8 @@ def main():
         "config": {"workload": desc, "nx": case["nx"], "ny": case["ny"], "precision": "fp64",
                    "poisson_tol": case["poisson_tol"], "sweeps_per_launch": case["sweep_block"] or 8},
         "sweeps_per_step": f64["sweeps_per_step"],
+        "sweeps_per_step_distribution": f64["sweeps_per_step_distribution"],
+        "sweep_mlups": f64["sweep_mlups"],
         "sweep_time_share": f64["sweep_time_share"],
         "coupled_hbm_roofline_frac": f64["coupled_hbm_roofline_frac"],
         "coupled_algorithmic_GBs": f64["coupled_algorithmic_GBs"],

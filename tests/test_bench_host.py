@@ -44,3 +44,29 @@ def test_traffic_only_for_the_profiled_source(monkeypatch):
     assert bench.measured_traffic("fp64", "128x64") is None
     monkeypatch.setattr(bench, "sweep_source_digest", lambda: "0" * 64)
     assert bench.measured_traffic("fp64", "1024x512") is None
+
+
+def test_main_line_contract(monkeypatch, capsys):
+    """The JSON line's keys, with the GPU measurement replaced by a stand-in of the same shape."""
+    import json
+
+    def fake_form(case, precision, steps, warmup, sweep_launches, workload_name="1024x512"):
+        return {"value": 1000.0, "ms_per_step": 0.5, "sweeps_per_step": 80.0,
+                "sweeps_per_step_distribution": {"min": 70, "p10": 72.0, "p50": 80.0, "p90": 90.0, "max": 95},
+                "sweep_mlups": 2e5, "sweep_time_share": 0.5, "coupled_hbm_roofline_frac": 1.0,
+                "coupled_algorithmic_GBs": 8000.0, "init_s": 1.0,
+                "roofline": {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 1.25e-4,
+                             "traffic": None},
+                "state": {"step": 65, "V_s": 0.0, "height": 1.0, "nonfinite": 0}}
+
+    monkeypatch.setattr(bench, "run_form", fake_form)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-fp32", "--no-time-to-freeze", "--no-validation",
+                                      "--no-warm", "--no-batched", "--no-cpu-baseline"])
+    bench.main()
+    line = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "sweeps_per_step",
+              "sweeps_per_step_distribution", "sweep_mlups"):
+        assert k in line, k
+    assert line["n_gpus"] == 1 and line["config"]["nx"] == 1024 and line["dtype"] == "f64"
+    assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
