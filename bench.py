@@ -91,6 +91,25 @@ def workload(name):
     return c, desc
 
 
+def host_cpu():
+    """The host's CPU model (first "model name" of /proc/cpuinfo) and the cores this process
+    may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": usable}
+
+
 def cpu_baseline(case, k_sweeps, budget_s=25.0):
     """Oracle on the host cores: per-sweep time and the rest of a step, measured on the same
     grid, combined into one coupled step with the GPU's mean sweep count."""
@@ -112,6 +131,7 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
     step_s = rest + k_sweeps * per_sweep
     n = case["nx"] * case["ny"]
     return {"value": n / step_s / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sweeps_per_s": 1.0 / per_sweep, "host": host_cpu(),
             "sample": f"{case['nx']}x{case['ny']} grid: {nsw} timed oracle sweeps "
                       f"({per_sweep * 1e3:.2f} ms each) and one step with two sweeps "
                       f"({rest * 1e3:.1f} ms besides the sweep), combined as one step with "

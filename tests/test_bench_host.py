@@ -70,3 +70,9 @@ def test_main_line_contract(monkeypatch, capsys):
         assert k in line, k
     assert line["n_gpus"] == 1 and line["config"]["nx"] == 1024 and line["dtype"] == "f64"
     assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
+
+
+def test_host_cpu():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1
+    assert h["cpu_model"] is None or isinstance(h["cpu_model"], str)
