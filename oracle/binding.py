@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 FIELDS = ["psi", "ux", "uy", "usx", "usy", "p", "T", "H", "fs", "mdot",
           "psiu_x", "psiu_y", "phi", "fl"]
-POPS = {"f": (0, 9), "h": (1, 9), "g": (2, 9), "l": (3, 5)}
+POPS = {"f": (0, 9), "h": (1, 9), "g": (2, 9), "l": (3, 5), "g_post": (4, 9)}
 R_GRAD_S = 1
 
 
@@ -47,10 +47,48 @@ class OrcDiag(C.Structure):
         ("front_y", C.c_double), ("height", C.c_double), ("max_u", C.c_double),
         ("resid", C.c_double), ("sweeps", C.c_int), ("noconv", C.c_int),
         ("t_fre", C.c_double), ("V_l0", C.c_double), ("nonfinite", C.c_int),
+        ("op_resid", C.c_double), ("op_resid_ramp", C.c_double),
     ]
 
 
 _lib = None
+
+
+def _bind(L):
+    """Declare the argument types of every entry point of an oracle library."""
+    dp = C.POINTER(C.c_double)
+    L.orc_create.argtypes = [C.POINTER(OrcParams), C.POINTER(C.c_void_p)]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_destroy.restype = None
+    L.orc_init.argtypes = [C.c_void_p]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int]
+    L.orc_solve_potential.argtypes = [C.c_void_p, C.c_double, C.c_int,
+                                      C.POINTER(C.c_int), dp]
+    L.orc_get_field.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_set_field.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_get_pop.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_set_pop.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(OrcDiag)]
+    L.orc_sweep_log.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_int,
+                                C.POINTER(C.c_int)]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_node_f.argtypes = [C.c_double] * 6 + [dp, dp]
+    L.orc_node_f.restype = None
+    L.orc_node_h.argtypes = [C.c_double] * 9 + [dp, dp]
+    L.orc_node_h.restype = None
+    L.orc_node_g.argtypes = [C.c_double] * 6 + [dp]
+    L.orc_node_g.restype = None
+    L.orc_node_l.argtypes = [C.c_double, dp]
+    L.orc_node_l.restype = None
+    L.orc_invert_enthalpy.argtypes = [C.POINTER(OrcParams), C.c_double, C.c_double, dp, dp]
+    L.orc_stencil.argtypes = [C.POINTER(OrcParams), dp, C.c_int, dp, dp, dp]
+    return L
+
+
+def load(path: str):
+    """Another build of the oracle's source (the tests build deliberately broken copies to
+    show that the pins catch them); pass the result as `L` to Oracle and the node functions."""
+    return _bind(C.CDLL(path))
 
 
 def lib():
@@ -59,34 +97,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        dp = C.POINTER(C.c_double)
-        L.orc_create.argtypes = [C.POINTER(OrcParams), C.POINTER(C.c_void_p)]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_destroy.restype = None
-        L.orc_init.argtypes = [C.c_void_p]
-        L.orc_step.argtypes = [C.c_void_p, C.c_int]
-        L.orc_solve_potential.argtypes = [C.c_void_p, C.c_double, C.c_int,
-                                          C.POINTER(C.c_int), dp]
-        L.orc_get_field.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_set_field.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_get_pop.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_set_pop.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(OrcDiag)]
-        L.orc_sweep_log.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_int,
-                                    C.POINTER(C.c_int)]
-        L.orc_set_threads.argtypes = [C.c_int]
-        L.orc_node_f.argtypes = [C.c_double] * 6 + [dp, dp]
-        L.orc_node_f.restype = None
-        L.orc_node_h.argtypes = [C.c_double] * 9 + [dp, dp]
-        L.orc_node_h.restype = None
-        L.orc_node_g.argtypes = [C.c_double] * 6 + [dp]
-        L.orc_node_g.restype = None
-        L.orc_node_l.argtypes = [C.c_double, dp]
-        L.orc_node_l.restype = None
-        L.orc_invert_enthalpy.argtypes = [C.POINTER(OrcParams), C.c_double, C.c_double, dp, dp]
-        L.orc_stencil.argtypes = [C.POINTER(OrcParams), dp, C.c_int, dp, dp, dp]
-        _lib = L
+        _lib = _bind(C.CDLL(LIB_PATH))
     return _lib
 
 
@@ -104,19 +115,20 @@ def make_params(case: dict) -> OrcParams:
     return p
 
 
-def set_threads(n: int) -> None:
-    lib().orc_set_threads(int(n))
+def set_threads(n: int, L=None) -> None:
+    (L or lib()).orc_set_threads(int(n))
 
 
 class Oracle:
     """One oracle run.  Mirrors the GPU binding's methods so tests read alike."""
 
-    def __init__(self, case: dict, init: bool = True):
+    def __init__(self, case: dict, init: bool = True, L=None):
+        self._L = L or lib()
         self.case = dict(case)
         self.params = make_params(case)
         self.nx, self.ny = int(case["nx"]), int(case["ny"])
         h = C.c_void_p()
-        rc = lib().orc_create(C.byref(self.params), C.byref(h))
+        rc = self._L.orc_create(C.byref(self.params), C.byref(h))
         if rc != 0:
             raise ValueError(f"orc_create failed ({rc})")
         self._h = h
@@ -125,44 +137,44 @@ class Oracle:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().orc_destroy(self._h)
+            self._L.orc_destroy(self._h)
             self._h = None
 
     __del__ = close
 
     def init(self):
-        rc = lib().orc_init(self._h)
+        rc = self._L.orc_init(self._h)
         if rc != 0:
             raise RuntimeError(f"orc_init failed ({rc})")
 
     def step(self, n: int = 1):
-        rc = lib().orc_step(self._h, int(n))
+        rc = self._L.orc_step(self._h, int(n))
         if rc != 0:
             raise RuntimeError(f"orc_step failed ({rc})")
 
     def solve_potential(self, tol: float, max_sweeps: int):
         k = C.c_int()
         r = C.c_double()
-        rc = lib().orc_solve_potential(self._h, float(tol), int(max_sweeps), C.byref(k), C.byref(r))
+        rc = self._L.orc_solve_potential(self._h, float(tol), int(max_sweeps), C.byref(k), C.byref(r))
         return rc, k.value, r.value
 
     def field(self, name: str) -> np.ndarray:
         out = np.empty((self.ny, self.nx), dtype=np.float64)
-        rc = lib().orc_get_field(self._h, FIELDS.index(name), _dp(out))
+        rc = self._L.orc_get_field(self._h, FIELDS.index(name), _dp(out))
         if rc != 0:
             raise ValueError(name)
         return out
 
     def set_field(self, name: str, arr):
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(self.ny, self.nx)
-        rc = lib().orc_set_field(self._h, FIELDS.index(name), _dp(a))
+        rc = self._L.orc_set_field(self._h, FIELDS.index(name), _dp(a))
         if rc != 0:
             raise ValueError(name)
 
     def pop(self, name: str) -> np.ndarray:
         idx, nq = POPS[name]
         out = np.empty((nq, self.ny, self.nx), dtype=np.float64)
-        rc = lib().orc_get_pop(self._h, idx, _dp(out))
+        rc = self._L.orc_get_pop(self._h, idx, _dp(out))
         if rc != 0:
             raise ValueError(name)
         return out
@@ -170,62 +182,62 @@ class Oracle:
     def set_pop(self, name: str, arr):
         idx, nq = POPS[name]
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(nq, self.ny, self.nx)
-        rc = lib().orc_set_pop(self._h, idx, _dp(a))
+        rc = self._L.orc_set_pop(self._h, idx, _dp(a))
         if rc != 0:
             raise ValueError(name)
 
     def diag(self) -> dict:
         d = OrcDiag()
-        lib().orc_diagnostics(self._h, C.byref(d))
+        self._L.orc_diagnostics(self._h, C.byref(d))
         return {k: getattr(d, k) for k, _ in OrcDiag._fields_}
 
     def sweep_log(self) -> np.ndarray:
         cnt = C.c_int()
-        lib().orc_sweep_log(self._h, None, 0, C.byref(cnt))
+        self._L.orc_sweep_log(self._h, None, 0, C.byref(cnt))
         n = min(cnt.value, 1 << 16)
         buf = (C.c_int * max(n, 1))()
-        lib().orc_sweep_log(self._h, buf, n, C.byref(cnt))
+        self._L.orc_sweep_log(self._h, buf, n, C.byref(cnt))
         return np.array(buf[:n], dtype=np.int64)
 
 
 # ---- node-level pieces -------------------------------------------------------------------
 
-def node_f(psi, ux, uy, Ax, Ay, mdot):
+def node_f(psi, ux, uy, Ax, Ay, mdot, L=None):
     feq = np.empty(9); F = np.empty(9)
-    lib().orc_node_f(psi, ux, uy, Ax, Ay, mdot, _dp(feq), _dp(F))
+    (L or lib()).orc_node_f(psi, ux, uy, Ax, Ay, mdot, _dp(feq), _dp(F))
     return feq, F
 
 
-def node_h(p, rho, ux, uy, S, Ftx, Fty, Gx, Gy):
+def node_h(p, rho, ux, uy, S, Ftx, Fty, Gx, Gy, L=None):
     heq = np.empty(9); R = np.empty(9)
-    lib().orc_node_h(p, rho, ux, uy, S, Ftx, Fty, Gx, Gy, _dp(heq), _dp(R))
+    (L or lib()).orc_node_h(p, rho, ux, uy, S, Ftx, Fty, Gx, Gy, _dp(heq), _dp(R))
     return heq, R
 
 
-def node_g(H, T, Cv, Cref, ux, uy):
+def node_g(H, T, Cv, Cref, ux, uy, L=None):
     geq = np.empty(9)
-    lib().orc_node_g(H, T, Cv, Cref, ux, uy, _dp(geq))
+    (L or lib()).orc_node_g(H, T, Cv, Cref, ux, uy, _dp(geq))
     return geq
 
 
-def node_l(phi):
+def node_l(phi, L=None):
     leq = np.empty(5)
-    lib().orc_node_l(phi, _dp(leq))
+    (L or lib()).orc_node_l(phi, _dp(leq))
     return leq
 
 
-def invert_enthalpy(case: dict, H: float, psi: float):
+def invert_enthalpy(case: dict, H: float, psi: float, L=None):
     p = make_params(case)
     T = C.c_double(); fl = C.c_double()
-    lib().orc_invert_enthalpy(C.byref(p), float(H), float(psi), C.byref(T), C.byref(fl))
+    (L or lib()).orc_invert_enthalpy(C.byref(p), float(H), float(psi), C.byref(T), C.byref(fl))
     return T.value, fl.value
 
 
-def stencil(case: dict, field, ghost: int):
+def stencil(case: dict, field, ghost: int, L=None):
     p = make_params(case)
     a = np.ascontiguousarray(field, dtype=np.float64)
     gx = np.empty_like(a); gy = np.empty_like(a); lap = np.empty_like(a)
-    rc = lib().orc_stencil(C.byref(p), _dp(a), int(ghost), _dp(gx), _dp(gy), _dp(lap))
+    rc = (L or lib()).orc_stencil(C.byref(p), _dp(a), int(ghost), _dp(gx), _dp(gy), _dp(lap))
     if rc != 0:
         raise ValueError("stencil")
     return gx, gy, lap

@@ -734,6 +734,7 @@ static double* pop_ptr(const orc_state* s, int set, int* nq) {
         case ORC_POP_H: *nq = 9; return s->h;
         case ORC_POP_G: *nq = 9; return s->g;
         case ORC_POP_L: *nq = 5; return s->l;
+        case ORC_POP_G_POST: *nq = 9; return s->gt;
         default: return NULL;
     }
 }
@@ -745,6 +746,7 @@ int orc_get_pop(const orc_state* s, int set, double* dst) {
     return ORC_OK;
 }
 int orc_set_pop(orc_state* s, int set, const double* src) {
+    if (set == ORC_POP_G_POST) return ORC_EINVAL; /* a record of the last step, not state */
     int nq = 0;
     double* ptr = s ? pop_ptr(s, set, &nq) : NULL;
     if (!ptr || !src) return ORC_EINVAL;
@@ -757,6 +759,51 @@ int orc_sweep_log(const orc_state* s, int* dst, int cap, int* count) {
     if (dst)
         for (int k = 0; k < n && k < cap; k++) dst[k] = s->log[k];
     if (count) *count = s->log_n;
+    return ORC_OK;
+}
+
+/* ||div(sigma grad phi)|| of the potential equation (Sec. 2) in the discrete form of Eq. (36):
+   grad(sigma).grad(phi) + sigma lap(phi) at every node, with sigma mixed by Eq. (1) from the
+   current psi and f_s (ghost rows: psi by the wetting rule, f_s mirrored, phi Dirichlet at the
+   electrodes).  *ramp gets the same norm for the linear electrode ramp. */
+static int operator_residual(const orc_state* s, double* res, double* ramp) {
+    const orc_params* p = &s->p;
+    int nx = s->nx, ny = s->ny;
+    size_t NP = (size_t)(ny + 2) * nx;
+    double* Ppsi = malloc(sizeof(double) * NP);
+    double* Pfs = malloc(sizeof(double) * NP);
+    double* Pphi = malloc(sizeof(double) * NP);
+    double* Plin = malloc(sizeof(double) * NP);
+    double* lin = malloc(sizeof(double) * (size_t)s->N);
+    if (!Ppsi || !Pfs || !Pphi || !Plin || !lin) {
+        free(Ppsi); free(Pfs); free(Pphi); free(Plin); free(lin);
+        return ORC_ENOMEM;
+    }
+    pad_field(s, s->fld[ORC_PSI], GH_WET, Ppsi);
+    pad_field(s, s->fld[ORC_FS], GH_MIRROR, Pfs);
+    pad_field(s, s->fld[ORC_PHI], GH_PHI, Pphi);
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++)
+            lin[(size_t)j * nx + i] = p->phi_bot + (p->phi_top - p->phi_bot) * (j + 0.5) / ny;
+    pad_field(s, lin, GH_PHI, Plin);
+    /* sigma on the padded grid (reuses the f_s array) */
+    for (size_t r = 0; r < NP; r++) Pfs[r] = mix(p->sig_s, p->sig_l, p->sig_g, Ppsi[r], Pfs[r]);
+    double a = 0, b = 0;
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            double gsx, gsy, gpx, gpy, lap, glx, gly, llap;
+            stencil_at(s, Pfs, i, j, &gsx, &gsy, NULL);
+            stencil_at(s, Pphi, i, j, &gpx, &gpy, &lap);
+            stencil_at(s, Plin, i, j, &glx, &gly, &llap);
+            double sg = Pfs[(size_t)(j + 1) * nx + i];
+            double v = gsx * gpx + gsy * gpy + sg * lap;
+            double w = gsx * glx + gsy * gly + sg * llap;
+            a += v * v;
+            b += w * w;
+        }
+    *res = sqrt(a);
+    *ramp = sqrt(b);
+    free(Ppsi); free(Pfs); free(Pphi); free(Plin); free(lin);
     return ORC_OK;
 }
 
@@ -821,5 +868,5 @@ int orc_diagnostics(const orc_state* s, orc_diag* d) {
     d->noconv = s->noconv;
     d->t_fre = s->t_fre;
     d->V_l0 = s->V_l0;
-    return ORC_OK;
+    return operator_residual(s, &d->op_resid, &d->op_resid_ramp);
 }

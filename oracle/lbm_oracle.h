@@ -66,8 +66,9 @@ enum {
     ORC_FS, ORC_MDOT, ORC_PSIU_X, ORC_PSIU_Y, ORC_PHI, ORC_FL,
     ORC_NFIELDS
 };
-/* Population sets: [q][j][i]. */
-enum { ORC_POP_F = 0, ORC_POP_H = 1, ORC_POP_G = 2, ORC_POP_L = 3 };
+/* Population sets: [q][j][i].  ORC_POP_G_POST (read only) is the post-collision g of the
+   last step, before streaming: what the enthalpy budget of the walls is written in. */
+enum { ORC_POP_F = 0, ORC_POP_H = 1, ORC_POP_G = 2, ORC_POP_L = 3, ORC_POP_G_POST = 4 };
 
 typedef struct orc_diag {
     long long step;
@@ -82,6 +83,12 @@ typedef struct orc_diag {
     double t_fre;             /* interpolated freezing step, -1 if not yet */
     double V_l0;              /* V_l at initialisation */
     int nonfinite;
+    /* operator residual of the potential equation div(sigma grad phi) = 0 (Sec. 2), written
+       with the isotropic stencils of Eq. (36) as grad(sigma).grad(phi) + sigma lap(phi), sigma
+       mixed by Eq. (1) from the current psi and f_s: its L2 norm over the grid for the current
+       phi, and for the linear electrode ramp with the same sigma (the residual the solve
+       starts from; 0 when sigma is uniform) */
+    double op_resid, op_resid_ramp;
 } orc_diag;
 
 typedef struct orc_state orc_state;

@@ -44,19 +44,23 @@ def test_flat_interface_keeps_the_tanh_profile():
     assert abs(y0 - 19.5) < 0.05  # the layer neither grows nor shrinks
 
 
-def test_laplace_pressure_jump(threads):
+def check_laplace(L=None):
     """2D static drop: p_in - p_out = gamma / R.  The isotropic stencils resolve a tanh of
     width W with an O((dx/W)^2) loss in mu grad(psi); measured ratios 0.940 (W=4), 0.986
     (W=6), 1.002 (W=8) at R/W = 3-4.5, so the pin runs at W = 6 within 3%."""
     c = inputs.free_drop(72, 72, 15.0, R=1.0, S=1.0, Ca_E=0.0)
     c["W"] = 6.0
-    o = Oracle(c)
+    o = Oracle(c, L=L)
     o.step(4000)
     p, psi = o.field("p"), o.field("psi")
     R = math.sqrt(psi.clip(0, 1).sum() / math.pi)
     dp = p[36, 36] - p[0, 0]
     assert dp == pytest.approx(c["gamma"] / R, rel=0.03)
     assert o.diag()["max_u"] < 1e-4
+
+
+def test_laplace_pressure_jump(threads):
+    check_laplace()
 
 
 def test_conduction_from_cold_substrate():
@@ -74,13 +78,12 @@ def test_conduction_from_cold_substrate():
     assert np.max(np.abs(T - ref)) < 0.01 * abs(c["T_w"] - c["T_g"])
 
 
-@pytest.mark.parametrize("ste", [0.1, 0.2])
-def test_one_phase_neumann_front(ste):
+def check_neumann(ste, L=None):
     """Liquid at T_m on a substrate at T_w = -Ste: the front sits at s = 2 lambda sqrt(alpha_s t)
     (Neumann), measured from the wall as the f_l = 1/2 crossing."""
     alpha_s = 0.2
     c = inputs.stefan_strip(4, 48, h0=1e6, Ste=ste, rho_ratio_sl=1.0, alpha_s=alpha_s)
-    o = Oracle(c)
+    o = Oracle(c, L=L)
     lam = neumann_lambda(ste)
     errs = []
     done = 0
@@ -95,11 +98,15 @@ def test_one_phase_neumann_front(ste):
     assert max(errs) < 0.02, errs
 
 
-@pytest.mark.parametrize("ratio", [0.9, 1.1])
-def test_final_height_with_volume_change(ratio):
+@pytest.mark.parametrize("ste", [0.1, 0.2])
+def test_one_phase_neumann_front(ste):
+    check_neumann(ste)
+
+
+def check_final_height(ratio, L=None):
     """A liquid layer freezing completely ends at h_f = rho_l h_0 / rho_s (mass conservation)."""
     c = inputs.stefan_strip(4, 48, h0=16.0, Ste=0.5, rho_ratio_sl=ratio)
-    o = Oracle(c)
+    o = Oracle(c, L=L)
     v0 = o.field("psi").clip(0, 1).sum() / 4
     for _ in range(40):
         o.step(250)
@@ -109,3 +116,8 @@ def test_final_height_with_volume_change(ratio):
     assert d["V_l"] < 1e-3 * d["V_l0"], "layer did not freeze"
     v1 = o.field("psi").clip(0, 1).sum() / 4
     assert v1 / v0 == pytest.approx(1 / ratio, rel=0.01)
+
+
+@pytest.mark.parametrize("ratio", [0.9, 1.1])
+def test_final_height_with_volume_change(ratio):
+    check_final_height(ratio)

@@ -14,15 +14,19 @@ def _uniform_case(nx, ny):
     return c
 
 
-def test_linear_profile_is_an_exact_fixed_point():
+def check_linear_fixed_point(L=None):
     """Uniform sigma: the linear profile between the electrodes (walls half a link outside the
     edge nodes) is a steady state of the sweeps, to round-off."""
     c = _uniform_case(8, 16)
-    o = Oracle(c)
+    o = Oracle(c, L=L)
     rc, k, r = o.solve_potential(-1.0, 500)
     phi = o.field("phi")
     j = np.arange(16)
     np.testing.assert_allclose(phi, np.broadcast_to(((j + 0.5) / 16)[:, None], phi.shape), atol=2e-15)
+
+
+def test_linear_profile_is_an_exact_fixed_point():
+    check_linear_fixed_point()
 
 
 def test_layered_conductivity_matches_series_resistance():
