@@ -132,6 +132,17 @@ typedef struct lbm_diag {
     double t_fre;                 /* freezing step: V_l first <= 1% of V_l0, interpolated; -1 if not yet */
     double V_l0;                  /* V_l at initialisation */
     int nonfinite;                /* 1 if psi, u, p, T or phi holds NaN/Inf */
+    /* Operator residual of the potential equation div(sigma grad phi) = 0 (Sec. 2), written
+       with the isotropic stencils of Eq. (36) as grad(sigma).grad(phi) + sigma lap(phi) (the
+       discrete form the free charge of Eq. (14) takes for eps), sigma mixed by Eq. (1) from the
+       current psi and f_s: its L2 norm over the grid for the current phi (op_resid) and for the
+       linear electrode ramp with the same sigma (op_resid_ramp, where a solve starts; 0 for a
+       uniform sigma).  The LB sweeps converge to their own discretisation of the interface
+       conditions, so op_resid / op_resid_ramp levels off near a few percent on a W = 4
+       interface instead of reaching 0; it shows gross non-convergence, the relative change
+       (resid) the stopping rule. */
+    double op_resid, op_resid_ramp;
+    int init_converged;           /* 1 if lbm_init's potential solve met the stopping rule */
 } lbm_diag;
 
 typedef struct lbm_handle lbm_handle;
@@ -148,7 +159,11 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
    populations leaves a linear ramp unchanged).  `workspace` is a device pointer
    to at least lbm_workspace_bytes() bytes, 256-byte aligned; `stream` is a
    hipStream_t (NULL = the null stream).  Work is queued on the stream; the call
-   returns after the initial solve has converged (it reads the convergence flag). */
+   returns after the initial solve has ended (it reads the loop's outcome).  If that solve
+   reached poisson_max_sweeps before the stopping rule, lbm_init returns LBM_ENOCONV and
+   still sets *out to a valid handle (lbm_diag.init_converged = 0); the caller decides
+   whether to go on (lbm_solve_potential can continue the solve).  On any other error *out
+   is left unset. */
 int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream,
              lbm_handle** out);
 
@@ -185,6 +200,11 @@ int lbm_set_field(lbm_handle* h, int field, const double* src);
 int lbm_get_pop(lbm_handle* h, int set, double* dst);
 int lbm_set_pop(lbm_handle* h, int set, const double* src);
 
+/* One field as nx*ny FP64 values, row-major [j][i], into device memory `dst` (caller-owned,
+   at least nx*ny*8 bytes): the same raw values lbm_get_field returns (bases added in the FP32
+   forms), written by a kernel queued on the handle's stream; asynchronous, no host copy. */
+int lbm_get_field_device(lbm_handle* h, int field, double* dst);
+
 /* Sweep counts of every potential solve since lbm_init (index 0 = initial solve);
    copies min(count, cap) entries, *count gets the total. */
 int lbm_sweep_log(lbm_handle* h, int* dst, int cap, int* count);
@@ -213,11 +233,13 @@ int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
 
 /* Autotuner of the potential-sweep launch shape (sweeps per launch x waves per
    workgroup) for one grid size and precision; the shape changes no result, only speed.
-   Every candidate in {2, 4, 8} x {4, 8} is initialised on a temporary workspace that
-   the library allocates and frees (hipMalloc/hipFree), then `launches` launches of it are
-   timed twice on `stream` (the faster pass counts).  Results are cached per (nx, ny,
-   precision) for the life of the process; flags & LBM_TUNE_FORCE re-times.  Other
-   fields of *p only shape the timed state.  Synchronises the stream. */
+   Every candidate in {2, 4, 8} x {4, 8} is initialised in the caller's device workspace
+   (`workspace`, 256-byte aligned, at least lbm_autotune_workspace_bytes() bytes; its
+   contents are overwritten; the library allocates nothing), then `launches` launches of it
+   are timed twice on `stream` (the faster pass counts).  Results are cached per (nx, ny,
+   precision) for the life of the process; flags & LBM_TUNE_FORCE re-times (a cached answer
+   needs no workspace: pass NULL).  Other fields of *p only shape the timed state.
+   LBM_ESPACE if the workspace is smaller than needed.  Synchronises the stream. */
 #define LBM_TUNE_FORCE 1
 #define LBM_TUNE_MAXCAND 8
 typedef struct {
@@ -228,7 +250,9 @@ typedef struct {
     int cand_waves[LBM_TUNE_MAXCAND];
     float us_per_sweep[LBM_TUNE_MAXCAND];  /* measured time per sweep */
 } lbm_tune;
-int lbm_autotune(const lbm_params* p, void* stream, int launches, int flags, lbm_tune* out);
+int lbm_autotune_workspace_bytes(const lbm_params* p, size_t* bytes);
+int lbm_autotune(const lbm_params* p, void* workspace, size_t bytes, void* stream, int launches, int flags,
+                 lbm_tune* out);
 
 /* Release the handle (not the workspace, which the caller owns). */
 int lbm_destroy(lbm_handle* h);

@@ -46,6 +46,7 @@ struct lbm_handle {
     int last_sweeps = 0;
     double last_resid = 0.0;
     int noconv = 0;
+    int init_conv = 1;        // the initial potential solve met the stopping rule
     int kprev = 0;            // sweeps of the previous solve (first batch size)
     lbm_nn* wnn = nullptr;    // warm-start network used before every step's solve (or none)
     int wfactor = 0;
@@ -472,18 +473,21 @@ int init_state(lbm_handle* h) {
     lbm::k_init<R, H><<<h->nb, NT, 0, h->stream>>>(d, s);
     lbm::k_oml<R><<<h->nb, NT, 0, h->stream>>>(d, s, 0);
     LAUNCHCHK(h);
+    int solve_rc = LBM_OK;
     if (h->prm.skip_initial_solve) {
         // the caller seeds and solves the potential (warm start); the ramp stays for now
         h->log.push_back(0);
     } else {
         // first solve from equilibrium populations: the stopping test counts from sweep 2
-        int rc = run_sweeps<R>(h, h->prm.poisson_tol, 2, h->prm.poisson_max_sweeps, nullptr, nullptr);
-        if (rc && rc != LBM_ENOCONV) return rc;
+        solve_rc = run_sweeps<R>(h, h->prm.poisson_tol, 2, h->prm.poisson_max_sweeps, nullptr, nullptr);
+        if (solve_rc && solve_rc != LBM_ENOCONV) return solve_rc;
+        h->init_conv = solve_rc == LBM_OK;
     }
     lbm::k_vl0<R><<<h->nb, NT, 0, h->stream>>>(d, s);
     lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->partials, h->dctl, 1, 0);
     LAUNCHCHK(h);
-    return fetch_ctl(h);
+    int rc = fetch_ctl(h);
+    return rc ? rc : solve_rc;
 }
 
 template <typename R>
@@ -644,6 +648,30 @@ int copy_planes(lbm_handle* h, R* dev, double* host, int planes, bool to_host, O
     return block_to_dev<R>(h, dev, blk);
 }
 
+// One field into caller device memory as FP64, row-major without pitch, with the enthalpy
+// base added where the FP32 forms keep one (base == nullptr: none).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_field_out(Dev d, const R* __restrict__ src, const R* __restrict__ base,
+                                                  double* __restrict__ dst) {
+    const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (k >= (int64_t)d.nx * d.ny) return;
+    const int i = (int)(k % d.nx), j = (int)(k / d.nx);
+    const int64_t n = lbm::at(d, i, j);
+    dst[k] = (double)src[n] + (base ? (double)base[n] : 0.0);
+}
+
+template <typename R>
+int get_field_device(lbm_handle* h, int field, double* dst) {
+    Offset off;
+    R* p = field_ptr<R>(h, field, &off);
+    if (!p || !dst) return LBM_EINVAL;
+    const R* base = off == OFF_G ? h->st<R>().hb : nullptr;
+    const int64_t n = (int64_t)h->dev.nx * h->dev.ny;
+    k_field_out<R><<<(unsigned)((n + NT - 1) / NT), NT, 0, h->stream>>>(h->dev, p, base, dst);
+    LAUNCHCHK(h);
+    return LBM_OK;
+}
+
 template <typename R>
 int get_set_field(lbm_handle* h, int field, double* buf, bool get) {
     Offset off;
@@ -759,12 +787,12 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
     rc = h->prec == LBM_FP32_FP16STORE ? init_state<float, true>(h)
          : h->prec == LBM_FP32          ? init_state<float>(h)
                                         : init_state<double>(h);
-    if (rc) {
+    if (rc && rc != LBM_ENOCONV) {
         lbm_destroy(h);
         return rc;
     }
-    *out = h;
-    return LBM_OK;
+    *out = h;  // also after a capped initial solve: the state is valid
+    return rc;
 }
 
 int lbm_step(lbm_handle* h, int n) {
@@ -810,6 +838,9 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
     out->t_fre = c.t_fre;
     out->V_l0 = c.V_l0;
     out->nonfinite = c.nonfinite;
+    out->op_resid = c.op_res[0];
+    out->op_resid_ramp = c.op_res[1];
+    out->init_converged = h->init_conv;
     return c.nonfinite ? LBM_ENONFINITE : LBM_OK;
 }
 
@@ -817,6 +848,11 @@ int lbm_get_field(lbm_handle* h, int field, double* dst) {
     if (!h) return LBM_ESTATE;
     return h->prec != LBM_FP64 ? get_set_field<float>(h, field, dst, true)
                                : get_set_field<double>(h, field, dst, true);
+}
+
+int lbm_get_field_device(lbm_handle* h, int field, double* dst) {
+    if (!h) return LBM_ESTATE;
+    return h->prec != LBM_FP64 ? get_field_device<float>(h, field, dst) : get_field_device<double>(h, field, dst);
 }
 
 int lbm_set_field(lbm_handle* h, int field, const double* src) {
@@ -860,8 +896,38 @@ struct CkptHeader {
     int64_t step;
     double last_resid;
     uint64_t ws_bytes;
+    uint64_t params_digest;  // of every lbm_params value: an image restores only into its own case
+    int32_t init_conv, pad;
 };
 constexpr uint64_t CKPT_MAGIC = 0x4c424d434b505431ull;  // "LBMCKPT1"
+constexpr int32_t CKPT_VERSION = 2;
+
+// FNV-1a over the values of every lbm_params member (not its padding bytes).
+uint64_t params_digest(const lbm_params& p) {
+    uint64_t x = 0xcbf29ce484222325ull;
+    auto mix8 = [&](uint64_t v) {
+        for (int k = 0; k < 8; k++) {
+            x ^= (v >> (8 * k)) & 0xff;
+            x *= 0x100000001b3ull;
+        }
+    };
+    auto i = [&](long long v) { mix8((uint64_t)v); };
+    auto d = [&](double v) {
+        uint64_t b;
+        std::memcpy(&b, &v, sizeof b);
+        mix8(b);
+    };
+    i(p.nx); i(p.ny); i(p.precision);
+    d(p.W); d(p.M); d(p.gamma);
+    d(p.rho_l); d(p.rho_g); d(p.rho_s); d(p.mu_l); d(p.mu_g); d(p.mu_s);
+    d(p.cp_l); d(p.cp_g); d(p.cp_s); d(p.k_l); d(p.k_g); d(p.k_s); d(p.latent);
+    d(p.T_w); d(p.T_g); d(p.eps_l); d(p.eps_g); d(p.eps_s); d(p.sig_l); d(p.sig_g); d(p.sig_s);
+    d(p.phi_top); d(p.phi_bot); d(p.theta_deg);
+    i(p.shape); d(p.R0); d(p.xc); d(p.yc); d(p.h0);
+    d(p.poisson_tol); i(p.poisson_max_sweeps); i(p.readings);
+    i(p.sweep_block); i(p.sweep_waves);
+    return x;
+}
 
 size_t ckpt_bytes(const lbm_handle* h) {
     return sizeof(CkptHeader) + sizeof(int32_t) * h->log.size() + carve_bytes(&h->prm, h->dev);
@@ -887,7 +953,9 @@ int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
     if (*bytes < need) return LBM_ESPACE;
     CkptHeader hd{};
     hd.magic = CKPT_MAGIC;
-    hd.version = 1;
+    hd.version = CKPT_VERSION;
+    hd.params_digest = params_digest(h->prm);
+    hd.init_conv = h->init_conv;
     hd.nx = h->dev.nx;
     hd.ny = h->dev.ny;
     hd.precision = h->prec;
@@ -922,9 +990,13 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
     CkptHeader hd;
     std::memcpy(&hd, host, sizeof hd);
     size_t ws = carve_bytes(&h->prm, h->dev);
-    if (hd.magic != CKPT_MAGIC || hd.version != 1 || hd.nx != h->dev.nx || hd.ny != h->dev.ny ||
+    if (hd.magic != CKPT_MAGIC || hd.version != CKPT_VERSION || hd.nx != h->dev.nx || hd.ny != h->dev.ny ||
         hd.precision != h->prec || hd.sweep_block != h->swm || hd.sweep_waves != h->swv || hd.ws_bytes != ws ||
         hd.nlog < 0 || bytes < sizeof hd + sizeof(int32_t) * (size_t)hd.nlog + ws)
+        return LBM_EINVAL;
+    // buffer indices index the handle's plane tables: anything else is a corrupt image
+    if (hd.sp < 0 || hd.sp > 1 || hd.lcur < 0 || hd.lcur > 2 || hd.kprev < 0 || hd.noconv < 0 || hd.step < 0 ||
+        hd.params_digest != params_digest(h->prm))
         return LBM_EINVAL;
     const char* in = (const char*)host + sizeof hd;
     std::vector<int> log(hd.nlog);
@@ -943,6 +1015,7 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
     h->last_sweeps = hd.last_sweeps;
     h->step = hd.step;
     h->last_resid = hd.last_resid;
+    h->init_conv = hd.init_conv;
     h->resid_stale = false;
     h->vl_pending = false;
     h->log = std::move(log);
@@ -1015,9 +1088,9 @@ std::map<TuneKey, lbm_tune> tune_cache;
 constexpr int TUNE_M[] = {2, 4, 8};
 constexpr int TUNE_W[] = {4, 8};
 
-int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune* out) {
-    lbm_tune r{};
-    size_t need = 0;
+// Workspace that holds any candidate's state (the largest over the shapes tried).
+int tune_bytes(const lbm_params* p, size_t* need) {
+    *need = 0;
     for (int m : TUNE_M)
         for (int w : TUNE_W) {
             lbm_params q = *p;
@@ -1026,10 +1099,13 @@ int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune*
             size_t b = 0;
             int rc = lbm_workspace_bytes(&q, &b);
             if (rc) return rc;
-            need = std::max(need, b);
+            *need = std::max(*need, b);
         }
-    void* ws = nullptr;
-    if (hipMalloc(&ws, need) != hipSuccess) return LBM_EHIP;
+    return LBM_OK;
+}
+
+int tune_shapes(const lbm_params* p, void* ws, size_t need, hipStream_t stream, int launches, lbm_tune* out) {
+    lbm_tune r{};
     int rc = LBM_OK;
     float best = 0.f;
     for (int m : TUNE_M)
@@ -1039,6 +1115,7 @@ int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune*
             q.sweep_waves = w;
             q.poisson_tol = -1.0;  // a short fixed initial solve: the timing needs no convergence
             q.poisson_max_sweeps = 2 * m;
+            q.skip_initial_solve = 0;
             lbm_handle* h = nullptr;
             rc = lbm_init(&q, ws, need, stream, &h);
             if (rc) break;
@@ -1063,7 +1140,6 @@ int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune*
                 r.sweep_waves = w;
             }
         }
-    (void)hipFree(ws);
     if (rc) return rc;
     *out = r;
     return LBM_OK;
@@ -1073,7 +1149,15 @@ int tune_shapes(const lbm_params* p, hipStream_t stream, int launches, lbm_tune*
 
 extern "C" {
 
-int lbm_autotune(const lbm_params* p, void* stream, int launches, int flags, lbm_tune* out) {
+int lbm_autotune_workspace_bytes(const lbm_params* p, size_t* bytes) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!bytes) return LBM_EINVAL;
+    return tune_bytes(p, bytes);
+}
+
+int lbm_autotune(const lbm_params* p, void* workspace, size_t bytes, void* stream, int launches, int flags,
+                 lbm_tune* out) {
     int rc = validate(p);
     if (rc) return rc;
     if (!out || launches < 1) return LBM_EINVAL;
@@ -1087,8 +1171,13 @@ int lbm_autotune(const lbm_params* p, void* stream, int launches, int flags, lbm
             return LBM_OK;
         }
     }
+    size_t need = 0;
+    rc = tune_bytes(p, &need);
+    if (rc) return rc;
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return LBM_EINVAL;
+    if (bytes < need) return LBM_ESPACE;
     lbm_tune r{};
-    rc = tune_shapes(p, (hipStream_t)stream, launches, &r);
+    rc = tune_shapes(p, workspace, need, (hipStream_t)stream, launches, &r);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> g(tune_mu);
@@ -1128,6 +1217,7 @@ struct lbm_batch {
     std::vector<int> lcur, kprev;
     std::vector<std::vector<int>> log;
     std::vector<int> frozen_sp;          // buffer parity of a frozen case's final state (-1: running)
+    std::vector<int> init_conv;          // each case's initial solve met the stopping rule
     std::vector<long long> case_step;    // steps each case has taken
     int sp = 0;
     long long step = 0;
@@ -1382,6 +1472,8 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     BHIP(b, hipGetLastError());
     int rc = batch_sweeps<R>(b, 2);
     if (rc) return rc;
+    b->init_conv.assign(nc, 1);
+    for (int c = 0; c < nc; c++) b->init_conv[c] = b->ctl_h[c].conv;
     lbm::kb_vl0<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
     lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 1);
     BHIP(b, hipGetLastError());
@@ -1526,6 +1618,7 @@ int lbm_batch_diagnostics(lbm_batch* b, lbm_diag* per_case) {
         h.log = b->log[c];
         h.last_sweeps = b->log[c].empty() ? 0 : b->log[c].back();
         h.last_resid = b->ctl_h[c].resid;
+        h.init_conv = b->init_conv.empty() ? 1 : b->init_conv[c];
         int rc = lbm_diagnostics(&h, &per_case[c]);
         h.hctl = nullptr;  // owned by the batch
         if (rc == LBM_ENONFINITE) worst = rc;

@@ -77,6 +77,7 @@ struct Ctl {
     int final_buf;                   // potential buffer holding the last loop's final state
     double dsum[6];                  // sum psi, sum f, sum g, V_l, V_s, max |u|
     double front, height;
+    double op_res[2];                // ||div(sigma grad phi)|| of phi and of the linear ramp
     // FP16 population storage: per set (f, h, g) and buffer, the scale exponent the buffer was
     // last written with and the largest |deviation| (FP32 bits) ever written into it
     int hexp[3][2];
@@ -100,13 +101,14 @@ __device__ __forceinline__ void ctl_reset(Ctl* c, double tol, int min_sweeps, in
 constexpr int SW_MAXM = 8;  // most sweeps one blocked launch performs
 // FP32 potential base moves every REBASE_SWEEPS sweeps of a long solve (multiple of SW_MAXM)
 constexpr int REBASE_SWEEPS = 256;
+constexpr int DIAG_N = 9;  // per-tile diagnostics partials
 __host__ __device__ constexpr int64_t part_vl(int nb) { return 0; }
 __host__ __device__ constexpr int64_t part_diag(int nb) { return (int64_t)nb; }
 __host__ __device__ constexpr int64_t part_sweep(int nb, int nbt, int slot) {
-    return (int64_t)8 * nb + (int64_t)slot * SW_MAXM * 2 * nbt;
+    return (int64_t)(1 + DIAG_N) * nb + (int64_t)slot * SW_MAXM * 2 * nbt;
 }
 __host__ __device__ constexpr int64_t part_total(int nb, int nbt) {
-    return (int64_t)8 * nb + (int64_t)2 * SW_MAXM * 2 * nbt;
+    return (int64_t)(1 + DIAG_N) * nb + (int64_t)2 * SW_MAXM * 2 * nbt;
 }
 
 template <typename R>
@@ -162,6 +164,11 @@ __device__ __forceinline__ void grad_lap(const R v[3][3], R& gx, R& gy, R& lap) 
     R c = v[1][1];
     lap = R(6) * (wa * (v[1][2] + v[1][0] + v[2][1] + v[0][1] - R(4) * c) +
                   wd * (v[2][2] + v[2][0] + v[0][0] + v[0][2] - R(4) * c));
+}
+
+// The linear electrode ramp at row j (walls half a link outside the edge rows).
+__device__ __forceinline__ double phi_lin(const Dev& d, int j) {
+    return d.phi_bot + (d.phi_top - d.phi_bot) * (j + 0.5) / d.ny;
 }
 
 // XCD-aware block order: consecutive workgroup ids go to the 8 XCDs round-robin, so
@@ -1466,11 +1473,60 @@ __global__ void __launch_bounds__(NT) k_vl0(Dev d, State<R> s) {
 // Diagnostics: per-block FP64 sums, max |u| and a non-finite count; k_diag_finalize
 // adds them in block order and scans the centre column for the droplet height
 // (psi = 1/2) and the freezing front (f_l = 1/2).
+// A field value in FP64 with the ghost rule G applied in FP64 (x already wrapped).
+template <int G, typename R>
+__device__ __forceinline__ double ghosted_d(const R* __restrict__ f, const Dev& d, int i, int j) {
+    if (j < 0) {
+        const double b = (double)f[i];
+        if (G == GWET) return b + d.wet * b * (1.0 - b);
+        if (G == GPHI) return 2.0 * d.phi_bot - b;
+        return b;
+    }
+    if (j >= d.ny) {
+        const double t = (double)f[at(d, i, d.ny - 1)];
+        return G == GPHI ? 2.0 * d.phi_top - t : t;
+    }
+    return (double)f[at(d, i, j)];
+}
+
+// Operator residual of the potential equation at node (i, j): div(sigma grad phi) written with
+// Eq. (36) as grad(sigma).grad(phi) + sigma lap(phi) (the discrete form q_v takes for eps),
+// sigma mixed by Eq. (1) from psi (wetting ghost) and f_s (mirrored); *ramp: the same for the
+// linear electrode ramp (Dirichlet ghosts) with this sigma.  FP64 throughout.
+template <typename R>
+__device__ __forceinline__ double op_residual(const Dev& d, const R* psi, const R* fs, const R* phi, int i, int j,
+                                              double* ramp) {
+    const int im = wrapx(i - 1, d.nx), ip = wrapx(i + 1, d.nx);
+    const int cols[3] = {im, i, ip};
+    double vs[3][3], vp[3][3], vl[3][3];
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++) {
+        const int jj = j + dy;
+        const double lin = jj < 0 ? 2.0 * d.phi_bot - phi_lin(d, 0)
+                           : (jj >= d.ny ? 2.0 * d.phi_top - phi_lin(d, d.ny - 1) : phi_lin(d, jj));
+#pragma unroll
+        for (int dx = 0; dx < 3; dx++) {
+            const double ps = ghosted_d<GWET, R>(psi, d, cols[dx], jj);
+            const double f = ghosted_d<GMIRROR, R>(fs, d, cols[dx], jj);
+            vs[dy + 1][dx] = mix<double>(d.sig_s, d.sig_l, d.sig_g, ps, f);
+            vp[dy + 1][dx] = ghosted_d<GPHI, R>(phi, d, cols[dx], jj);
+            vl[dy + 1][dx] = lin;
+        }
+    }
+    double gsx, gsy, dum, gpx, gpy, lap, glx, gly, llap;
+    grad_lap<double>(vs, gsx, gsy, dum);
+    grad_lap<double>(vp, gpx, gpy, lap);
+    grad_lap<double>(vl, glx, gly, llap);
+    const double sg = vs[1][1];
+    *ramp = gsx * glx + gsy * gly + sg * llap;
+    return gsx * gpx + gsy * gpy + sg * lap;
+}
+
 template <typename R, bool H = false>
 __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
     int i, j;
     node_of(d, tile, i, j);
-    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    double v[DIAG_N] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < d.nx && j < d.ny) {
         int64_t n = at(d, i, j);
         double ps = s.psi[sp][n];
@@ -1497,15 +1553,19 @@ __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, 
         v[5] = sqrt(ux * ux + uy * uy);
         double chk = ps + ux + uy + (double)s.p[sp][n] + (double)s.T[sp][n] + (double)s.phi[lcur][n];
         v[6] = isfinite(chk) ? 0.0 : 1.0;
+        double rr;
+        const double ro = op_residual<R>(d, s.psi[sp], s.fs[sp], s.phi[lcur], i, j, &rr);
+        v[7] = ro * ro;
+        v[8] = rr * rr;
     }
     __shared__ double sh[NT / 64];
-    double r[7];
+    double r[DIAG_N];
     for (int k = 0; k < 5; k++) r[k] = block_sum(v[k], sh);
     r[5] = block_max(v[5], sh);
-    r[6] = block_sum(v[6], sh);
+    for (int k = 6; k < DIAG_N; k++) r[k] = block_sum(v[k], sh);
     if (threadIdx.x == 0) {
-        double* pw = s.partials + part_diag(d.gx * d.gy) + 7 * (int64_t)tile;
-        for (int k = 0; k < 7; k++) pw[k] = r[k];
+        double* pw = s.partials + part_diag(d.gx * d.gy) + DIAG_N * (int64_t)tile;
+        for (int k = 0; k < DIAG_N; k++) pw[k] = r[k];
     }
 }
 template <typename R, bool H = false>
@@ -1518,20 +1578,22 @@ __global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State<R> s, int sp)
     __shared__ double sh[NT / 64];
     int nb = d.gx * d.gy;
     const double* pv = s.partials + part_diag(nb);
-    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    double a[DIAG_N] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < nb; k += NT) {
-        for (int m = 0; m < 5; m++) a[m] += pv[7 * k + m];
-        a[5] = fmax(a[5], pv[7 * k + 5]);
-        a[6] += pv[7 * k + 6];
+        for (int m = 0; m < 5; m++) a[m] += pv[DIAG_N * k + m];
+        a[5] = fmax(a[5], pv[DIAG_N * k + 5]);
+        for (int m = 6; m < DIAG_N; m++) a[m] += pv[DIAG_N * k + m];
     }
-    double out[7];
+    double out[DIAG_N];
     for (int m = 0; m < 5; m++) out[m] = block_sum(a[m], sh);
     out[5] = block_max(a[5], sh);
-    out[6] = block_sum(a[6], sh);
+    for (int m = 6; m < DIAG_N; m++) out[m] = block_sum(a[m], sh);
     if (threadIdx.x != 0) return;
     Ctl* c = s.ctl;
     for (int m = 0; m < 6; m++) c->dsum[m] = out[m];
     c->nonfinite = out[6] > 0.0;
+    c->op_res[0] = sqrt(out[7]);
+    c->op_res[1] = sqrt(out[8]);
     const R* psi = s.psi[sp];
     int ic = d.nx / 2;
     double height = 0.0;
@@ -1770,10 +1832,6 @@ __global__ void __launch_bounds__(NT) k_nn_features(Dev d, State<R> s, int psp, 
     x[3 * (int64_t)c + 2] = (float)(a2 * inv);
 }
 
-__device__ __forceinline__ double phi_ramp(const Dev& d, int j) {
-    return d.phi_bot + (d.phi_top - d.phi_bot) * (j + 0.5) / d.ny;
-}
-
 // Target: the cell average of (phi - ramp) / (phi_top - phi_bot).
 template <typename R>
 __global__ void __launch_bounds__(NT) k_nn_target(Dev d, State<R> s, int lcur, int f, float* __restrict__ t) {
@@ -1783,7 +1841,7 @@ __global__ void __launch_bounds__(NT) k_nn_target(Dev d, State<R> s, int lcur, i
     const int I = c % nxc, J = c / nxc;
     double a = 0.0;
     for (int j = J * f; j < (J + 1) * f; j++)
-        for (int i = I * f; i < (I + 1) * f; i++) a += (double)s.phi[lcur][at(d, i, j)] - phi_ramp(d, j);
+        for (int i = I * f; i < (I + 1) * f; i++) a += (double)s.phi[lcur][at(d, i, j)] - phi_lin(d, j);
     t[c] = (float)(a / ((double)f * f) / (d.phi_top - d.phi_bot));
 }
 
@@ -1805,7 +1863,7 @@ __device__ __forceinline__ void b_nn_seed(const Dev& d, const State<R>& s, int l
     const int jb = j0 + 1 > nyc - 1 ? nyc - 1 : (j0 + 1 < 0 ? 0 : j0 + 1);
     const double v = (1.0 - fy) * ((1.0 - fx) * yc[ja * nxc + ia] + fx * yc[ja * nxc + ib]) +
                      fy * ((1.0 - fx) * yc[jb * nxc + ia] + fx * yc[jb * nxc + ib]);
-    const double phi = phi_ramp(d, j) + (d.phi_top - d.phi_bot) * v;
+    const double phi = phi_lin(d, j) + (d.phi_top - d.phi_bot) * v;
     const double leq = LWA * phi;
     const int64_t n = at(d, i, j);
     constexpr bool based = std::is_same<R, float>::value;

@@ -30,7 +30,8 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_nn_get_params", "lbm_nn_forward", "lbm_nn_gradient", "lbm_nn_train_step",
            "lbm_nn_destroy", "lbm_nn_last_error", "lbm_nn_features", "lbm_nn_target", "lbm_nn_seed",
            "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample", "lbm_checkpoint", "lbm_restore",
-           "lbm_run_until_frozen", "lbm_batch_run_until_frozen"]
+           "lbm_run_until_frozen", "lbm_batch_run_until_frozen", "lbm_autotune_workspace_bytes",
+           "lbm_get_field_device"]
 
 LBM_TUNE_FORCE = 1
 
@@ -70,6 +71,7 @@ class LbmDiag(C.Structure):
         ("front_y", C.c_double), ("height", C.c_double), ("max_u", C.c_double),
         ("resid", C.c_double), ("sweeps", C.c_int), ("noconv", C.c_int),
         ("t_fre", C.c_double), ("V_l0", C.c_double), ("nonfinite", C.c_int),
+        ("op_resid", C.c_double), ("op_resid_ramp", C.c_double), ("init_converged", C.c_int),
     ]
 
 
@@ -124,7 +126,9 @@ def lib():
         L.lbm_batch_get_field.argtypes = [vp, C.c_int, C.c_int, dp]
         L.lbm_batch_sweep_log.argtypes = [vp, C.c_int, ip, C.c_int, ip]
         L.lbm_batch_destroy.argtypes = [vp]
-        L.lbm_autotune.argtypes = [C.POINTER(LbmParams), vp, C.c_int, C.c_int, C.POINTER(LbmTune)]
+        L.lbm_autotune_workspace_bytes.argtypes = [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]
+        L.lbm_autotune.argtypes = [C.POINTER(LbmParams), vp, C.c_size_t, vp, C.c_int, C.c_int, C.POINTER(LbmTune)]
+        L.lbm_get_field_device.argtypes = [vp, C.c_int, vp]
         fp = C.POINTER(C.c_float)
         L.lbm_nn_param_count.argtypes = [ip]
         L.lbm_nn_workspace_bytes.argtypes = [C.c_longlong, C.POINTER(C.c_size_t)]
@@ -205,10 +209,16 @@ def autotune(case: dict, precision: str = "fp64", launches: int = 20, force: boo
         return dict(table[key], cached="file")
     p = make_params(case, precision)
     out = LbmTune()
+    need = C.c_size_t()
+    rc = lib().lbm_autotune_workspace_bytes(C.byref(p), C.byref(need))
+    if rc != LBM_OK:
+        raise LbmError("lbm_autotune_workspace_bytes", rc)
     with torch.cuda.device(torch.device(device)):
         stream = torch.cuda.current_stream()
-        rc = lib().lbm_autotune(C.byref(p), C.c_void_p(stream.cuda_stream), int(launches),
-                                LBM_TUNE_FORCE if force else 0, C.byref(out))
+        ws = torch.empty(need.value, dtype=torch.uint8, device=device)  # the caller's workspace
+        rc = lib().lbm_autotune(C.byref(p), C.c_void_p(ws.data_ptr()), need, C.c_void_p(stream.cuda_stream),
+                                int(launches), LBM_TUNE_FORCE if force else 0, C.byref(out))
+        del ws
     if rc != LBM_OK:
         raise LbmError("lbm_autotune", rc)
     res = {"sweep_block": out.sweep_block, "sweep_waves": out.sweep_waves,
@@ -228,11 +238,14 @@ class Solver:
     """One case on one GPU.  The workspace is a torch uint8 tensor; the stream is torch's
     current stream on `device` at construction."""
 
-    def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0", workspace=None):
+    def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0", workspace=None,
+                 require_converged: bool = False):
         """`precision`: "fp64", "fp32" or "fp16store" (FP32 arithmetic with the f, h and g
         populations stored in binary16).  `workspace`: optional caller-owned uint8 device
         tensor of at least `workspace_bytes(case, precision)` bytes (its contents do not
-        matter); by default one is allocated."""
+        matter); by default one is allocated.  An initial potential solve that reaches the
+        sweep cap leaves `init_converged` False (lbm_init's LBM_ENOCONV); with
+        `require_converged` it raises instead."""
         import torch
 
         if not torch.cuda.is_available():
@@ -253,9 +266,13 @@ class Solver:
         h = C.c_void_p()
         rc = lib().lbm_init(C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
                             C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream), C.byref(h))
-        if rc != LBM_OK:
+        if rc not in (LBM_OK, LBM_ENOCONV):
             raise LbmError("lbm_init", rc)
         self._h = h
+        self.init_converged = rc == LBM_OK
+        if require_converged and not self.init_converged:
+            raise LbmError("lbm_init", rc, f"initial potential solve stopped at the cap "
+                                           f"({self.params.poisson_max_sweeps} sweeps)")
 
     def _check(self, what, rc, ok=(LBM_OK,)):
         if rc not in ok:
@@ -286,6 +303,17 @@ class Solver:
     def field(self, name: str) -> np.ndarray:
         out = np.empty((self.ny, self.nx), dtype=np.float64)
         self._check("lbm_get_field", lib().lbm_get_field(self._h, FIELDS.index(name), _dp(out)))
+        return out
+
+    def field_device(self, name: str, out=None):
+        """One field as a torch FP64 (ny, nx) device tensor, written by the library's kernel
+        on the solver's stream (no host copy)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.nx * self.ny
+        self._check("lbm_get_field_device", lib().lbm_get_field_device(self._h, FIELDS.index(name),
+                                                                       C.c_void_p(out.data_ptr())))
         return out
 
     def set_field(self, name: str, arr):
