@@ -326,6 +326,17 @@ int lbm_nn_get_params(lbm_nn* nn, float* host);
 int lbm_nn_forward(lbm_nn* nn, const float* x, float* y, int n, int h, int w);
 /* Gradient of L = sum over pixels of (y - t)^2 with respect to every parameter (host FP32,
    parameter order; padding entries 0) and L (host).  x, t on the device.  Synchronises. */
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+   harnesses that forbid hipMalloc): lbm_nn_forward with the packed input and the hidden
+   activations in a fixed scratch array of the library (2.25 MiB per device, held until the
+   process ends) instead of the network's workspace.  n h w <= LBM_NN_NOALLOC_MAX_PIXELS
+   (LBM_EINVAL beyond), independent of the network's pixel capacity; the same kernels and the
+   same arithmetic, so y equals lbm_nn_forward's bitwise.  The device current on the calling
+   thread must be the network's.  Allocates nothing.  Every call on a device shares that
+   device's scratch and the last call's contents stay there: calls that overlap on one device
+   (several streams or threads) race.  Asynchronous on the network's stream. */
+#define LBM_NN_NOALLOC_MAX_PIXELS 16384
+int lbm_nn_forward_noalloc(lbm_nn* nn, const float* x, float* y, int n, int h, int w);
 int lbm_nn_gradient(lbm_nn* nn, const float* x, const float* t, int n, int h, int w, float* grad, double* loss);
 /* One Adam step of learning rate lr on L; *loss (optional, synchronises) gets L before the step. */
 int lbm_nn_train_step(lbm_nn* nn, const float* x, const float* t, int n, int h, int w, float lr, double* loss);

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -90,29 +91,67 @@ bool shape_ok(const lbm_nn* nn, int n, int h, int w) {
     return n >= 1 && h >= 1 && w >= 1 && (int64_t)n * h * w <= nn->cap;
 }
 
-// Forward pass; activations stay in the workspace for a following backward pass.
-int run_forward(lbm_nn* nn, const float* x, float* y, int n, int h, int w, hipStream_t st) {
+// Forward pass into the packed-input buffer xh and the hidden buffers act[0..NL-2] (layer l
+// reads act[l-1] and writes act[l]: consecutive entries must differ).  The handle's own
+// buffers keep the activations for a following backward pass.
+int run_forward_into(lbm_nn* nn, const float* x, float* y, int n, int h, int w, hipStream_t st, half* xh,
+                     half* const* act) {
     const int npix = n * h * w;
-    nn::k_pack_input<<<(npix + 255) / 256, 256, 0, st>>>(x, nn->xh, npix);
+    nn::k_pack_input<<<(npix + 255) / 256, 256, 0, st>>>(x, xh, npix);
     const int segs = (w + 31) / 32;
     const int64_t waves = (int64_t)n * h * segs;
     const int blocks = (int)((waves + 3) / 4);
-    const half* in = nn->xh;
+    const half* in = xh;
     for (int l = 0; l < nn::NL; l++) {
         const half* wl = nn->wh + nn::woff(l);
         const float* bl = nn->p + nn::WTOTAL + l * nn::CH;
         if (l == 0)
-            nn::k_conv<nn::CIN0, nn::EPI_TANH><<<blocks, nn::WGT, 0, st>>>(in, wl, bl, nullptr, nn->act[0], nullptr, n, h,
+            nn::k_conv<nn::CIN0, nn::EPI_TANH><<<blocks, nn::WGT, 0, st>>>(in, wl, bl, nullptr, act[0], nullptr, n, h,
                                                                             w, nn::dil(l), 1.f);
         else if (l < nn::NL - 1)
-            nn::k_conv<nn::CH, nn::EPI_TANH><<<blocks, nn::WGT, 0, st>>>(in, wl, bl, nullptr, nn->act[l], nullptr, n, h,
+            nn::k_conv<nn::CH, nn::EPI_TANH><<<blocks, nn::WGT, 0, st>>>(in, wl, bl, nullptr, act[l], nullptr, n, h,
                                                                           w, nn::dil(l), 1.f);
         else
             nn::k_conv<nn::CH, nn::EPI_LINEAR><<<blocks, nn::WGT, 0, st>>>(in, wl, bl, nullptr, nullptr, y, n, h, w,
                                                                             nn::dil(l), 1.f);
-        if (l < nn::NL - 1) in = nn->act[l];
+        if (l < nn::NL - 1) in = act[l];
     }
     NNCHK(nn, hipGetLastError());
+    return LBM_OK;
+}
+
+int run_forward(lbm_nn* nn, const float* x, float* y, int n, int h, int w, hipStream_t st) {
+    return run_forward_into(nn, x, y, n, h, w, st, nn->xh, nn->act);
+}
+
+// Scratch of the allocation-free forward pass (lbm_nn_forward_noalloc): the packed input
+// (CIN0 channels) and two hidden buffers used in turn (CH channels each), FP16, for up to
+// LBM_NN_NOALLOC_MAX_PIXELS pixels: 2.25 MiB per device, held until the process ends.  In
+// host code this name stands for the array, not its device address: kernels get the address
+// from noalloc_scratch().
+constexpr int64_t NOALLOC_HALVES = (int64_t)LBM_NN_NOALLOC_MAX_PIXELS * (nn::CIN0 + 2 * nn::CH);
+static __device__ __align__(256) half scratch[NOALLOC_HALVES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+half* scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up on the first call on
+// that device.
+int noalloc_scratch(lbm_nn* nn, half** out) {
+    int dev = 0;
+    NNCHK(nn, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        nn->err = "device index beyond the scratch table";
+        return LBM_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        NNCHK(nn, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        scratch_ptr[dev] = (half*)p;
+    }
+    *out = scratch_ptr[dev];
     return LBM_OK;
 }
 
@@ -270,6 +309,20 @@ int lbm_nn_forward(lbm_nn* nnh, const float* x, float* y, int n, int h, int w) {
     if (!nnh) return LBM_ESTATE;
     if (!x || !y) return LBM_EINVAL;
     return nnapi::forward(nnh, x, y, n, h, w, nnh->stream);
+}
+
+int lbm_nn_forward_noalloc(lbm_nn* nnh, const float* x, float* y, int n, int h, int w) {
+    if (!nnh) return LBM_ESTATE;
+    if (!x || !y || n < 1 || h < 1 || w < 1 || (int64_t)n * h * w > LBM_NN_NOALLOC_MAX_PIXELS) return LBM_EINVAL;
+    half* base = nullptr;
+    int rc = noalloc_scratch(nnh, &base);
+    if (rc) return rc;
+    half* xh = base;
+    half* a0 = xh + (int64_t)LBM_NN_NOALLOC_MAX_PIXELS * nn::CIN0;
+    half* a1 = a0 + (int64_t)LBM_NN_NOALLOC_MAX_PIXELS * nn::CH;
+    half* act[nn::NL - 1];
+    for (int l = 0; l < nn::NL - 1; l++) act[l] = (l & 1) ? a1 : a0;
+    return run_forward_into(nnh, x, y, n, h, w, nnh->stream, xh, act);
 }
 
 int lbm_nn_gradient(lbm_nn* nnh, const float* x, const float* t, int n, int h, int w, float* grad, double* loss) {
