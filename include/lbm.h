@@ -53,10 +53,13 @@ extern "C" {
 #define LBM_ESPACE (-6)     /* workspace smaller than lbm_workspace_bytes() */
 
 /* Arithmetic and storage (lbm_params.precision).  FP64: every population and field in
-   double.  FP32: populations, fields and arithmetic in float, with the enthalpy rest
-   link and H stored relative to the liquid's latent heat rho_s L and the D2Q5 links and
-   phi stored relative to the linear electrode ramp (their increments are below an FP32
-   ulp of the raw values); FP64 is kept for the potential residual, the liquid and solid
+   double.  FP32: populations, fields and the populations' arithmetic in float: the
+   phase-field populations are stored as deviations from w_i psi of their node and collided,
+   streamed and summed in that deviation form; the enthalpy rest link and H are stored
+   relative to the node's latent heat psi rho_s L; the D2Q5 links are FP32 base/remainder
+   pairs (their increments are below an FP32 ulp of the raw values).  The coupling terms
+   (gradients, Laplacians, normals, chemical potential, forces, sources) are evaluated in FP64
+   from the stored fields in every form, as are the potential residual, the liquid and solid
    volume sums, the freezing-time detector and the front search.  FP32_FP16STORE: the
    FP32 form with the f, h and g populations stored in binary16 as deviations from the
    zero-velocity equilibria of their nodes' stored moments (Eqs. (18), (22), (29)), each set
@@ -66,9 +69,9 @@ extern "C" {
    lbm_get_pop decodes the binary16 sets on the host, lbm_set_pop returns LBM_EINVAL for f, h
    and g (a write would have to be encoded against the running scales).  Because its populations are stored
    relative to the node's stored psi, p, H and T, lbm_set_field of one of those fields also
-   moves that node's f, h or g populations by the change of their zero-velocity equilibria
-   (in FP64 and FP32 the populations stay as they are).  The ABI always exchanges raw FP64
-   values. */
+   moves that node's f, h or g populations by the change of their zero-velocity equilibria;
+   in the FP32 form the same holds for psi and f (in FP64 the populations stay as they are).
+   The ABI always exchanges raw FP64 values. */
 #define LBM_FP64 0
 #define LBM_FP32 1
 #define LBM_FP32_FP16STORE 2

@@ -43,7 +43,9 @@
  *    (4/W) cos(theta) psi(i,0)(1 - psi(i,0)); mirror at the top;
  *  - ghost rows of p and S mirror; of rho, eps, sigma are mixed from the
  *    ghost psi and mirrored f_s; of phi are 2 phi_wall - phi(edge);
- *  - psi is clamped to [0, 1] inside Eq. (1) only; F_b = 0.
+ *  - psi is clamped to [0, 1] inside Eq. (1) and in lambda = 4 psi (1 - psi) / W of the
+ *    Allen-Cahn counter term (beyond [0, 1] the printed factor changes sign, and the term
+ *    would sharpen an overshoot instead of relaxing it); F_b = 0.
  */
 #include "lbm_oracle.h"
 
@@ -544,7 +546,10 @@ static void step_once(orc_state* s) {
                 nyv = gy / mag;
             }
             double ps = psi[n];
-            double lam = 4 * ps * (1 - ps) / p->W;
+            /* psi clamped to [0, 1] in lambda as in Eq. (1): outside it the printed factor
+               changes sign and the counter term would steepen instead of relax */
+            double pcl = clamp01(ps);
+            double lam = 4 * pcl * (1 - pcl) / p->W;
             double Ax = (ps * ux[n] - pux[n]) + CS2 * lam * nxv;
             double Ay = (ps * uy[n] - puy[n]) + CS2 * lam * nyv;
             double feq[9], F[9];

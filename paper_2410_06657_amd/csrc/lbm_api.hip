@@ -552,7 +552,9 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
 
 // Device plane(s) of a field or population set in the current state, with the offset
 // kind that converts stored values to the raw FP64 values of the ABI.
-enum Offset { OFF_NONE, OFF_G, OFF_BASE };  // enthalpy base; potential link bases
+// enthalpy base; potential link bases; FP32 phase-field populations held as deviations from
+// w_i psi of their node
+enum Offset { OFF_NONE, OFF_G, OFF_BASE, OFF_F };
 
 template <typename R>
 R* field_ptr(lbm_handle* h, int field, Offset* off) {
@@ -583,7 +585,7 @@ R* pop_ptr(lbm_handle* h, int set, int* nq, Offset* off) {
     State<R>& s = h->st<R>();
     *off = OFF_NONE;
     switch (set) {
-        case LBM_POP_F: *nq = 9; return s.f[h->sp];
+        case LBM_POP_F: *nq = 9; *off = h->prec != LBM_FP64 ? OFF_F : OFF_NONE; return s.f[h->sp];
         case LBM_POP_H: *nq = 9; return s.h[h->sp];
         case LBM_POP_G: *nq = 9; *off = h->prec != LBM_FP64 ? OFF_G : OFF_NONE; return s.g[h->sp];
         case LBM_POP_L: *nq = 4; *off = h->prec != LBM_FP64 ? OFF_BASE : OFF_NONE; return s.l[h->lcur];
@@ -618,8 +620,8 @@ int copy_planes(lbm_handle* h, R* dev, double* host, int planes, bool to_host, O
     // OFF_BASE: one base plane per potential link
     std::vector<R> base;
     const size_t bplanes = off == OFF_BASE ? (size_t)planes : 1;
-    R* bp = off == OFF_BASE ? h->st<R>().lb : h->st<R>().hb;
-    if (off == OFF_G || (off == OFF_BASE && to_host)) {
+    R* bp = off == OFF_BASE ? h->st<R>().lb : (off == OFF_F ? h->st<R>().psi[h->sp] : h->st<R>().hb);
+    if (off == OFF_G || off == OFF_F || (off == OFF_BASE && to_host)) {
         int rc = block_to_host<R>(h, base, bp, ny * pitch * bplanes);
         if (rc) return rc;
     }
@@ -628,6 +630,11 @@ int copy_planes(lbm_handle* h, R* dev, double* host, int planes, bool to_host, O
     auto offset = [&](size_t k) -> double {
         if (off == OFF_G) return (planes == 1 || k < per) ? (double)base[pidx(k % per)] : 0.0;
         if (off == OFF_BASE) return (double)base[pidx(k)];
+        if (off == OFF_F) {  // w_i psi as the kernels form it
+            const int q = (int)(k / per);
+            const double w = q == 0 ? lbm::W0 : (q < 5 ? lbm::WA : lbm::WD);
+            return (double)((R)w * base[pidx(k % per)]);
+        }
         return 0.0;
     };
     std::vector<R> blk;

@@ -155,15 +155,21 @@ __device__ __forceinline__ void load3(const R* __restrict__ f, const Dev& d, int
     }
 }
 
-// Eq. (36a) and (36b) on a 3x3 neighbourhood.
+// Eq. (36a) and (36b) on a 3x3 neighbourhood.  Differences from the centre are formed first:
+// neighbouring values of a smooth field are close, so each difference is (nearly) exact and
+// the rounding of the sums is relative to the differences, not to the field (an O(1) field
+// such as psi or phi would otherwise carry an absolute rounding error of several ulps of 1
+// into its Laplacian; in FP32 that is a relative error of 1e-5 to 1e-4 in the chemical
+// potential and the free charge).
 template <typename R>
 __device__ __forceinline__ void grad_lap(const R v[3][3], R& gx, R& gy, R& lap) {
     const R wa = R(WA), wd = R(WD);
-    gx = R(3) * (wa * (v[1][2] - v[1][0]) + wd * (v[2][2] - v[2][0] - v[0][0] + v[0][2]));
-    gy = R(3) * (wa * (v[2][1] - v[0][1]) + wd * (v[2][2] + v[2][0] - v[0][0] - v[0][2]));
-    R c = v[1][1];
-    lap = R(6) * (wa * (v[1][2] + v[1][0] + v[2][1] + v[0][1] - R(4) * c) +
-                  wd * (v[2][2] + v[2][0] + v[0][0] + v[0][2] - R(4) * c));
+    const R c = v[1][1];
+    const R e = v[1][2] - c, w = v[1][0] - c, n = v[2][1] - c, s = v[0][1] - c;
+    const R ne = v[2][2] - c, nw = v[2][0] - c, sw = v[0][0] - c, se = v[0][2] - c;
+    gx = R(3) * (wa * (e - w) + wd * ((ne - nw) + (se - sw)));
+    gy = R(3) * (wa * (n - s) + wd * ((ne - se) + (nw - sw)));
+    lap = R(6) * (wa * ((e + w) + (n + s)) + wd * ((ne + nw) + (sw + se)));
 }
 
 // The linear electrode ramp at row j (walls half a link outside the edge rows).
@@ -296,6 +302,18 @@ __device__ __forceinline__ R coll_f(int q, R fq, R psi, R ux, R uy, R Ax, R Ay, 
     R feq = R(QW[q]) * psi * (R(1) + R(3) * cu);
     R F = R(QW[q]) * (R(3) * (R(QX[q]) * Ax + R(QY[q]) * Ay) + psi * md);
     return fq - R(d.omf) * (fq - feq) + R(d.facf) * F;
+}
+
+// The same collision in deviation form (the FP32 forms, which store f_i - w_i psi): with
+// f = w psi + dev at the source node, f - f_eq = dev - 3 w psi c.u, so the post-collision
+// deviation from w psi is dev - omega (dev - 3 w psi c.u) + (1 - 1/(2 tau_f)) F: every rounding
+// is relative to deviations, not to the O(w) populations.
+template <typename R>
+__device__ __forceinline__ R coll_f_dev(int q, R dq, R psi, R ux, R uy, R Ax, R Ay, R md, const Dev& d) {
+    R cu = R(QX[q]) * ux + R(QY[q]) * uy;
+    R neq = dq - R(QW[q]) * psi * (R(3) * cu);
+    R F = R(QW[q]) * (R(3) * (R(QX[q]) * Ax + R(QY[q]) * Ay) + psi * md);
+    return dq - R(d.omf) * neq + R(d.facf) * F;
 }
 
 template <typename R>
@@ -512,7 +530,8 @@ __device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile
             h16_put((half_t*)s.h[0], q * d.plane + n, hq - h_rest<R>(q, R(0)), sc);
             h16_put((half_t*)s.g[0], q * d.plane + n, gq - g_rest<R>(q, Hn, T, R(d.Cref)), sc);
         } else {
-            s.f[0][q * d.plane + n] = fq;
+            // FP32: f stored as its deviation from w_i psi (0 here)
+            s.f[0][q * d.plane + n] = based ? fq - f_rest<R>(q, psi) : fq;
             s.h[0][q * d.plane + n] = hq;
             s.g[0][q * d.plane + n] = gq;
         }
@@ -565,30 +584,57 @@ __device__ __forceinline__ void vl_finalize_body(const Dev& d, const double* par
 // then remember psi^n u^n for the next step.
 // A at a node from psi^n around it (v), u^n and (psi u)^{n-1} there.  (psi u)^n itself is
 // stored for the next step by the g stage (k_g_stream), after every reader of the old value.
+// The coupling terms (gradients and Laplacians of Eq. (36), normals, the chemical potential,
+// the forces and sources) are evaluated in FP64 from the stored fields in every form: on the
+// gfx950 VALU an FP64 fused multiply-add issues at the rate of an unpacked FP32 one, so this
+// costs the FP32 forms only conversions, while FP32 differences of O(1) fields at neighbouring
+// nodes would inject errors far above one rounding of the stored values.  The FP32 forms keep
+// FP32 arithmetic for the populations' collision, streaming and moments.
+using K = double;
+template <typename R>
+__device__ __forceinline__ void to_k(const R (&v)[3][3], K (&w)[3][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) w[a][b] = (K)v[a][b];
+}
+
 template <typename R>
 __device__ __forceinline__ void a_term(const Dev& d, const R (&v)[3][3], R ux, R uy, R pux, R puy, R& Ax, R& Ay) {
-    R gx, gy, lap;
-    grad_lap<R>(v, gx, gy, lap);
-    R mag = sqrt(gx * gx + gy * gy);
-    R nx = R(0), ny = R(0);
-    if (mag > R(1e-12)) {
+    K w[3][3];
+    to_k(v, w);
+    K gx, gy, lap;
+    grad_lap<K>(w, gx, gy, lap);
+    K mag = sqrt(gx * gx + gy * gy);
+    K nx = 0.0, ny = 0.0;
+    if (mag > 1e-12) {
         nx = gx / mag;
         ny = gy / mag;
     }
-    R ps = v[1][1];
-    R lam = R(4) * ps * (R(1) - ps) / R(d.W);
-    R px = ps * ux, py = ps * uy;
-    Ax = (px - pux) + R(CS2) * lam * nx;
-    Ay = (py - puy) + R(CS2) * lam * ny;
+    K ps = w[1][1];
+    // psi clamped to [0, 1] in lambda as in Eq. (1): beyond [0, 1] the printed factor turns
+    // negative and the counter term would steepen an overshoot (an instability) instead of
+    // relaxing it
+    const K pcl = clamp01(ps);
+    K lam = 4.0 * pcl * (1.0 - pcl) / d.W;
+    K px = ps * (K)ux, py = ps * (K)uy;
+    Ax = R((px - (K)pux) + CS2 * lam * nx);
+    Ay = R((py - (K)puy) + CS2 * lam * ny);
 }
 
 // Stage 1b: f pulled and collided at its source, half-way bounce-back at the
 // walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.  The collision
 // inputs of the tile and its ring are staged in LDS first (`ring`).
-// H: FP16 storage; returns the largest |deviation| the thread wrote (0 otherwise).
+// FP64 keeps the populations raw.  The FP32 forms (R = float; H: binary16 storage) keep each
+// population as its deviation from w_i psi of its node and collide in deviation form: a link
+// pulled from node y arrives as w_i psi(y) + e_i with e_i the collided deviation, psi^{n+1} is
+// (sum_i w_i psi(y_i) + sum_i e_i) / (1 - mdot/2), and the stored deviation is
+// w_i (psi(y_i) - psi^{n+1}) + e_i, a difference of neighbouring psi plus a small term.
+// H: returns the largest |deviation| the thread wrote (0 otherwise).
 template <typename R, bool H = false>
 __device__ __forceinline__ float f_collide_stream(const Dev& d, const State<R>& s, int sp, int tile,
                                                   const FIn<R>* ring, H16Scales hs = {}) {
+    constexpr bool DEV = std::is_same<R, float>::value;
     const R* md = s.md[sp];
     int i, j;
     node_of(d, tile, i, j);
@@ -596,42 +642,48 @@ __device__ __forceinline__ float f_collide_stream(const Dev& d, const State<R>& 
     int64_t n = at(d, i, j);
     const R* fsrc = s.f[sp];
     R* fdst = s.f[sp ^ 1];
-    auto src = [&](int q, int64_t m, R base) -> R {
-        if constexpr (H) return h16_get((const half_t*)fsrc, q * d.plane + m, base, hs.inv);
+    auto src = [&](int q, int64_t m) -> R {  // the stored value (raw, or the deviation)
+        if constexpr (H) return h16_get((const half_t*)fsrc, q * d.plane + m, 0.f, hs.inv);
         else return fsrc[q * d.plane + m];
     };
     const int me = ring_self();
-    R sum = R(0);
-    R vals[H ? 9 : 1];
+    R sum = R(0), esum = R(0);
+    R ev[DEV ? 9 : 1], pv[DEV ? 9 : 1];
 #pragma unroll
     for (int q = 0; q < 9; q++) {
         int jj = j - QY[q];
-        R val;
-        if (jj < 0 || jj >= d.ny) {
-            int o = QOPP[q];
-            const FIn<R>& a = ring[me];
-            val = coll_f<R>(o, src(o, n, f_rest<R>(o, a.psi)), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+        const bool wall = jj < 0 || jj >= d.ny;
+        const int o = wall ? QOPP[q] : q;  // bounce-back: the node's own opposite link
+        const FIn<R>& a = wall ? ring[me] : ring[ring_from(me, QX[q], QY[q])];
+        const int64_t m = wall ? n : at(d, wrapx(i - QX[q], d.nx), jj);
+        if constexpr (DEV) {
+            const R e = coll_f_dev<R>(o, src(o, m), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            ev[q] = e;
+            pv[q] = a.psi;
+            sum += f_rest<R>(q, a.psi);
+            esum += e;
         } else {
-            int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            const FIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
-            val = coll_f<R>(q, src(q, m, f_rest<R>(q, a.psi)), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            const R val = coll_f<R>(o, src(o, m), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            fdst[q * d.plane + n] = val;
+            sum += val;
         }
-        if constexpr (H) vals[q] = val;
-        else fdst[q * d.plane + n] = val;
-        sum += val;
     }
-    R pn = sum / (R(1) - R(0.5) * md[n]);
+    R pn = (sum + esum) / (R(1) - R(0.5) * md[n]);
     s.psi[sp ^ 1][n] = pn;
     R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, pn, s.fs[sp][n]);
     s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
     float mx = 0.f;
-    if constexpr (H) {
+    if constexpr (DEV) {
         // deviations from the equilibrium of the psi stored beside them
 #pragma unroll
         for (int q = 0; q < 9; q++) {
-            const float dv = vals[q] - f_rest<R>(q, pn);
-            mx = fmaxf(mx, fabsf(dv));
-            h16_put((half_t*)fdst, q * d.plane + n, dv, hs.sc);
+            const R dv = R(QW[q]) * (pv[q] - pn) + ev[q];
+            if constexpr (H) {
+                mx = fmaxf(mx, fabsf(dv));
+                h16_put((half_t*)fdst, q * d.plane + n, dv, hs.sc);
+            } else {
+                fdst[q * d.plane + n] = dv;
+            }
         }
     }
     return mx;
@@ -1121,37 +1173,42 @@ __device__ __forceinline__ void rho_mix3(const Dev& d, const R (&vp)[3][3], cons
 // S = rho mdot + u . grad(rho) at node m, vr the density around it.
 template <typename R>
 __device__ __forceinline__ R source_S(const State<R>& s, int sp, int64_t m, const R (&vr)[3][3]) {
-    R grx, gry, dum;
-    grad_lap<R>(vr, grx, gry, dum);
-    return vr[1][1] * s.md[sp][m] + s.ux[sp][m] * grx + s.uy[sp][m] * gry;
+    K w[3][3];
+    to_k(vr, w);
+    K grx, gry, dum;
+    grad_lap<K>(w, grx, gry, dum);
+    return R(w[1][1] * (K)s.md[sp][m] + (K)s.ux[sp][m] * grx + (K)s.uy[sp][m] * gry);
 }
 // F = F_s + F_e at node (i, j) from psi, f_s and rho around it (written to Fx, Fy).
 template <typename R>
 __device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int lcur, int i, int j, int64_t n,
-                                           const R (&vp)[3][3], const R (&vf)[3][3], R& FxOut, R& FyOut) {
+                                           const R (&vp)[3][3], const R (&vf)[3][3], K& FxOut, K& FyOut) {
     const R* phi = s.phi[lcur];
-    R vph[3][3], ve[3][3];
-    load3<GPHI, R>(phi, d, i, j, vph);
+    R vph_r[3][3];
+    load3<GPHI, R>(phi, d, i, j, vph_r);
+    K wp[3][3], vph[3][3], ve[3][3];
+    to_k(vp, wp);
+    to_k(vph_r, vph);
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int b = 0; b < 3; b++) ve[a][b] = mix<R>(d.eps_s, d.eps_l, d.eps_g, vp[a][b], vf[a][b]);
-    R gx, gy, lap;
-    grad_lap<R>(vp, gx, gy, lap);
-    R ps = vp[1][1];
-    R mu = R(4) * R(d.beta) * ps * (ps - R(1)) * (ps - R(0.5)) - R(d.kappa) * lap;
-    R Fx = mu * gx, Fy = mu * gy;
-    R gpx, gpy, lphi, gex, gey, dum;
-    grad_lap<R>(vph, gpx, gpy, lphi);
-    grad_lap<R>(ve, gex, gey, dum);
-    R eps = ve[1][1];
-    R Ex = -gpx, Ey = -gpy;
-    R qv = -(gex * gpx + gey * gpy + eps * lphi);
-    R E2 = Ex * Ex + Ey * Ey;
-    Fx += qv * Ex - R(0.5) * E2 * gex;
-    Fy += qv * Ey - R(0.5) * E2 * gey;
-    s.Fx[n] = Fx;
-    s.Fy[n] = Fy;
+        for (int b = 0; b < 3; b++) ve[a][b] = mix<K>(d.eps_s, d.eps_l, d.eps_g, wp[a][b], (K)vf[a][b]);
+    K gx, gy, lap;
+    grad_lap<K>(wp, gx, gy, lap);
+    K ps = wp[1][1];
+    K mu = 4.0 * d.beta * ps * (ps - 1.0) * (ps - 0.5) - d.kappa * lap;
+    K Fx = mu * gx, Fy = mu * gy;
+    K gpx, gpy, lphi, gex, gey, dum;
+    grad_lap<K>(vph, gpx, gpy, lphi);
+    grad_lap<K>(ve, gex, gey, dum);
+    K eps = ve[1][1];
+    K Ex = -gpx, Ey = -gpy;
+    K qv = -(gex * gpx + gey * gpy + eps * lphi);
+    K E2 = Ex * Ex + Ey * Ey;
+    Fx += qv * Ex - 0.5 * E2 * gex;
+    Fy += qv * Ey - 0.5 * E2 * gey;
+    s.Fx[n] = R(Fx);
+    s.Fy[n] = R(Fy);
     FxOut = Fx;
     FyOut = Fy;
 }
@@ -1161,22 +1218,27 @@ __device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int 
 template <typename R>
 __device__ __forceinline__ void h_prep2_at(const Dev& d, const State<R>& s, int sp, int i, int j, int64_t n,
                                            const R (&vp)[3][3], const R (&vf)[3][3], const R (&vr)[3][3],
-                                           const R (&vs)[3][3], R Fx, R Fy) {
-    R vpr[3][3];
-    load3<GMIRROR, R>(s.p[sp], d, i, j, vpr);
-    R grx, gry, gpx, gpy, gsx = R(0), gsy = R(0), dum;
-    grad_lap<R>(vr, grx, gry, dum);
-    grad_lap<R>(vpr, gpx, gpy, dum);
-    if (d.readings & 1u) grad_lap<R>(vs, gsx, gsy, dum);
-    R rho = vr[1][1];
-    R fsn = vf[1][1];
-    s.rho[n] = rho;
-    s.Ftx[n] = Fx - gpx + R(CS2) * grx + R(CS2) * gsx;
-    s.Fty[n] = Fy - gpy + R(CS2) * gry + R(CS2) * gsy;
-    s.Gx[n] = Fx + rho * (fsn * (R(0) - s.usx[n]));
-    s.Gy[n] = Fy + rho * (fsn * (R(0) - s.usy[n]));
-    R mu = mix<R>(d.mu_s, d.mu_l, d.mu_g, vp[1][1], fsn);
-    s.omh[n] = R(1) / (mu / (rho * R(CS2)) + R(0.5));
+                                           const R (&vs)[3][3], K Fx, K Fy) {
+    R vpr_r[3][3];
+    load3<GMIRROR, R>(s.p[sp], d, i, j, vpr_r);
+    K wr[3][3], vpr[3][3], ws[3][3];
+    to_k(vr, wr);
+    to_k(vpr_r, vpr);
+    to_k(vs, ws);
+    K grx, gry, gpx, gpy, gsx = 0.0, gsy = 0.0, dum;
+    grad_lap<K>(wr, grx, gry, dum);
+    grad_lap<K>(vpr, gpx, gpy, dum);
+    if (d.readings & 1u) grad_lap<K>(ws, gsx, gsy, dum);
+    const R rho_r = vr[1][1];
+    K rho = wr[1][1];
+    K fsn = (K)vf[1][1];
+    s.rho[n] = rho_r;
+    s.Ftx[n] = R(Fx - gpx + CS2 * grx + CS2 * gsx);
+    s.Fty[n] = R(Fy - gpy + CS2 * gry + CS2 * gsy);
+    s.Gx[n] = R(Fx + rho * (fsn * (0.0 - (K)s.usx[n])));
+    s.Gy[n] = R(Fy + rho * (fsn * (0.0 - (K)s.usy[n])));
+    R mu = mix<R>(d.mu_s, d.mu_l, d.mu_g, vp[1][1], vf[1][1]);
+    s.omh[n] = R(1) / (mu / (rho_r * R(CS2)) + R(0.5));
 }
 // Stages 3a and 3b in one pass.  The workgroup stages psi^{n+1}, f_s (wall ghosts applied) and
 // rho on its tile with a two-node ring (68 x 8) and S on the one-node ring (66 x 6) in LDS;
@@ -1221,7 +1283,8 @@ __device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp
     if (i >= d.nx || j >= d.ny) return;
     const int64_t n = at(d, i, j);
     const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-    R vp[3][3], vf[3][3], vr[3][3], vs[3][3], Fx, Fy;
+    R vp[3][3], vf[3][3], vr[3][3], vs[3][3];
+    K Fx, Fy;
     nb3(lps, tx + 2, ty + 2, vp);
     nb3(lfs, tx + 2, ty + 2, vf);
     nb3(lrho, tx + 2, ty + 2, vr);
@@ -1542,7 +1605,9 @@ __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, 
                 sg += (double)h16_get((const half_t*)s.g[sp], q * d.plane + n,
                                       g_rest<R>(q, s.H[sp][n], s.T[sp][n], R(d.Cref)), gi);
             } else {
-                sf += (double)s.f[sp][q * d.plane + n];
+                // FP32: f held as deviations from w_i psi
+                sf += (double)s.f[sp][q * d.plane + n] +
+                      (std::is_same<R, float>::value ? (double)f_rest<R>(q, s.psi[sp][n]) : 0.0);
                 sg += (double)s.g[sp][q * d.plane + n];
             }
         }
