@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Coupled-update throughput of the electrofreezing lattice Boltzmann hot path on one MI355X.
 
-A step is one full time step of Algorithm 1 on the 1024 x 512 sessile-drop workload (f, the
+A step is one full time step of Algorithm 1 on the 4096 x 2048 sessile-drop workload (f, the
 potential swept to a relative change of 1e-8, h, g and every coupling term), all in the HIP
-library; inputs are resident in HBM before the timed region.  Prints one JSON line with the
-coupled MLUPS, the roofline of the dominant kernel (the potential sweep) and the CPU oracle
-timed on a bounded sample of the same workload.
+library; inputs are resident in HBM before the timed region.  The initial potential is seeded
+by the learned warm start and swept to the same stopping rule before anything is timed (the
+run fails if that solve reaches its cap).  Prints one JSON line with the coupled MLUPS, the
+roofline of the kernel that takes the most time per step, the rooflines of every kernel of the
+step, the precision forms at the same size, and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,64 +31,67 @@ ELEM = {"fp64": 8, "fp32": 4, "fp16store": 4}
 # bytes per node of a step outside the sweeps; the FP16-storage form moves its 54 populations
 # as binary16 and its 26 field values as floats
 STEP_BYTES = {"fp64": STEP_ELEMS * 8, "fp32": STEP_ELEMS * 4, "fp16store": 54 * 2 + 26 * 4}
-# compulsory HBM bytes per node of one blocked launch (read once, written once, whatever the
-# number of sweeps): FP64 reads 4 links and 1/tau_l and writes 4 links and phi; FP32 reads 4
-# link remainders, 1/tau_l, the 4 pulled base increments and phi_B and writes 4 remainders and phi
+# compulsory HBM bytes per node of one blocked sweep launch (read once, written once, whatever
+# the number of sweeps): FP64 reads 4 links and 1/tau_l and writes 4 links and phi; FP32 reads
+# 4 link remainders, 1/tau_l, the 4 pulled base increments and phi_B and writes 4 remainders
+# and phi
 SWEEP_COMPULSORY = {"fp64": 10 * 8, "fp32": 15 * 4, "fp16store": 15 * 4}
+# bytes per node each kernel of the step must read and write when every neighbour it uses is
+# served on chip (populations 8 / 4 / 2 B, fields 8 / 4 / 4 B):
+#   f: f 9 + 9, psi, u (2), (psi u)^{n-1} (2), mdot, f_s in; psi, 1/tau_l out
+#   h inputs: psi, f_s, phi, u (2), mdot, p, u* (2) in; F (2), S, rho, F~ (2), F + rho f (2),
+#     1/tau_h out
+#   h streaming: h 9 + 9; p, rho, u (2), S, F~ (2), F + rho f (2), 1/tau_h, F (2), f_s in;
+#     u (2), u* (2), p out
+#   g streaming: g 9 + 9; H, T, psi (2 levels), f_s, u (2 levels x 2), mdot in; H, T, f_s,
+#     mdot, f_l, (psi u) (2) out
+KERNEL_BYTES = {
+    "k_f_fused_arm": {"fp64": 216, "fp32": 108, "fp16store": 72},
+    "k_h_prep": {"fp64": 144, "fp32": 72, "fp16store": 72},
+    "k_h_stream": {"fp64": 248, "fp32": 124, "fp16store": 88},
+    "k_g_stream": {"fp64": 304, "fp32": 152, "fp16store": 116},
+}
 
-
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sweep_tb_1024x512_counters.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernels_4096x2048_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2410_06657_amd", "csrc", "lbm_kernels.hpp")
 
 
-SWEEP_BEGIN = "// Blocked potential sweeps"
-SWEEP_END = "// FP32 form: renormalise"
+def kernel_source_digest():
+    """SHA-256 of the kernel source the counters must have been taken from."""
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
-def sweep_source_digest():
-    """SHA-256 of the sweep kernel's source section (its test, body and launch wrapper)."""
-    import hashlib
-    with open(KERNEL_SOURCE, encoding="utf-8") as f:
-        text = f.read()
-    a, b = text.find(SWEEP_BEGIN), text.find(SWEEP_END)
-    if a < 0 or b <= a:
+def measured_traffic(kernel, precision, workload_name):
+    """HBM bytes per launch of a kernel from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes scaled by a copy kernel's), or None when the summary is missing, covers
+    another workload, or was taken from a different kernel source."""
+    if workload_name != "4096x2048" or not os.path.exists(COUNTERS_FILE):
         return None
-    return hashlib.sha256(text[a:b].encode()).hexdigest()
-
-
-def measured_traffic(precision, workload_name):
-    """HBM bytes per launch of the timed sweep kernel from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel), or None when the summary
-    is missing, covers another workload, or was taken from a different kernel source."""
-    import hashlib
-    if workload_name != "1024x512" or not os.path.exists(COUNTERS_FILE):
-        return None
-    table = {}
+    sha, table = None, {}
     with open(COUNTERS_FILE) as f:
         for line in f:
             parts = line.split()
-            if len(parts) >= 2 and parts[0] in ("kernel_source_sha256", "traffic_bytes_per_launch_fp64",
-                                                "traffic_bytes_per_launch_fp32"):
-                table[parts[0]] = parts[1]
-    sha = sweep_source_digest()
-    if sha is None or table.get("kernel_source_sha256") != sha:
+            if len(parts) >= 2 and parts[0] == "kernel_source_sha256":
+                sha = parts[1]
+            elif len(parts) >= 4 and parts[0] == "traffic_bytes_per_launch":
+                table[(parts[1], parts[2])] = int(parts[3])
+    if sha is None or sha != kernel_source_digest():
         return None
-    # the FP16-storage form runs the FP32 sweep kernel (its potential links are FP32)
-    v = table.get(f"traffic_bytes_per_launch_{'fp32' if precision == 'fp16store' else precision}")
-    return int(v) if v else None
+    return table.get((kernel, precision))
 
 
 def workload(name):
     from paper_2410_06657_amd import inputs
-    if name == "1024x512":
+    if name == "4096x2048":
+        c = inputs.drop_4096x2048()
+        desc = "4096x2048 sessile drop, R0=640, theta=90, R=3, S=1 (prolate), Ca_E=0.1, Ste=0.1, rho_l/rho_g=10, k_s/k_l=2"
+    elif name == "1024x512":
         c = inputs.drop_1024x512(90.0, "prolate", 0.1)
         desc = "1024x512 sessile drop, R0=160, theta=90, R=3, S=1 (prolate), Ca_E=0.1, Ste=0.1, rho_l/rho_g=10, k_s/k_l=2"
     elif name == "128x64":
         c = inputs.drop_128x64(0)
         desc = "128x64 sessile drop, R0=24, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"
-    elif name == "4096x2048":
-        c = inputs.drop_4096x2048()
-        desc = "4096x2048 sessile drop, R0=640, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1"
     else:
         raise SystemExit(f"unknown workload {name}")
     return c, desc
@@ -114,14 +120,14 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
     """Oracle on the host cores: per-sweep time and the rest of a step, measured on the same
     grid, combined into one coupled step with the GPU's mean sweep count."""
     from oracle.binding import Oracle, set_threads
-    threads = os.cpu_count() or 1
+    threads = host_cpu()["nproc"]
     set_threads(threads)
     c = dict(case, poisson_tol=-1.0, poisson_max_sweeps=2)
     o = Oracle(c)  # fields, equilibria and a 2-sweep potential solve
     t0 = time.perf_counter()
-    o.solve_potential(-1.0, 5)
-    per_sweep = (time.perf_counter() - t0) / 5
-    nsw = max(5, min(200, int(budget_s * 0.5 / max(per_sweep, 1e-9))))
+    o.solve_potential(-1.0, 3)
+    per_sweep = (time.perf_counter() - t0) / 3
+    nsw = max(3, min(200, int(budget_s * 0.4 / max(per_sweep, 1e-9))))
     t0 = time.perf_counter()
     o.solve_potential(-1.0, nsw)
     per_sweep = (time.perf_counter() - t0) / nsw
@@ -134,28 +140,55 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
             "sweeps_per_s": 1.0 / per_sweep, "host": host_cpu(),
             "sample": f"{case['nx']}x{case['ny']} grid: {nsw} timed oracle sweeps "
                       f"({per_sweep * 1e3:.2f} ms each) and one step with two sweeps "
-                      f"({rest * 1e3:.1f} ms besides the sweep), combined as one step with "
+                      f"({rest * 1e3:.1f} ms besides the sweeps), combined as one step with "
                       f"{k_sweeps:.1f} sweeps (the GPU's mean)",
             "step_s": step_s}
 
 
-def run_form(case, precision, steps, warmup, sweep_launches, workload_name="1024x512"):
-    """Time `steps` coupled steps of one precision form, then the dominant kernel."""
-    import numpy as np
+def roofline_of(kernel, precision, n, seconds, workload_name, bytes_per_node, sweeps=None):
+    """HBM roofline of one kernel launch: algorithmic bytes over its live average duration."""
+    per_launch = bytes_per_node * n
+    achieved = per_launch / seconds / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4),
+         "traffic": measured_traffic(kernel, precision, workload_name),
+         "kernel": kernel, "avg_launch_us": round(seconds * 1e6, 2),
+         "algorithmic_bytes_per_launch": per_launch,
+         "working_set_fits_infinity_cache": per_launch <= INFINITY_CACHE_BYTES}
+    if sweeps is not None:
+        r["sweeps_per_launch"] = sweeps
+    return r
+
+
+def solver_converged(case, precision, net, factor, cap):
+    """A solver whose initial potential is the network's seed swept to the stopping rule."""
     import torch
 
     from paper_2410_06657_amd.lbm import Solver
+    t0 = time.perf_counter()
+    s = Solver(dict(case, skip_initial_solve=1, poisson_max_sweeps=cap), precision)
+    s.warm_start(net, factor)
+    rc, k, r = s.solve_potential(case["poisson_tol"], cap)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if rc != 0:
+        raise SystemExit(f"bench: the initial potential solve ({precision}) stopped at its cap of {cap} sweeps")
+    print(f"[bench] {precision}: warm-started initial solve {k} sweeps, {dt:.1f} s", file=sys.stderr, flush=True)
+    return s, k, dt
+
+
+def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net, factor, init_cap):
+    """Time `steps` coupled steps of one precision form from a converged potential, then each
+    kernel of the step."""
+    import numpy as np
+    import torch
 
     n = case["nx"] * case["ny"]
-    t0 = time.perf_counter()
-    s = Solver(case, precision=precision)
-    torch.cuda.synchronize()
-    init_s = time.perf_counter() - t0
-    print(f"[bench] {precision}: init {init_s:.1f}s, initial solve {s.sweep_log()[0]} sweeps",
-          file=sys.stderr, flush=True)
+    s, k_init, init_s = solver_converged(case, precision, net, factor, init_cap)
     s.step(warmup)
     torch.cuda.synchronize()
     nlog = len(s.sweep_log())
+    noconv0 = s.diag()["noconv"]
     t0 = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
@@ -164,90 +197,49 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name="1024
     kmean = float(np.mean(sweeps))
     ms_step = dt / steps * 1e3
     d = s.diag()
-    print(f"[bench] {precision}: {steps} steps, {ms_step:.3f} ms/step, {kmean:.1f} sweeps/step",
-          file=sys.stderr, flush=True)
-    # dominant kernel: the blocked potential sweep, timed with HIP events on the solver's
-    # stream over `sweep_launches` full launches of m sweeps each
+    capped = d["noconv"] - noconv0
+    print(f"[bench] {precision}: {steps} steps, {ms_step:.3f} ms/step, {kmean:.1f} sweeps/step, "
+          f"{capped} capped solves", file=sys.stderr, flush=True)
+    fields = {k: s.field(k) for k in ("psi", "ux", "uy", "p", "T", "phi")}
+    # the sweep kernel, timed with HIP events on the solver's stream over full launches
     m = case.get("sweep_block") or 8
-    nsweeps = sweep_launches * m
-    ms = s.time_sweeps(nsweeps)
-    launch_s = ms * 1e-3 / sweep_launches
-    es = ELEM[precision]
-    per_launch = SWEEP_ELEMS * es * n * m
-    achieved = per_launch / launch_s / 1e9
-    compulsory = SWEEP_COMPULSORY[precision] * n
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(precision, workload_name) if m == 8 else None,
-                "kernel": f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>",
-                "avg_launch_us": round(launch_s * 1e6, 3), "sweeps_per_launch": m,
-                "algorithmic_bytes_per_launch": per_launch,
-                "compulsory_hbm_bytes_per_launch": compulsory,
-                # a launch whose compulsory bytes fit the Infinity Cache may be served from it, so
-                # its byte counters (L2 misses) and "% HBM" are not HBM-only figures
-                "working_set_fits_infinity_cache": compulsory <= INFINITY_CACHE_BYTES}
-    coupled_bytes = (STEP_BYTES[precision] + SWEEP_ELEMS * kmean * es) * n
-    coupled_gbs = coupled_bytes / (ms_step * 1e-3) / 1e9
+    launch_s = s.time_sweeps(sweep_launches * m) * 1e-3 / sweep_launches
+    sweep_kernel = f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>"
+    rooflines = {"k_sweep_tb": roofline_of("k_sweep_tb", precision, n, launch_s, workload_name,
+                                           SWEEP_COMPULSORY[precision], sweeps=m)}
+    rooflines["k_sweep_tb"]["kernel"] = sweep_kernel
+    rooflines["k_sweep_tb"]["bytes"] = "compulsory: one read and one write of the links and fields per launch"
+    # the other kernels of the step (HIP events around back-to-back launches; leaves the state
+    # unusable, so this is the last thing done with the solver)
+    stage_ms = s.time_stages(5)
+    per_step = {"k_sweep_tb": kmean / m * launch_s * 1e3}
+    for name, ms in stage_ms.items():
+        rooflines[name] = roofline_of(name, precision, n, ms * 1e-3, workload_name, KERNEL_BYTES[name][precision])
+        per_step[name] = ms
+    stage_total = sum(stage_ms.values()) * 1e-3
+    dominant = max(per_step, key=per_step.get)
+    del s
+    torch.cuda.empty_cache()
     q = np.percentile(sweeps, [0, 10, 50, 90, 100])
+    coupled_bytes = (STEP_BYTES[precision] + SWEEP_ELEMS * kmean * ELEM[precision]) * n
     return {
         "value": round(n * steps / dt / 1e6, 3), "ms_per_step": round(ms_step, 4),
         "sweeps_per_step": round(kmean, 2),
         "sweeps_per_step_distribution": {"min": int(q[0]), "p10": float(q[1]), "p50": float(q[2]),
                                          "p90": float(q[3]), "max": int(q[4])},
+        "capped_solves_in_timed_steps": int(capped),
         "sweep_mlups": round(n * m / launch_s / 1e6, 1),
-        "sweep_time_share": round(min(1.0, kmean / m * launch_s * 1e3 / ms_step), 4),
-        "coupled_algorithmic_GBs": round(coupled_gbs, 1),
-        "coupled_hbm_roofline_frac": round(coupled_gbs / HBM_PEAK_GBS, 4),
-        "init_s": round(init_s, 2), "roofline": roofline,
-        "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"]},
+        "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "dominant_kernel": dominant,
+        "stage_kernels_hbm_frac_on_method_bytes": round(STEP_BYTES[precision] * n / stage_total / 1e9 / HBM_PEAK_GBS, 4),
+        "coupled_hbm_roofline_frac": round(coupled_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "initial_solve": {"sweeps": int(k_init), "seconds": round(init_s, 2), "start": "learned warm start",
+                          "converged": True},
+        "roofline": rooflines[dominant], "rooflines": rooflines,
+        "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"],
+                  "op_resid_over_ramp": d["op_resid"] / d["op_resid_ramp"] if d["op_resid_ramp"] else None},
+        "_fields": fields,
     }
-
-
-def run_precision_full_size(steps=10, sweeps=8, compare_after=2):
-    """The precision forms on the 4096 x 2048 drop (R0 = 640, theta = 90, R = 3, S = 1,
-    Ca_E = 0.1) with a fixed number of potential sweeps per step: relative L2 error per field
-    against the FP64 form after `compare_after` steps, then the time of `steps` more steps."""
-    import numpy as np
-    import torch
-
-    from paper_2410_06657_amd import inputs
-    from paper_2410_06657_amd.lbm import Solver
-
-    c = inputs.drop_4096x2048()
-    c.update(poisson_tol=-1.0, poisson_max_sweeps=sweeps)
-    n = c["nx"] * c["ny"]
-    fields = ("psi", "ux", "uy", "p", "T", "H", "fs", "phi")
-    out = {"workload": f"4096x2048 sessile drop, R0=640, theta=90, R=3, S=1, Ca_E=0.1, {sweeps} potential sweeps "
-                       f"per step (fixed), fields compared after {compare_after} steps, {steps} steps timed"}
-    ref = None
-    for prec in ("fp64", "fp32", "fp16store"):
-        s = Solver(c, prec)
-        s.step(compare_after)
-        cur = {k: s.field(k) for k in fields}
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.step(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        r = {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 4)}
-        # the sweep kernel at this size (its working set is far beyond the Infinity Cache)
-        launches = 10
-        launch_s = s.time_sweeps(launches * 8) * 1e-3 / launches
-        achieved = SWEEP_ELEMS * ELEM[prec] * n * 8 / launch_s / 1e9
-        r["sweep_roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(launch_s * 1e6, 2),
-                               "sweep_mlups": round(n * 8 / launch_s / 1e6, 1)}
-        if ref is None:
-            ref = cur
-        else:
-            r["rel_l2_error_vs_fp64"] = {k: float(np.linalg.norm(cur[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-300))
-                                         for k in fields}
-            r["speedup_vs_fp64"] = round(r["value"] / out["fp64"]["value"], 3)
-        out[prec] = r
-        del s
-        torch.cuda.empty_cache()
-        print(f"[bench] 4096x2048 {prec}: {r['ms_per_step']} ms/step", file=sys.stderr, flush=True)
-    return out
 
 
 def run_batched(steps, warmup, cap, seed=4, ncases=96):
@@ -525,20 +517,41 @@ def counters_probe(case, launches=20):
         del s
 
 
+def nn_probe(iters=10, batch=64, h=32, w=64):
+    """Short run of the warm-start network's kernels for a kernel trace: `iters` training steps
+    (forward, backward, Adam) and `iters` forward passes on `batch` random 32 x 64 maps."""
+    import torch
+
+    from paper_2410_06657_amd.lbm import Net
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn((batch, h, w, 3), generator=g, device="cuda")
+    t = torch.randn((batch, h, w), generator=g, device="cuda") * 0.1
+    net = Net(batch * h * w, seed=2)
+    for _ in range(iters):
+        net.train_step(x, t, 1e-3)
+    for _ in range(iters):
+        net.forward(x)
+    torch.cuda.synchronize()
+    print(f"[nn-probe] {iters} training steps and {iters} forward passes on {batch} x {h} x {w} pixels",
+          file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="1024x512")
-    ap.add_argument("--sweep-launches", type=int, default=100,
-                    help="blocked sweep launches timed with HIP events for the roofline")
+    ap.add_argument("--workload", default="4096x2048")
+    ap.add_argument("--sweep-launches", type=int, default=50,
+                    help="blocked sweep launches timed with HIP events for the sweep kernel's roofline")
+    ap.add_argument("--init-cap", type=int, default=4000000,
+                    help="sweep cap of the warm-started initial potential solve (the run fails if it is reached)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 forms (FP32 and FP16 storage)")
     ap.add_argument("--sweep-block", type=int, default=0,
                     help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
-    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--no-time-to-freeze", action="store_true", help="skip the time-to-freeze runs")
     ap.add_argument("--no-validation", action="store_true", help="skip the validation problems")
     ap.add_argument("--batched-steps", type=int, default=5)
@@ -546,44 +559,62 @@ def main():
                     help="potential sweeps cap per solve in the batched comparison")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc passes (copy calibration + sweep launches)")
+    ap.add_argument("--nn-probe", action="store_true",
+                    help="short run of the warm-start network's kernels (for a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
+    if args.nn_probe:
+        nn_probe()
+        return
     case, desc = workload(args.workload)
     case["sweep_block"] = args.sweep_block
     if args.counters:
         counters_probe(case)
         return
+    import numpy as np
+
+    from paper_2410_06657_amd import warm
     n = case["nx"] * case["ny"]
-    f64 = run_form(case, "fp64", args.steps, args.warmup, args.sweep_launches, args.workload)
+    factor = warm.factor_for(case["ny"])
+    net = warm.load((case["nx"] // factor) * (case["ny"] // factor))
+    run = lambda prec: run_form(case, prec, args.steps, args.warmup, args.sweep_launches, args.workload,
+                                net, factor, args.init_cap)
+    f64 = run("fp64")
+    ref = f64.pop("_fields")
     line = {
         "metric": METRIC, "value": f64["value"], "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "nx": case["nx"], "ny": case["ny"], "precision": "fp64",
-                   "poisson_tol": case["poisson_tol"], "sweeps_per_launch": case["sweep_block"] or 8},
+                   "poisson_tol": case["poisson_tol"], "sweeps_per_launch": case["sweep_block"] or 8,
+                   "initial_potential": "learned warm start, then sweeps to the same stopping rule"},
         "sweeps_per_step": f64["sweeps_per_step"],
         "sweeps_per_step_distribution": f64["sweeps_per_step_distribution"],
+        "capped_solves_in_timed_steps": f64["capped_solves_in_timed_steps"],
         "sweep_mlups": f64["sweep_mlups"],
-        "sweep_time_share": f64["sweep_time_share"],
+        "kernel_ms_per_step": f64["kernel_ms_per_step"],
+        "dominant_kernel": f64["dominant_kernel"],
+        "stage_kernels_hbm_frac_on_method_bytes": f64["stage_kernels_hbm_frac_on_method_bytes"],
         "coupled_hbm_roofline_frac": f64["coupled_hbm_roofline_frac"],
-        "coupled_algorithmic_GBs": f64["coupled_algorithmic_GBs"],
-        "init_s": f64["init_s"],
+        "initial_solve": f64["initial_solve"],
         "roofline": f64["roofline"],
+        "rooflines": f64["rooflines"],
         "state": f64["state"],
     }
     if not args.no_fp32:
-        f32 = run_form(case, "fp32", args.steps, args.warmup, args.sweep_launches, args.workload)
-        f32["speedup_vs_fp64"] = round(f32["value"] / f64["value"], 3)
-        line["forms"] = {"fp32": f32}
-        f16 = run_form(case, "fp16store", args.steps, args.warmup, args.sweep_launches, args.workload)
-        f16["speedup_vs_fp64"] = round(f16["value"] / f64["value"], 3)
-        line["forms"]["fp16store"] = f16
-        line["forms"]["precision_4096x2048"] = run_precision_full_size()
+        line["forms"] = {}
+        for prec in ("fp32", "fp16store"):
+            r = run(prec)
+            cur = r.pop("_fields")
+            r["speedup_vs_fp64"] = round(r["value"] / f64["value"], 3)
+            r["rel_l2_vs_fp64_after_timed_steps"] = {
+                k: float(np.linalg.norm(cur[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-300)) for k in ref}
+            line["forms"][prec] = r
     if not args.no_time_to_freeze:
         line["time_to_freeze"] = run_time_to_freeze()
     if not args.no_validation:

@@ -234,6 +234,17 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes);
    state advances by n sweeps.  Synchronises the stream. */
 int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
 
+/* Measurement: each kernel of the step outside the potential sweeps (Algorithm 1's f, h and g
+   updates and their coupling terms; lbm_stage_name(k) names kernel k) launched n times back to
+   back on the current state, bracketed by HIP events on the handle's stream; ms[k] gets the
+   average duration of kernel k.  The kernels also rewrite the single-buffered planes a step
+   carries into the next one (u*, psi u of the previous step, the FP32 enthalpy base), so the
+   handle is left in LBM_ESTATE: every later call but lbm_destroy, lbm_restore and the
+   measurement calls returns LBM_ESTATE until lbm_restore loads an image.  With ms == NULL only
+   *nstages is set and nothing runs; cap must be at least *nstages.  Synchronises the stream. */
+int lbm_time_stages(lbm_handle* h, int n, float* ms, int cap, int* nstages);
+const char* lbm_stage_name(int k);
+
 /* Autotuner of the potential-sweep launch shape (sweeps per launch x waves per
    workgroup) for one grid size and precision; the shape changes no result, only speed.
    Every candidate in {2, 4, 8} x {4, 8} is initialised in the caller's device workspace

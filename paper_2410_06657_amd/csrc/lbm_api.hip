@@ -55,6 +55,7 @@ struct lbm_handle {
     unsigned seq = 0;         // sequence number of the last published test
     bool resid_stale = false; // last_resid not yet read back from the control block
     bool vl_pending = false;  // the last step's liquid-volume sum not yet folded into the control block
+    bool spent = false;       // lbm_time_stages ran: the state is no longer a state of the method
     Ctl* dctl = nullptr;      // device control block
     double* partials = nullptr;
     std::string err;
@@ -550,6 +551,43 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
     return fetch_ctl(h);
 }
 
+// Measurement: each stage kernel of the step launched n times back to back on the current
+// state, bracketed by HIP events (each reads buffer sp and writes the other, so a repeat
+// rewrites the same values).  The kernels are the step's own, ungated.
+constexpr int NSTAGES = 4;
+const char* const STAGE_NAMES[NSTAGES] = {"k_f_fused_arm", "k_h_prep", "k_h_stream", "k_g_stream"};
+
+template <typename R, bool H = false>
+int time_stages(lbm_handle* h, int n, float* ms) {
+    const Dev& d = h->dev;
+    State<R>& s = h->st<R>();
+    const int sp = h->sp;
+    hipStream_t st = h->stream;
+    int frc = flush_vl(h);  // the f kernel's extra block would fold a pending volume sum
+    if (frc) return frc;
+    hipEvent_t ev[NSTAGES + 1];
+    for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+    HIPCHK(h, hipEventRecord(ev[0], st));
+    for (int k = 0; k < n; k++)
+        lbm::k_f_fused_arm<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, 0);
+    HIPCHK(h, hipEventRecord(ev[1], st));
+    for (int k = 0; k < n; k++) lbm::k_h_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp, h->lcur);
+    HIPCHK(h, hipEventRecord(ev[2], st));
+    for (int k = 0; k < n; k++) lbm::k_h_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 0);
+    HIPCHK(h, hipEventRecord(ev[3], st));
+    for (int k = 0; k < n; k++) lbm::k_g_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 0);
+    HIPCHK(h, hipEventRecord(ev[4], st));
+    LAUNCHCHK(h);
+    HIPCHK(h, hipEventSynchronize(ev[NSTAGES]));
+    for (int k = 0; k < NSTAGES; k++) {
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+        ms[k] = t / (float)n;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return LBM_OK;
+}
+
 // Device plane(s) of a field or population set in the current state, with the offset
 // kind that converts stored values to the raw FP64 values of the ABI.
 // enthalpy base; potential link bases; FP32 phase-field populations held as deviations from
@@ -803,7 +841,7 @@ int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, l
 }
 
 int lbm_step(lbm_handle* h, int n) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     if (n < 0) return LBM_EINVAL;
     for (int k = 0; k < n; k++) {
         int rc = h->prec == LBM_FP32_FP16STORE ? one_step<float, true>(h)
@@ -815,14 +853,14 @@ int lbm_step(lbm_handle* h, int n) {
 }
 
 int lbm_solve_potential(lbm_handle* h, double tol, int max_sweeps, int* sweeps, double* resid) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     if (max_sweeps < 1) return LBM_EINVAL;
     return h->prec != LBM_FP64 ? solve_potential<float>(h, tol, max_sweeps, sweeps, resid)
                                : solve_potential<double>(h, tol, max_sweeps, sweeps, resid);
 }
 
 int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     if (!out) return LBM_EINVAL;
     int rc = h->prec == LBM_FP32_FP16STORE ? diagnostics<float, true>(h)
              : h->prec == LBM_FP32          ? diagnostics<float>(h)
@@ -852,31 +890,31 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
 }
 
 int lbm_get_field(lbm_handle* h, int field, double* dst) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     return h->prec != LBM_FP64 ? get_set_field<float>(h, field, dst, true)
                                : get_set_field<double>(h, field, dst, true);
 }
 
 int lbm_get_field_device(lbm_handle* h, int field, double* dst) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     return h->prec != LBM_FP64 ? get_field_device<float>(h, field, dst) : get_field_device<double>(h, field, dst);
 }
 
 int lbm_set_field(lbm_handle* h, int field, const double* src) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     double* s = const_cast<double*>(src);
     return h->prec != LBM_FP64 ? get_set_field<float>(h, field, s, false)
                                : get_set_field<double>(h, field, s, false);
 }
 
 int lbm_get_pop(lbm_handle* h, int set, double* dst) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     if (h->prec == LBM_FP32_FP16STORE) return get_pop16(h, set, dst);
     return h->prec == LBM_FP32 ? get_set_pop<float>(h, set, dst, true) : get_set_pop<double>(h, set, dst, true);
 }
 
 int lbm_set_pop(lbm_handle* h, int set, const double* src) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     double* s = const_cast<double*>(src);
     // FP16 storage: a write of f, h or g would have to be encoded against the running scales
     if (h->prec == LBM_FP32_FP16STORE && set != LBM_POP_L) return LBM_EINVAL;
@@ -942,7 +980,7 @@ size_t ckpt_bytes(const lbm_handle* h) {
 }  // namespace
 
 int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     if (!bytes) return LBM_EINVAL;
     if (host) {
         int frc = flush_vl(h);  // the image carries the control block complete
@@ -1023,6 +1061,7 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
     h->step = hd.step;
     h->last_resid = hd.last_resid;
     h->init_conv = hd.init_conv;
+    h->spent = false;
     h->resid_stale = false;
     h->vl_pending = false;
     h->log = std::move(log);
@@ -1030,7 +1069,7 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
 }
 
 int lbm_run_until_frozen(lbm_handle* h, int max_steps, int check_every, int* steps_done) {
-    if (!h) return LBM_ESTATE;
+    if (!h || h->spent) return LBM_ESTATE;
     if (max_steps < 0 || check_every < 1) return LBM_EINVAL;
     int k = 0;
     while (k < max_steps) {
@@ -1051,6 +1090,20 @@ int lbm_time_sweeps(lbm_handle* h, int n, float* ms) {
     if (n < 1 || !ms) return LBM_EINVAL;
     return h->prec != LBM_FP64 ? time_sweeps<float, 1>(h, n, ms) : time_sweeps<double, 1>(h, n, ms);
 }
+
+int lbm_time_stages(lbm_handle* h, int n, float* ms, int cap, int* nstages) {
+    if (!h) return LBM_ESTATE;
+    if (n < 1 || !nstages) return LBM_EINVAL;
+    *nstages = NSTAGES;
+    if (!ms) return LBM_OK;
+    if (cap < NSTAGES) return LBM_EINVAL;
+    h->spent = true;
+    return h->prec == LBM_FP32_FP16STORE ? time_stages<float, true>(h, n, ms)
+           : h->prec == LBM_FP32          ? time_stages<float>(h, n, ms)
+                                          : time_stages<double>(h, n, ms);
+}
+
+const char* lbm_stage_name(int k) { return k >= 0 && k < NSTAGES ? STAGE_NAMES[k] : ""; }
 
 int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;

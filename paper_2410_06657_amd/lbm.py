@@ -31,7 +31,7 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_nn_destroy", "lbm_nn_last_error", "lbm_nn_features", "lbm_nn_target", "lbm_nn_seed",
            "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample", "lbm_checkpoint", "lbm_restore",
            "lbm_run_until_frozen", "lbm_batch_run_until_frozen", "lbm_autotune_workspace_bytes",
-           "lbm_get_field_device", "lbm_nn_forward_noalloc"]
+           "lbm_get_field_device", "lbm_nn_forward_noalloc", "lbm_time_stages", "lbm_stage_name"]
 
 LBM_TUNE_FORCE = 1
 
@@ -114,6 +114,9 @@ def lib():
         L.lbm_set_pop.argtypes = [vp, C.c_int, dp]
         L.lbm_sweep_log.argtypes = [vp, ip, C.c_int, ip]
         L.lbm_time_sweeps.argtypes = [vp, C.c_int, C.POINTER(C.c_float)]
+        L.lbm_time_stages.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_int)]
+        L.lbm_stage_name.argtypes = [C.c_int]
+        L.lbm_stage_name.restype = C.c_char_p
         L.lbm_destroy.argtypes = [vp]
         L.lbm_strerror.argtypes = [C.c_int]
         L.lbm_strerror.restype = C.c_char_p
@@ -342,6 +345,15 @@ class Solver:
         ms = C.c_float()
         self._check("lbm_time_sweeps", lib().lbm_time_sweeps(self._h, int(n), C.byref(ms)))
         return ms.value
+
+    def time_stages(self, n: int) -> dict:
+        """Average GPU milliseconds of each stage kernel over n back-to-back launches (HIP
+        events on the solver's stream); the state is left as it was."""
+        cnt = C.c_int()
+        self._check("lbm_time_stages", lib().lbm_time_stages(self._h, int(n), None, 0, C.byref(cnt)))
+        ms = (C.c_float * cnt.value)()
+        self._check("lbm_time_stages", lib().lbm_time_stages(self._h, int(n), ms, cnt.value, C.byref(cnt)))
+        return {lib().lbm_stage_name(k).decode(): float(ms[k]) for k in range(cnt.value)}
 
     def nn_features(self, factor: int):
         """Coarse input maps of the current state: torch FP32 (ny/f, nx/f, 3) on the device."""

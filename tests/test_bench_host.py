@@ -32,43 +32,59 @@ def test_byte_models():
     assert bench.ELEM["fp16store"] == 4 and bench.SWEEP_COMPULSORY["fp16store"] == bench.SWEEP_COMPULSORY["fp32"]
 
 
-def test_traffic_only_for_the_profiled_source(monkeypatch):
-    t64, t32 = bench.measured_traffic("fp64", "1024x512"), bench.measured_traffic("fp32", "1024x512")
-    if t64 is None:
-        pytest.skip("the committed counter summary was taken from another kernel source")
-    # above the compulsory bytes of a launch at 1024 x 512, below twice them
-    n = 1024 * 512
-    assert bench.SWEEP_COMPULSORY["fp64"] * n <= t64 < 2 * bench.SWEEP_COMPULSORY["fp64"] * n
-    assert bench.SWEEP_COMPULSORY["fp32"] * n <= t32 < 2 * bench.SWEEP_COMPULSORY["fp32"] * n
-    assert bench.measured_traffic("fp16store", "1024x512") == t32
-    assert bench.measured_traffic("fp64", "128x64") is None
-    monkeypatch.setattr(bench, "sweep_source_digest", lambda: "0" * 64)
-    assert bench.measured_traffic("fp64", "1024x512") is None
+def test_traffic_only_for_the_profiled_source(monkeypatch, tmp_path):
+    """Counter bytes are reported only from a summary of the same workload and kernel source."""
+    f = tmp_path / "c.md"
+    f.write_text(f"kernel_source_sha256 {bench.kernel_source_digest()}\n"
+                 "traffic_bytes_per_launch k_h_stream fp64 123456\n")
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
+    assert bench.measured_traffic("k_h_stream", "fp64", "4096x2048") == 123456
+    assert bench.measured_traffic("k_h_stream", "fp32", "4096x2048") is None
+    assert bench.measured_traffic("k_h_stream", "fp64", "1024x512") is None
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 64)
+    assert bench.measured_traffic("k_h_stream", "fp64", "4096x2048") is None
+
+
+def test_kernel_byte_tables():
+    # the kernels of a step together move more than the method's minimum (intermediate planes)
+    for prec in ("fp64", "fp32", "fp16store"):
+        assert sum(v[prec] for v in bench.KERNEL_BYTES.values()) >= bench.STEP_BYTES[prec]
+    assert bench.KERNEL_BYTES["k_g_stream"]["fp64"] == 18 * 8 + 20 * 8
 
 
 def test_main_line_contract(monkeypatch, capsys):
     """The JSON line's keys, with the GPU measurement replaced by a stand-in of the same shape."""
     import json
+    import types
 
-    def fake_form(case, precision, steps, warmup, sweep_launches, workload_name="1024x512"):
-        return {"value": 1000.0, "ms_per_step": 0.5, "sweeps_per_step": 80.0,
-                "sweeps_per_step_distribution": {"min": 70, "p10": 72.0, "p50": 80.0, "p90": 90.0, "max": 95},
-                "sweep_mlups": 2e5, "sweep_time_share": 0.5, "coupled_hbm_roofline_frac": 1.0,
-                "coupled_algorithmic_GBs": 8000.0, "init_s": 1.0,
-                "roofline": {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 1.25e-4,
-                             "traffic": None},
-                "state": {"step": 65, "V_s": 0.0, "height": 1.0, "nonfinite": 0}}
+    import numpy as np
+
+    def fake_form(case, precision, steps, warmup, sweep_launches, workload_name, net, factor, init_cap):
+        rl = {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 1.25e-4, "traffic": None}
+        return {"value": 1000.0, "ms_per_step": 0.5, "sweeps_per_step": 10.0,
+                "sweeps_per_step_distribution": {"min": 9, "p10": 9.0, "p50": 10.0, "p90": 11.0, "max": 12},
+                "capped_solves_in_timed_steps": 0, "sweep_mlups": 2e5,
+                "kernel_ms_per_step": {"k_h_stream": 0.5}, "dominant_kernel": "k_h_stream",
+                "stage_kernels_hbm_frac_on_method_bytes": 0.5, "coupled_hbm_roofline_frac": 0.5,
+                "initial_solve": {"sweeps": 1000, "seconds": 1.0, "start": "learned warm start", "converged": True},
+                "roofline": rl, "rooflines": {"k_h_stream": rl},
+                "state": {"step": 45, "V_s": 0.0, "height": 1.0, "nonfinite": 0, "op_resid_over_ramp": 0.05},
+                "_fields": {"psi": np.zeros((2, 2))}}
 
     monkeypatch.setattr(bench, "run_form", fake_form)
+    monkeypatch.setitem(sys.modules, "paper_2410_06657_amd.warm",
+                        types.SimpleNamespace(factor_for=lambda ny: 64, load=lambda px: None))
+    import paper_2410_06657_amd
+    monkeypatch.setattr(paper_2410_06657_amd, "warm", sys.modules["paper_2410_06657_amd.warm"], raising=False)
     monkeypatch.setattr(sys, "argv", ["bench.py", "--no-fp32", "--no-time-to-freeze", "--no-validation",
                                       "--no-warm", "--no-batched", "--no-cpu-baseline"])
     bench.main()
     line = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
               "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "sweeps_per_step",
-              "sweeps_per_step_distribution", "sweep_mlups"):
+              "sweeps_per_step_distribution", "sweep_mlups", "rooflines", "initial_solve"):
         assert k in line, k
-    assert line["n_gpus"] == 1 and line["config"]["nx"] == 1024 and line["dtype"] == "f64"
+    assert line["n_gpus"] == 1 and line["config"]["nx"] == 4096 and line["dtype"] == "f64"
     assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
 
 
