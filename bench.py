@@ -38,18 +38,15 @@ STEP_BYTES = {"fp64": STEP_ELEMS * 8, "fp32": STEP_ELEMS * 4, "fp16store": 54 * 
 SWEEP_COMPULSORY = {"fp64": 10 * 8, "fp32": 15 * 4, "fp16store": 15 * 4}
 # bytes per node each kernel of the step must read and write when every neighbour it uses is
 # served on chip (populations 8 / 4 / 2 B, fields 8 / 4 / 4 B):
-#   f: f 9 + 9, psi, u (2), (psi u)^{n-1} (2), mdot, f_s in; psi, 1/tau_l out
-#   h inputs: psi, f_s, phi, u (2), mdot, p, u* (2) in; F (2), S, rho, F~ (2), F + rho f (2),
-#     1/tau_h out
-#   h streaming: h 9 + 9; p, rho, u (2), S, F~ (2), F + rho f (2), 1/tau_h, F (2), f_s in;
-#     u (2), u* (2), p out
-#   g streaming: g 9 + 9; H, T, psi (2 levels), f_s, u (2 levels x 2), mdot in; H, T, f_s,
-#     mdot, f_l, (psi u) (2) out
+#   f: f 9 + 9; psi, u (2), (psi u)^{n-1} (2), mdot, f_s in; psi, 1/tau_l out
+#   h: h 9 + 9; psi^{n+1}, f_s, phi, p, u (2), u* (2), mdot in; p, u (2), u* (2) out (every
+#     coupling term of the flow step is evaluated on chip)
+#   g: g 9 + 9; H, T, psi (2 levels), f_s, u (2 levels x 2), mdot in; H, T, f_s, mdot, f_l,
+#     (psi u) (2) out; the FP32 forms also read and write the enthalpy base
 KERNEL_BYTES = {
-    "k_f_fused_arm": {"fp64": 216, "fp32": 108, "fp16store": 72},
-    "k_h_prep": {"fp64": 144, "fp32": 72, "fp16store": 72},
-    "k_h_stream": {"fp64": 248, "fp32": 124, "fp16store": 88},
-    "k_g_stream": {"fp64": 304, "fp32": 152, "fp16store": 116},
+    "k_f_fused_arm": {"fp64": 27 * 8, "fp32": 27 * 4, "fp16store": 18 * 2 + 9 * 4},
+    "k_h_fused": {"fp64": 32 * 8, "fp32": 32 * 4, "fp16store": 18 * 2 + 14 * 4},
+    "k_g_stream": {"fp64": 35 * 8, "fp32": 37 * 4, "fp16store": 18 * 2 + 19 * 4},
 }
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernels_4096x2048_counters.md")

@@ -122,6 +122,11 @@ Dev make_dev(const lbm_params* p) {
     d.tbx = (p->nx + (64 - 2 * m) - 1) / (64 - 2 * m);
     int ry = lbm::SW_NPT * sweep_w(p);
     d.tby = (p->ny + (ry - 2 * m) - 1) / (ry - 2 * m);
+    // flow step: segments as tall as 32 rows while the launch keeps at least 2048 workgroups
+    d.hx = (p->nx + lbm::WX - 1) / lbm::WX;
+    d.hseg = 32;
+    while (d.hseg > lbm::WR && (int64_t)d.hx * ((p->ny + d.hseg - 1) / d.hseg) < 2048) d.hseg -= lbm::WR;
+    d.hy = (p->ny + d.hseg - 1) / d.hseg;
     double tauf = p->M / lbm::CS2 + 0.5;  // Sec. 3.1
     d.omf = 1.0 / tauf;
     d.facf = 1.0 - 0.5 / tauf;
@@ -182,8 +187,7 @@ size_t carve(const Dev& d, char* base, State<R>* s, bool h16 = false) {
     t.dl = based ? c.take<R>(4 * P) : nullptr;
     t.pbp = based ? c.take<R>(P) : nullptr;
     t.hb = based ? c.take<R>(P) : nullptr;
-    R** singles[] = {&t.usx, &t.usy, &t.pux, &t.puy, &t.Ax, &t.Ay, &t.oml, &t.S, &t.Fx,
-                     &t.Fy, &t.rho, &t.Ftx, &t.Fty, &t.Gx, &t.Gy, &t.omh, &t.fl};
+    R** singles[] = {&t.usx[0], &t.usx[1], &t.usy[0], &t.usy[1], &t.pux, &t.puy, &t.oml, &t.fl};
     for (R** q : singles) *q = c.take<R>(P);
     t.partials = c.take<double>((size_t)lbm::part_total(nb, nbt));
     t.ctl = c.take<Ctl>(1);
@@ -450,8 +454,7 @@ int one_step(lbm_handle* h) {
     // stages 3-4 and the volume sum, gated on the loop's end and reading its final buffer
     // from the control block; queued behind every test of the loop (see run_sweeps)
     const std::function<void()> tail = [&]() {
-        lbm::k_h_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp, -1);
-        lbm::k_h_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_h_fused<R, H><<<d.hx * d.hy, NT, 0, st>>>(d, s, sp, -1);
         lbm::k_g_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
     };
     int rc = run_sweeps<R>(h, tol, 1, maxsw, nullptr, nullptr, true, &tail);
@@ -554,8 +557,8 @@ int time_sweeps(lbm_handle* h, int n, float* ms) {
 // Measurement: each stage kernel of the step launched n times back to back on the current
 // state, bracketed by HIP events (each reads buffer sp and writes the other, so a repeat
 // rewrites the same values).  The kernels are the step's own, ungated.
-constexpr int NSTAGES = 4;
-const char* const STAGE_NAMES[NSTAGES] = {"k_f_fused_arm", "k_h_prep", "k_h_stream", "k_g_stream"};
+constexpr int NSTAGES = 3;
+const char* const STAGE_NAMES[NSTAGES] = {"k_f_fused_arm", "k_h_fused", "k_g_stream"};
 
 template <typename R, bool H = false>
 int time_stages(lbm_handle* h, int n, float* ms) {
@@ -571,12 +574,10 @@ int time_stages(lbm_handle* h, int n, float* ms) {
     for (int k = 0; k < n; k++)
         lbm::k_f_fused_arm<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, 0);
     HIPCHK(h, hipEventRecord(ev[1], st));
-    for (int k = 0; k < n; k++) lbm::k_h_prep<R><<<h->nb, NT, 0, st>>>(d, s, sp, h->lcur);
+    for (int k = 0; k < n; k++) lbm::k_h_fused<R, H><<<d.hx * d.hy, NT, 0, st>>>(d, s, sp, h->lcur);
     HIPCHK(h, hipEventRecord(ev[2], st));
-    for (int k = 0; k < n; k++) lbm::k_h_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 0);
-    HIPCHK(h, hipEventRecord(ev[3], st));
     for (int k = 0; k < n; k++) lbm::k_g_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 0);
-    HIPCHK(h, hipEventRecord(ev[4], st));
+    HIPCHK(h, hipEventRecord(ev[3], st));
     LAUNCHCHK(h);
     HIPCHK(h, hipEventSynchronize(ev[NSTAGES]));
     for (int k = 0; k < NSTAGES; k++) {
@@ -603,8 +604,8 @@ R* field_ptr(lbm_handle* h, int field, Offset* off) {
         case LBM_PSI: return s.psi[sp];
         case LBM_UX: return s.ux[sp];
         case LBM_UY: return s.uy[sp];
-        case LBM_USX: return s.usx;
-        case LBM_USY: return s.usy;
+        case LBM_USX: return s.usx[sp];
+        case LBM_USY: return s.usy[sp];
         case LBM_P: return s.p[sp];
         case LBM_T: return s.T[sp];
         case LBM_H: *off = h->prec != LBM_FP64 ? OFF_G : OFF_NONE; return s.H[sp];
@@ -945,7 +946,7 @@ struct CkptHeader {
     int32_t init_conv, pad;
 };
 constexpr uint64_t CKPT_MAGIC = 0x4c424d434b505431ull;  // "LBMCKPT1"
-constexpr int32_t CKPT_VERSION = 2;
+constexpr int32_t CKPT_VERSION = 3;
 
 // FNV-1a over the values of every lbm_params member (not its padding bytes).
 uint64_t params_digest(const lbm_params& p) {
@@ -1265,6 +1266,7 @@ struct lbm_batch {
     std::vector<lbm::BatchCase<float>> cf;
     void* table = nullptr;               // device BatchCase<R>[ncases]
     int* first_node = nullptr;           // device: first node-grid block of each case
+    int* first_flow = nullptr;           // device: first flow-step window of each case
     int* first_sw = nullptr;             // device: first sweep-grid block of each case
     int* lcur_d = nullptr;               // device: current potential buffer of each case
     int* lcur0_d = nullptr;              // device: buffer at the start of the running solve
@@ -1273,7 +1275,7 @@ struct lbm_batch {
     lbm::SweepLaunch* fix_d = nullptr;
     Ctl* ctl_d = nullptr;                // ncases control blocks
     Ctl* ctl_h = nullptr;                // pinned mirror
-    int node_blocks = 0, sweep_blocks = 0;
+    int node_blocks = 0, sweep_blocks = 0, flow_blocks = 0;
     std::vector<int> lcur, kprev;
     std::vector<std::vector<int>> log;
     std::vector<int> frozen_sp;          // buffer parity of a frozen case's final state (-1: running)
@@ -1291,7 +1293,7 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> off;   // byte offset of each case's state
-    size_t table, first_node, first_sw, lcur, lcur0, tol, maxsw, fix, ctl, total;
+    size_t table, first_node, first_flow, first_sw, lcur, lcur0, tol, maxsw, fix, ctl, total;
 };
 
 int batch_validate(int ncases, const lbm_params* cases) {
@@ -1320,6 +1322,7 @@ BatchLayout batch_layout(int ncases, const lbm_params* cases) {
     auto take = [&](size_t bytes) { size_t r = off; off = round_up(off + bytes, ALIGN); return r; };
     L.table = take(cs * ncases);
     L.first_node = take(sizeof(int) * ncases);
+    L.first_flow = take(sizeof(int) * ncases);
     L.first_sw = take(sizeof(int) * ncases);
     L.lcur = take(sizeof(int) * ncases);
     L.lcur0 = take(sizeof(int) * ncases);
@@ -1468,8 +1471,7 @@ void batch_stage(lbm_batch* b, int which, int sp) {
     if (which == 0) {
         lbm::kb_f_fused<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
     } else {
-        lbm::kb_h_prep<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
-        lbm::kb_h_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_h_fused<R><<<b->flow_blocks, NT, 0, b->stream>>>(tb, b->first_flow, nc, sp, b->lcur_d);
         lbm::kb_g_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
         lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 0);
     }
@@ -1504,7 +1506,7 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     int nc = b->ncases;
     auto& cases = bcases<R>(b);
     cases.resize(nc);
-    std::vector<int> fn(nc), fs(nc);
+    std::vector<int> fn(nc), fs(nc), ff(nc);
     std::vector<double> tol(nc);
     std::vector<int> maxsw(nc);
     Ctl* ctl = (Ctl*)(ws + L.ctl);
@@ -1514,13 +1516,16 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
         cases[c].s.ctl = ctl + c;
         fn[c] = b->node_blocks;
         fs[c] = b->sweep_blocks;
+        ff[c] = b->flow_blocks;
         b->node_blocks += b->dev[c].gx * b->dev[c].gy;
+        b->flow_blocks += b->dev[c].hx * b->dev[c].hy;
         b->sweep_blocks += b->dev[c].tbx * b->dev[c].tby;
         tol[c] = b->prm[c].poisson_tol;
         maxsw[c] = b->prm[c].poisson_max_sweeps;
     }
     BHIP(b, hipMemcpyAsync(b->table, cases.data(), sizeof(lbm::BatchCase<R>) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->first_node, fn.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->first_flow, ff.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->first_sw, fs.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->tol_d, tol.data(), sizeof(double) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->maxsw_d, maxsw.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
@@ -1608,6 +1613,7 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
     for (int c = 0; c < ncases; c++) b->dev.push_back(make_dev(&cases[c]));
     b->table = ws + L.table;
     b->first_node = (int*)(ws + L.first_node);
+    b->first_flow = (int*)(ws + L.first_flow);
     b->first_sw = (int*)(ws + L.first_sw);
     b->lcur_d = (int*)(ws + L.lcur);
     b->lcur0_d = (int*)(ws + L.lcur0);

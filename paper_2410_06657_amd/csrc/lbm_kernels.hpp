@@ -50,6 +50,7 @@ struct Dev {
     int64_t plane;                  // elements per field plane = pitch * ny
     int gx, gy;                     // tiles in x and y
     int tbx, tby;                   // tiles of the blocked potential sweep in x and y
+    int hx, hy, hseg;               // flow-step windows: strips in x, segments in y, rows each
     double omf, facf;               // 1/tau_f and 1 - 1/(2 tau_f)
     double beta, kappa, wet, W;     // Eq. (5) and the wetting slope (4/W) cos(theta)
     double rho_s, rho_l, rho_g, mu_s, mu_l, mu_g;
@@ -474,8 +475,9 @@ struct State {
     R* dl;             // FP32: the 4 pulled base increments D of the current bases (see k_sweep_prep)
     R* pbp;            // FP32: the base potential phi_B = sum b / (1 - w_0)
     R* hb;             // enthalpy base of the FP32 rest link and H (unused in FP64)
-    R *usx, *usy, *pux, *puy, *Ax, *Ay, *oml, *S, *Fx, *Fy;
-    R *rho, *Ftx, *Fty, *Gx, *Gy, *omh, *fl;
+    R* usx[2];
+    R* usy[2];
+    R *pux, *puy, *oml, *fl;
     double* partials;  // per-block FP64 reduction partials
     Ctl* ctl;
 };
@@ -512,7 +514,7 @@ __device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile
     R fs = pc * (R(1) - fl);
     double phi0 = d.phi_bot + (d.phi_top - d.phi_bot) * (j + 0.5) / d.ny;
     s.psi[0][n] = psi;
-    s.ux[0][n] = 0; s.uy[0][n] = 0; s.usx[n] = 0; s.usy[n] = 0; s.p[0][n] = 0;
+    s.ux[0][n] = 0; s.uy[0][n] = 0; s.usx[0][n] = 0; s.usy[0][n] = 0; s.p[0][n] = 0;
     s.H[0][n] = Hn; s.T[0][n] = T; s.fs[0][n] = fs; s.md[0][n] = 0; s.fl[n] = fl;
     s.pux[n] = 0; s.puy[n] = 0;
     R rho = mix<R>(d.rho_s, d.rho_l, d.rho_g, psi, fs);
@@ -1161,38 +1163,75 @@ __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) 
 }
 
 // ---------------------------------------------------------------------------
-// Stage 3a: surface tension (Eqs. (3)-(5)) and electric force (Eq. (14)) with
-// psi^{n+1}; S = rho mdot + u . grad(rho) (Eq. (24)).
+// Stage 3, the flow step: surface tension (Eqs. (3)-(5)) and electric force (Eq. (14)) from
+// psi^{n+1}; S = rho mdot + u . grad(rho) (Eq. (24)); the collision inputs of h (rho, F~,
+// F + rho f_solid, 1/tau_h); h pulled and collided at its source with bounce-back at the
+// walls; u* (Eq. (25)), u (Eq. (26) with u_s = 0) and p (Eq. (27)).
+//
+// The chain psi, f_s -> rho -> S -> collision inputs -> pulls reaches three nodes out, so a
+// workgroup owns a strip of WX columns and a segment of d.hseg rows and walks down it WR rows
+// per pass, each quantity kept in LDS in a small ring of rows:
+//   psi^{n+1} (wetting ghost), f_s and rho (mirror ghost)   WX + 6 columns, 8 rows
+//   p (mirror ghost), phi (Dirichlet ghost), epsilon, S      WX + 4 columns, 6 rows
+//   collision inputs and F                                   WX + 2 columns, 6 rows
+// Pass t (rows b .. b + 3) stages psi, f_s, rho three rows ahead (b + 3 ..), p, phi,
+// epsilon and S two rows ahead, the collision inputs one row ahead, then streams rows b ..
+// b + 3.  Rows behind the window are never evaluated again, so besides the x halo only the
+// first pass of a segment evaluates anything twice.  WX + 2 = 64: one wave per row of
+// collision inputs.
+
+constexpr int WX = 62, WE = WX + 2, WS = WX + 4, WQ = WX + 6, WR = 4;
+static_assert(WE == 64 && NT == 64 * WR, "one wave per window row");
+
 template <typename R>
-__device__ __forceinline__ void rho_mix3(const Dev& d, const R (&vp)[3][3], const R (&vf)[3][3], R (&vr)[3][3]) {
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-        for (int b = 0; b < 3; b++) vr[a][b] = mix<R>(d.rho_s, d.rho_l, d.rho_g, vp[a][b], vf[a][b]);
+struct HWin {
+    R ps[8 * WQ], fs[8 * WQ], rho[8 * WQ];  // row y at slot (y - jb) & 7
+    R p[6 * WS], ph[6 * WS], S[6 * WS];     // row y at slot (y - jb) mod 6
+    K eps[6 * WS];
+    R in[10][6 * WE];  // collision inputs, member by member (HIn order), rows as p
+    R Fx[6 * WE], Fy[6 * WE];
+    int col[WQ];  // grid column of window column c (x wrapped)
+};
+template <typename R>
+__device__ __forceinline__ HIn<R> hin_at(const HWin<R>& L, int o) {
+    return HIn<R>{L.in[0][o], L.in[1][o], L.in[2][o], L.in[3][o], L.in[4][o],
+                  L.in[5][o], L.in[6][o], L.in[7][o], L.in[8][o], L.in[9][o]};
 }
-// S = rho mdot + u . grad(rho) at node m, vr the density around it.
 template <typename R>
-__device__ __forceinline__ R source_S(const State<R>& s, int sp, int64_t m, const R (&vr)[3][3]) {
+__device__ __forceinline__ void hin_put(HWin<R>& L, int o, const HIn<R>& a) {
+    L.in[0][o] = a.p; L.in[1][o] = a.rho; L.in[2][o] = a.ux; L.in[3][o] = a.uy; L.in[4][o] = a.S;
+    L.in[5][o] = a.Ftx; L.in[6][o] = a.Fty; L.in[7][o] = a.Gx; L.in[8][o] = a.Gy; L.in[9][o] = a.om;
+}
+
+// v[dy+1][dx+1] = row_{dy}[c + dx], rows r0, r1, r2 = y - 1, y, y + 1.
+template <typename T, typename U>
+__device__ __forceinline__ void rows3(const T* r0, const T* r1, const T* r2, int c, U (&v)[3][3]) {
+#pragma unroll
+    for (int dx = -1; dx <= 1; dx++) {
+        v[0][dx + 1] = r0[c + dx];
+        v[1][dx + 1] = r1[c + dx];
+        v[2][dx + 1] = r2[c + dx];
+    }
+}
+
+// S = rho mdot + u . grad(rho) at a node with mass source md and velocity (ux, uy); vr is
+// the density around it.
+template <typename R>
+__device__ __forceinline__ R source_S(R md, R ux, R uy, const R (&vr)[3][3]) {
     K w[3][3];
     to_k(vr, w);
     K grx, gry, dum;
     grad_lap<K>(w, grx, gry, dum);
-    return R(w[1][1] * (K)s.md[sp][m] + (K)s.ux[sp][m] * grx + (K)s.uy[sp][m] * gry);
+    return R(w[1][1] * (K)md + (K)ux * grx + (K)uy * gry);
 }
-// F = F_s + F_e at node (i, j) from psi, f_s and rho around it (written to Fx, Fy).
+
+// F = F_s + F_e at a node from psi, epsilon and phi around it.
 template <typename R>
-__device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int lcur, int i, int j, int64_t n,
-                                           const R (&vp)[3][3], const R (&vf)[3][3], K& FxOut, K& FyOut) {
-    const R* phi = s.phi[lcur];
-    R vph_r[3][3];
-    load3<GPHI, R>(phi, d, i, j, vph_r);
-    K wp[3][3], vph[3][3], ve[3][3];
+__device__ __forceinline__ void h_force(const Dev& d, const R (&vp)[3][3], const K (&ve)[3][3],
+                                        const R (&vph_r)[3][3], K& FxOut, K& FyOut) {
+    K wp[3][3], vph[3][3];
     to_k(vp, wp);
     to_k(vph_r, vph);
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-        for (int b = 0; b < 3; b++) ve[a][b] = mix<K>(d.eps_s, d.eps_l, d.eps_g, wp[a][b], (K)vf[a][b]);
     K gx, gy, lap;
     grad_lap<K>(wp, gx, gy, lap);
     K ps = wp[1][1];
@@ -1207,20 +1246,15 @@ __device__ __forceinline__ void h_prep1_at(const Dev& d, const State<R>& s, int 
     K E2 = Ex * Ex + Ey * Ey;
     Fx += qv * Ex - 0.5 * E2 * gex;
     Fy += qv * Ey - 0.5 * E2 * gey;
-    s.Fx[n] = R(Fx);
-    s.Fy[n] = R(Fy);
     FxOut = Fx;
     FyOut = Fy;
 }
 
-// Stage 3b: collision inputs of h: rho, F~, F + rho f_solid, 1/tau_h.
-// vs: S around the node (read only under the grad S reading).
+// Collision inputs of h at a node: vr, vpr and vs are rho, p and S around it; ps and fs its
+// own psi and f_s, (ux, uy) its velocity, (usx, usy) its u* of the previous step, F its force.
 template <typename R>
-__device__ __forceinline__ void h_prep2_at(const Dev& d, const State<R>& s, int sp, int i, int j, int64_t n,
-                                           const R (&vp)[3][3], const R (&vf)[3][3], const R (&vr)[3][3],
-                                           const R (&vs)[3][3], K Fx, K Fy) {
-    R vpr_r[3][3];
-    load3<GMIRROR, R>(s.p[sp], d, i, j, vpr_r);
+__device__ __forceinline__ HIn<R> h_inputs(const Dev& d, R ps, R fs, const R (&vr)[3][3], const R (&vpr_r)[3][3],
+                                           const R (&vs)[3][3], R ux, R uy, R usx, R usy, K Fx, K Fy) {
     K wr[3][3], vpr[3][3], ws[3][3];
     to_k(vr, wr);
     to_k(vpr_r, vpr);
@@ -1231,109 +1265,32 @@ __device__ __forceinline__ void h_prep2_at(const Dev& d, const State<R>& s, int 
     if (d.readings & 1u) grad_lap<K>(ws, gsx, gsy, dum);
     const R rho_r = vr[1][1];
     K rho = wr[1][1];
-    K fsn = (K)vf[1][1];
-    s.rho[n] = rho_r;
-    s.Ftx[n] = R(Fx - gpx + CS2 * grx + CS2 * gsx);
-    s.Fty[n] = R(Fy - gpy + CS2 * gry + CS2 * gsy);
-    s.Gx[n] = R(Fx + rho * (fsn * (0.0 - (K)s.usx[n])));
-    s.Gy[n] = R(Fy + rho * (fsn * (0.0 - (K)s.usy[n])));
-    R mu = mix<R>(d.mu_s, d.mu_l, d.mu_g, vp[1][1], vf[1][1]);
-    s.omh[n] = R(1) / (mu / (rho_r * R(CS2)) + R(0.5));
+    K fsn = (K)fs;
+    R mu = mix<R>(d.mu_s, d.mu_l, d.mu_g, ps, fs);
+    return HIn<R>{vpr_r[1][1],
+                  rho_r,
+                  ux,
+                  uy,
+                  vs[1][1],
+                  R(Fx - gpx + CS2 * grx + CS2 * gsx),
+                  R(Fy - gpy + CS2 * gry + CS2 * gsy),
+                  R(Fx + rho * (fsn * (0.0 - (K)usx))),
+                  R(Fy + rho * (fsn * (0.0 - (K)usy))),
+                  R(1) / (mu / (rho_r * R(CS2)) + R(0.5))};
 }
-// Stages 3a and 3b in one pass.  The workgroup stages psi^{n+1}, f_s (wall ghosts applied) and
-// rho on its tile with a two-node ring (68 x 8) and S on the one-node ring (66 x 6) in LDS;
-// every node then takes its psi, f_s, rho and S neighbourhoods from there.  The arithmetic is
-// that of the two stages run one after the other (the same expressions on the same values;
-// bitwise equal to that when it was fused).
-template <typename R>
-__device__ __forceinline__ void b_h_prep(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
-    __shared__ R lps[QN2], lfs[QN2], lrho[QN2], lS[RN];
-    const int i0 = (tile % d.gx) * TX - 2, j0 = (tile / d.gx) * TY - 2;
-    const R* psi = s.psi[sp ^ 1];
-    const R* fs = s.fs[sp];
-    for (int k = threadIdx.x; k < QN2; k += NT) {
-        const int gj = j0 + k / QX2;
-        if (gj < -1 || gj > d.ny) continue;  // beyond the ghost rows: never read
-        int gi = (i0 + k % QX2) % d.nx;
-        if (gi < 0) gi += d.nx;
-        const R p = ghosted<GWET, R>(psi, d, gi, gj), f = ghosted<GMIRROR, R>(fs, d, gi, gj);
-        lps[k] = p;
-        lfs[k] = f;
-        lrho[k] = mix<R>(d.rho_s, d.rho_l, d.rho_g, p, f);
-    }
-    __syncthreads();
-    auto nb3 = [&](const R* a, int qx, int qy, R (&v)[3][3]) {
-#pragma unroll
-        for (int dy = -1; dy <= 1; dy++)
-#pragma unroll
-            for (int dx = -1; dx <= 1; dx++) v[dy + 1][dx + 1] = a[(qy + dy) * QX2 + qx + dx];
-    };
-    for (int k = threadIdx.x; k < RN; k += NT) {
-        const int rx = k % RX, ry = k / RX, gj = j0 + 1 + ry;
-        if (gj < 0 || gj >= d.ny) continue;
-        int gi = (i0 + 1 + rx) % d.nx;
-        if (gi < 0) gi += d.nx;
-        R vr[3][3];
-        nb3(lrho, rx + 1, ry + 1, vr);
-        lS[k] = source_S<R>(s, sp, at(d, gi, gj), vr);
-    }
-    __syncthreads();
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
+
+// h pulled and collided at its source, bounce-back at the walls; u* (Eq. (25)), u (Eq. (26)
+// with u_s = 0), p (Eq. (27)).  hv[q]: the stored value the pull of direction q reads (h_q at
+// the source, or h_opp(q) at this node where the source is beyond a wall; FP16 storage: the
+// binary16 value, not yet scaled and offset); nbr(q): collision inputs of the source (a node
+// inside the grid); (Fx, Fy) and fsn: this node's force and solid fraction.  Returns the
+// largest binary16-stored deviation (FP16 storage) or 0.
+template <typename R, bool H, typename NB>
+__device__ __forceinline__ float h_stream_at(const Dev& d, const State<R>& s, int sp, int i, int j,
+                                             const HIn<R>& self, NB&& nbr, const R (&hv)[9], H16Scales hs,
+                                             R Fx, R Fy, R fsn) {
     const int64_t n = at(d, i, j);
-    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-    R vp[3][3], vf[3][3], vr[3][3], vs[3][3];
-    K Fx, Fy;
-    nb3(lps, tx + 2, ty + 2, vp);
-    nb3(lfs, tx + 2, ty + 2, vf);
-    nb3(lrho, tx + 2, ty + 2, vr);
-    // S around the node; beyond a wall the mirror ghost is the wall row's own value
-#pragma unroll
-    for (int dy = -1; dy <= 1; dy++) {
-        const int gj = j + dy, ry = (gj < 0 ? 0 : (gj >= d.ny ? d.ny - 1 : gj)) - (j0 + 1);
-#pragma unroll
-        for (int dx = -1; dx <= 1; dx++) vs[dy + 1][dx + 1] = lS[ry * RX + tx + 1 + dx];
-    }
-    h_prep1_at<R>(d, s, lcur, i, j, n, vp, vf, Fx, Fy);
-    s.S[n] = lS[ring_self()];
-    h_prep2_at<R>(d, s, sp, i, j, n, vp, vf, vr, vs, Fx, Fy);
-}
-// Stage kernels queued behind a potential loop before the host knows its outcome are gated:
-// they run only if the loop has ended (else the host queues them again once it has), and
-// take the final potential buffer from the control block (lcur < 0).
-template <typename R>
-__global__ void __launch_bounds__(NT) k_h_prep(Dev d, State<R> s, int sp, int lcur) {
-    if (lcur < 0) {
-        if (!s.ctl->done) return;
-        lcur = s.ctl->final_buf;
-    }
-    b_h_prep<R>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
-}
-
-template <typename R>
-__device__ __forceinline__ HIn<R> h_inputs(const State<R>& s, int sp, int64_t m) {
-    return HIn<R>{s.p[sp][m], s.rho[m], s.ux[sp][m], s.uy[sp][m], s.S[m],
-                  s.Ftx[m], s.Fty[m], s.Gx[m], s.Gy[m], s.omh[m]};
-}
-
-// Stage 3c: h pulled and collided at its source, bounce-back at the walls;
-// u* (Eq. (25)), u (Eq. (26) with u_s = 0), p (Eq. (27)).
-template <typename R, bool H = false>
-__device__ __forceinline__ float h_stream_node(const Dev& d, const State<R>& s, int sp, int tile,
-                                               const HIn<R>* ring, H16Scales hs) {
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return 0.f;
-    int64_t n = at(d, i, j);
-    const R* hsrc = s.h[sp];
     R* hdst = s.h[sp ^ 1];
-    auto src = [&](int q, int64_t m, R base) -> R {
-        if constexpr (H) return h16_get((const half_t*)hsrc, q * d.plane + m, base, hs.inv);
-        else return hsrc[q * d.plane + m];
-    };
-    const int me = ring_self();
-    const HIn<R> self = ring[me];
     R sx = R(0), sy = R(0), s0 = R(0);
     R vals[H ? 9 : 1];
 #pragma unroll
@@ -1342,11 +1299,14 @@ __device__ __forceinline__ float h_stream_node(const Dev& d, const State<R>& s, 
         R val;
         if (jj < 0 || jj >= d.ny) {
             int o = QOPP[q];
-            val = coll_h<R>(o, src(o, n, h_rest<R>(o, self.p)), self);
+            R raw = hv[q];
+            if constexpr (H) raw = h_rest<R>(o, self.p) + raw * hs.inv;
+            val = coll_h<R>(o, raw, self);
         } else {
-            int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-            const HIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
-            val = coll_h<R>(q, src(q, m, h_rest<R>(q, a.p)), a);
+            const HIn<R> a = nbr(q);
+            R raw = hv[q];
+            if constexpr (H) raw = h_rest<R>(q, a.p) + raw * hs.inv;
+            val = coll_h<R>(q, raw, a);
         }
         if constexpr (H) vals[q] = val;
         else hdst[q * d.plane + n] = val;
@@ -1355,11 +1315,10 @@ __device__ __forceinline__ float h_stream_node(const Dev& d, const State<R>& s, 
         if (q) s0 += val;
     }
     R rho = self.rho;
-    R fsn = s.fs[sp][n];
-    R ax = (sx + R(0.5) * s.Fx[n]) / rho;
-    R ay = (sy + R(0.5) * s.Fy[n]) / rho;
-    s.usx[n] = ax;
-    s.usy[n] = ay;
+    R ax = (sx + R(0.5) * Fx) / rho;
+    R ay = (sy + R(0.5) * Fy) / rho;
+    s.usx[sp ^ 1][n] = ax;
+    s.usy[sp ^ 1][n] = ay;
     R ux = ax + R(0.5) * fsn * (R(0) - ax);
     R uy = ay + R(0.5) * fsn * (R(0) - ay);
     s.ux[sp ^ 1][n] = ux;
@@ -1382,21 +1341,226 @@ __device__ __forceinline__ float h_stream_node(const Dev& d, const State<R>& s, 
     }
     return mx;
 }
-template <typename R, bool H = false>
-__device__ __forceinline__ void b_h_stream(const Dev& d, const State<R>& s, int sp, int tile) {
-    __shared__ HIn<R> ring[RN];
-    stage_ring(d, tile, ring, [&](int64_t m) { return h_inputs<R>(s, sp, m); });
-    if constexpr (H) {
-        const H16Scales hs = h16_scales(s.ctl, PS_H, sp);
-        h16_note_max(&s.ctl->hmax[PS_H][sp ^ 1], h_stream_node<R, true>(d, s, sp, tile, ring, hs));
-    } else {
-        h_stream_node<R>(d, s, sp, tile, ring, H16Scales{});
-    }
+
+// Column c (any integer) wrapped onto the periodic grid.
+__device__ __forceinline__ int wrap_col(int c, int nx) {
+    c %= nx;
+    return c < 0 ? c + nx : c;
 }
+
+// A field's value at row y in [-1, ny] from the value `raw` stored at row min(max(y, 0), ny - 1)
+// of the same column: ghosted() split into its read and its ghost rule.
+template <int G, typename R>
+__device__ __forceinline__ R ghost_fix(R raw, const Dev& d, int y) {
+    if (y < 0) {
+        if (G == GWET) return raw + R(d.wet) * raw * (R(1) - raw);
+        if (G == GPHI) return R(2.0 * d.phi_bot) - raw;
+        return raw;
+    }
+    if (y >= d.ny) {
+        if (G == GPHI) return R(2.0 * d.phi_top) - raw;
+        return raw;
+    }
+    return raw;
+}
+__device__ __forceinline__ int clamp_row(int y, int ny) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); }
+
+// Rows of pass t of a window (segment rows [jb, je)): psi, f_s, rho rows [qlo, qhi); p, phi,
+// epsilon, S rows [plo, phi); collision inputs rows [elo, ehi); streamed rows b .. b + 3.
+struct HPass {
+    int b, qlo, qhi, plo, phi, elo, ehi;
+};
+__device__ __forceinline__ HPass h_pass(const Dev& d, int jb, int je, int t) {
+    HPass a;
+    a.b = jb + WR * t;
+    a.qlo = max(t < 0 ? jb - 3 : a.b + 3, -1);
+    a.qhi = min(min(a.b + 7, je + 3), d.ny + 1);
+    a.plo = max(t < 0 ? jb - 2 : a.b + 2, -1);
+    a.phi = min(min(a.b + 6, je + 2), d.ny + 1);
+    a.elo = max(t < 0 ? jb - 1 : a.b + 1, 0);
+    a.ehi = min(min(a.b + 5, je + 1), d.ny);
+    return a;
+}
+
+// The global reads of one pass's staging, held in registers from the pass before: psi and
+// f_s (Q items), p and phi (P items), mdot and u (the S items), u and u* (this wave's row of
+// collision inputs).  Each thread holds at most two items of each kind (items k = threadIdx.x
+// and threadIdx.x + NT; a pass has at most 6 * WQ < 2 * NT Q items and 4 * WS P items).
+template <typename R>
+struct HFetch {
+    R qps[2], qfs[2], pp[2], pph[2], smd[2], sux[2], suy[2];
+    R eux, euy, eusx, eusy;
+};
+
 template <typename R, bool H = false>
-__global__ void __launch_bounds__(NT) k_h_stream(Dev d, State<R> s, int sp, int gate) {
-    if (gate && !s.ctl->done) return;
-    b_h_stream<R, H>(d, s, sp, xcd_tile(blockIdx.x, gridDim.x));
+__device__ __forceinline__ void b_h_fused(const Dev& d, const State<R>& s, int sp, int lcur, int tile) {
+    static_assert(6 * WQ <= 2 * NT && WR * WS <= 2 * NT, "two staging items per thread at most");
+    __shared__ HWin<R> L;
+    const int i0 = (tile % d.hx) * WX, jb = (tile / d.hx) * d.hseg;
+    const int je = min(jb + d.hseg, d.ny);
+    for (int c = threadIdx.x; c < WQ; c += NT) L.col[c] = wrap_col(i0 - 3 + c, d.nx);
+    H16Scales hs{};
+    if constexpr (H) hs = h16_scales(s.ctl, PS_H, sp);
+    float mx = 0.f;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const R* psi = s.psi[sp ^ 1];
+    const R* fs = s.fs[sp];
+    const R* pr = s.p[sp];
+    const R* ph = s.phi[lcur];
+    const R* ux = s.ux[sp];
+    const R* uy = s.uy[sp];
+    const R* md = s.md[sp];
+    const R* hsrc = s.h[sp];
+    auto q8 = [&](int y) { return ((y - jb + 8) & 7) * WQ; };
+    auto r6 = [&](int y) { return (y - jb + 6) % 6; };
+    __syncthreads();  // L.col
+    // issue the global reads of pass t's staging
+    auto fetch = [&](int t, HFetch<R>& f) {
+        const HPass a = h_pass(d, jb, je, t);
+        const int nq = (a.qhi - a.qlo) * WQ, np = (a.phi - a.plo) * WS;
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k < nq) {
+                const int64_t m = at(d, L.col[k % WQ], clamp_row(a.qlo + k / WQ, d.ny));
+                f.qps[u] = psi[m];
+                f.qfs[u] = fs[m];
+            }
+            if (k < np) {
+                const int y = a.plo + k / WS;
+                const int64_t m = at(d, L.col[k % WS + 1], clamp_row(y, d.ny));
+                f.pp[u] = pr[m];
+                f.pph[u] = ph[m];
+                if (y >= 0 && y < d.ny) {
+                    f.smd[u] = md[m];
+                    f.sux[u] = ux[m];
+                    f.suy[u] = uy[m];
+                }
+            }
+        }
+        const int ye = a.elo + wv;
+        if (ye < a.ehi) {
+            const int64_t m = at(d, L.col[lane + 2], ye);
+            f.eux = ux[m];
+            f.euy = uy[m];
+            f.eusx = s.usx[sp][m];
+            f.eusy = s.usy[sp][m];
+        }
+    };
+    HFetch<R> f;
+    fetch(-1, f);
+    // Pass -1 fills the rings for pass 0: psi, f_s, rho rows jb - 3 .., p, phi, epsilon, S rows
+    // jb - 2 .., collision inputs rows jb - 1 and jb.  Pass t >= 0 (b = jb + 4 t) adds psi, f_s,
+    // rho rows b + 3 .. b + 6, p, phi, epsilon, S rows b + 2 .. b + 5 and collision inputs rows
+    // b + 1 .. b + 4, then streams rows b .. b + 3.  Rows past what the segment's last row needs,
+    // and beyond the ghost rows, are skipped.  Global reads are issued a phase ahead of the
+    // arithmetic that waits for them: a pass's staging reads during the previous pass's
+    // streaming, its pulls of h before its collision inputs are evaluated.
+    for (int t = -1;; t++) {
+        const HPass a = h_pass(d, jb, je, t);
+        const int b = a.b;
+        if (b >= je) break;
+        const int nq = (a.qhi - a.qlo) * WQ, np = (a.phi - a.plo) * WS;
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k < nq) {
+                const int y = a.qlo + k / WQ, c = k % WQ;
+                const R pv = ghost_fix<GWET, R>(f.qps[u], d, y), fv = ghost_fix<GMIRROR, R>(f.qfs[u], d, y);
+                const int o = q8(y) + c;
+                L.ps[o] = pv;
+                L.fs[o] = fv;
+                L.rho[o] = mix<R>(d.rho_s, d.rho_l, d.rho_g, pv, fv);
+            }
+            if (k < np) {
+                const int y = a.plo + k / WS, c = k % WS;
+                const int o = r6(y) * WS + c;
+                L.p[o] = ghost_fix<GMIRROR, R>(f.pp[u], d, y);
+                L.ph[o] = ghost_fix<GPHI, R>(f.pph[u], d, y);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k >= np) break;
+            const int y = a.plo + k / WS, c = k % WS;
+            const int o = r6(y) * WS + c, qo = q8(y) + c + 1;
+            L.eps[o] = mix<K>(d.eps_s, d.eps_l, d.eps_g, (K)L.ps[qo], (K)L.fs[qo]);
+            if (y >= 0 && y < d.ny) {
+                R vr[3][3];
+                rows3(L.rho + q8(y - 1), L.rho + q8(y), L.rho + q8(y + 1), c + 1, vr);
+                L.S[o] = source_S<R>(f.smd[u], f.sux[u], f.suy[u], vr);
+            }
+        }
+        __syncthreads();
+        // this pass's streamed node (row b + wv, column i0 + lane): its solid fraction and the
+        // nine values its pulls read
+        const int j = b + wv, i = i0 + lane;
+        const bool gv = t >= 0 && j < je && lane < WX && i < d.nx;
+        R fsn = R(0);
+        R hv[9];
+        if (gv) {
+            fsn = L.fs[q8(j) + lane + 3];
+            const int64_t n = at(d, i, j);
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                const int jj = j - QY[q];
+                const int64_t k = (jj < 0 || jj >= d.ny) ? QOPP[q] * d.plane + n
+                                                         : q * d.plane + at(d, wrapx(i - QX[q], d.nx), jj);
+                if constexpr (H) hv[q] = (R)((const half_t*)hsrc)[k];
+                else hv[q] = hsrc[k];
+            }
+        }
+        const int ye = a.elo + wv;
+        if (ye < a.ehi) {
+            const int c = lane;
+            R vp[3][3], vr[3][3], vpr[3][3], vph[3][3], vs[3][3];
+            K ve[3][3];
+            rows3(L.ps + q8(ye - 1), L.ps + q8(ye), L.ps + q8(ye + 1), c + 2, vp);
+            rows3(L.rho + q8(ye - 1), L.rho + q8(ye), L.rho + q8(ye + 1), c + 2, vr);
+            const int sm = r6(ye - 1) * WS, s0 = r6(ye) * WS, sq = r6(ye + 1) * WS;
+            rows3(L.p + sm, L.p + s0, L.p + sq, c + 1, vpr);
+            rows3(L.ph + sm, L.ph + s0, L.ph + sq, c + 1, vph);
+            rows3(L.eps + sm, L.eps + s0, L.eps + sq, c + 1, ve);
+            // S beyond a wall: the mirror ghost is the wall row's own value
+            const int ys = ye > 0 ? sm : s0, yn = ye < d.ny - 1 ? sq : s0;
+            rows3(L.S + ys, L.S + s0, L.S + yn, c + 1, vs);
+            K Fx, Fy;
+            h_force<R>(d, vp, ve, vph, Fx, Fy);
+            const int o = r6(ye) * WE + c;
+            hin_put(L, o, h_inputs<R>(d, vp[1][1], L.fs[q8(ye) + c + 2], vr, vpr, vs, f.eux, f.euy, f.eusx,
+                                      f.eusy, Fx, Fy));
+            L.Fx[o] = R(Fx);
+            L.Fy[o] = R(Fy);
+        }
+        __syncthreads();
+        if (b + WR < je) fetch(t + 1, f);
+        if (gv) {
+            const int c = lane + 1;
+            const int rm = r6(j - 1) * WE, r0 = r6(j) * WE, rp = r6(j + 1) * WE;
+            // source of direction q: (i - cx, j - cy)
+            auto nbr = [&](int q) -> HIn<R> {
+                const int row = QY[q] > 0 ? rm : (QY[q] < 0 ? rp : r0);
+                return hin_at(L, row + c - QX[q]);
+            };
+            const float m = h_stream_at<R, H>(d, s, sp, i, j, hin_at(L, r0 + c), nbr, hv, hs, L.Fx[r0 + c],
+                                              L.Fy[r0 + c], fsn);
+            mx = fmaxf(mx, m);
+        }
+    }
+    if constexpr (H) h16_note_max(&s.ctl->hmax[PS_H][sp ^ 1], mx);
+}
+// Stage kernels queued behind a potential loop before the host knows its outcome are gated:
+// with lcur < 0 the kernel runs only if the loop has ended (else the host queues it again
+// once it has) and takes the final potential buffer from the control block.
+template <typename R, bool H = false>
+__global__ void __launch_bounds__(NT) k_h_fused(Dev d, State<R> s, int sp, int lcur) {
+    if (lcur < 0) {
+        if (!s.ctl->done) return;
+        lcur = s.ctl->final_buf;
+    }
+    b_h_fused<R, H>(d, s, sp, lcur, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename R>
@@ -1733,8 +1897,7 @@ LBM_BATCHED(kb_oml, b_oml, sp)
 LBM_BATCHED(kb_f_fused, b_f_fused, sp)
 LBM_BATCHED(kb_rebase, b_rebase, lcur[c])
 LBM_BATCHED(kb_sweep_prep, b_sweep_prep)
-LBM_BATCHED(kb_h_prep, b_h_prep, sp, lcur[c])
-LBM_BATCHED(kb_h_stream, b_h_stream, sp)
+LBM_BATCHED(kb_h_fused, b_h_fused, sp, lcur[c])
 LBM_BATCHED(kb_g_stream, b_g_stream, sp)
 LBM_BATCHED(kb_vl0, b_vl0)
 #undef LBM_BATCHED

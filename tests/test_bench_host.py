@@ -49,7 +49,11 @@ def test_kernel_byte_tables():
     # the kernels of a step together move more than the method's minimum (intermediate planes)
     for prec in ("fp64", "fp32", "fp16store"):
         assert sum(v[prec] for v in bench.KERNEL_BYTES.values()) >= bench.STEP_BYTES[prec]
-    assert bench.KERNEL_BYTES["k_g_stream"]["fp64"] == 18 * 8 + 20 * 8
+    # g: 18 populations; H, T, psi (2 levels), f_s, u (2 levels x 2), mdot in; H, T, f_s, mdot,
+    # f_l, psi u (2) out
+    assert bench.KERNEL_BYTES["k_g_stream"]["fp64"] == 18 * 8 + 17 * 8
+    # h: 18 populations; psi, f_s, phi, p, u (2), u* (2), mdot in; p, u (2), u* (2) out
+    assert bench.KERNEL_BYTES["k_h_fused"]["fp64"] == 18 * 8 + 14 * 8
 
 
 def test_main_line_contract(monkeypatch, capsys):
