@@ -167,7 +167,7 @@ struct Carver {
 // h16: the f, h and g sets in binary16 (the FP16-storage form; R = float).
 template <typename R>
 size_t carve(const Dev& d, char* base, State<R>* s, bool h16 = false) {
-    int nb = d.gx * d.gy, nbt = d.tbx * d.tby;
+    int nb = lbm::part_nb(d), nbt = d.tbx * d.tby;
     Carver c{base};
     State<R> t{};
     size_t P = (size_t)d.plane;
@@ -435,7 +435,7 @@ int one_step(lbm_handle* h) {
     const double tol = h->prm.poisson_tol;
     const int maxsw = h->prm.poisson_max_sweeps;
     const int fin = h->vl_pending ? 1 : 0;
-    lbm::k_f_fused_arm<R, H><<<h->nb + fin, NT, 0, st>>>(d, s, sp, tol, 1, maxsw, fin);
+    lbm::k_f_fused_arm<R, H><<<d.gx * d.hy + fin, NT, 0, st>>>(d, s, sp, tol, 1, maxsw, fin);
     h->vl_pending = false;
     LAUNCHCHK(h);
     if (h->wnn) {
@@ -455,7 +455,7 @@ int one_step(lbm_handle* h) {
     // from the control block; queued behind every test of the loop (see run_sweeps)
     const std::function<void()> tail = [&]() {
         lbm::k_h_fused<R, H><<<d.hx * d.hy, NT, 0, st>>>(d, s, sp, -1);
-        lbm::k_g_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 1);
+        lbm::k_g_stream<R, H><<<d.gx * d.hy, NT, 0, st>>>(d, s, sp, 1);
     };
     int rc = run_sweeps<R>(h, tol, 1, maxsw, nullptr, nullptr, true, &tail);
     if (rc == LBM_ENOCONV)
@@ -487,7 +487,7 @@ int init_state(lbm_handle* h) {
         if (solve_rc && solve_rc != LBM_ENOCONV) return solve_rc;
         h->init_conv = solve_rc == LBM_OK;
     }
-    lbm::k_vl0<R><<<h->nb, NT, 0, h->stream>>>(d, s);
+    lbm::k_vl0<R><<<d.gx * d.hy, NT, 0, h->stream>>>(d, s);
     lbm::k_vl_finalize<<<1, NT, 0, h->stream>>>(d, h->partials, h->dctl, 1, 0);
     LAUNCHCHK(h);
     int rc = fetch_ctl(h);
@@ -572,11 +572,11 @@ int time_stages(lbm_handle* h, int n, float* ms) {
     for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
     HIPCHK(h, hipEventRecord(ev[0], st));
     for (int k = 0; k < n; k++)
-        lbm::k_f_fused_arm<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, 0);
+        lbm::k_f_fused_arm<R, H><<<d.gx * d.hy, NT, 0, st>>>(d, s, sp, h->prm.poisson_tol, 1, h->prm.poisson_max_sweeps, 0);
     HIPCHK(h, hipEventRecord(ev[1], st));
     for (int k = 0; k < n; k++) lbm::k_h_fused<R, H><<<d.hx * d.hy, NT, 0, st>>>(d, s, sp, h->lcur);
     HIPCHK(h, hipEventRecord(ev[2], st));
-    for (int k = 0; k < n; k++) lbm::k_g_stream<R, H><<<h->nb, NT, 0, st>>>(d, s, sp, 0);
+    for (int k = 0; k < n; k++) lbm::k_g_stream<R, H><<<d.gx * d.hy, NT, 0, st>>>(d, s, sp, 0);
     HIPCHK(h, hipEventRecord(ev[3], st));
     LAUNCHCHK(h);
     HIPCHK(h, hipEventSynchronize(ev[NSTAGES]));
@@ -1267,6 +1267,7 @@ struct lbm_batch {
     void* table = nullptr;               // device BatchCase<R>[ncases]
     int* first_node = nullptr;           // device: first node-grid block of each case
     int* first_flow = nullptr;           // device: first flow-step window of each case
+    int* first_fg = nullptr;             // device: first f/g-stage window of each case
     int* first_sw = nullptr;             // device: first sweep-grid block of each case
     int* lcur_d = nullptr;               // device: current potential buffer of each case
     int* lcur0_d = nullptr;              // device: buffer at the start of the running solve
@@ -1275,7 +1276,7 @@ struct lbm_batch {
     lbm::SweepLaunch* fix_d = nullptr;
     Ctl* ctl_d = nullptr;                // ncases control blocks
     Ctl* ctl_h = nullptr;                // pinned mirror
-    int node_blocks = 0, sweep_blocks = 0, flow_blocks = 0;
+    int node_blocks = 0, sweep_blocks = 0, flow_blocks = 0, fg_blocks = 0;
     std::vector<int> lcur, kprev;
     std::vector<std::vector<int>> log;
     std::vector<int> frozen_sp;          // buffer parity of a frozen case's final state (-1: running)
@@ -1293,7 +1294,7 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> off;   // byte offset of each case's state
-    size_t table, first_node, first_flow, first_sw, lcur, lcur0, tol, maxsw, fix, ctl, total;
+    size_t table, first_node, first_flow, first_fg, first_sw, lcur, lcur0, tol, maxsw, fix, ctl, total;
 };
 
 int batch_validate(int ncases, const lbm_params* cases) {
@@ -1323,6 +1324,7 @@ BatchLayout batch_layout(int ncases, const lbm_params* cases) {
     L.table = take(cs * ncases);
     L.first_node = take(sizeof(int) * ncases);
     L.first_flow = take(sizeof(int) * ncases);
+    L.first_fg = take(sizeof(int) * ncases);
     L.first_sw = take(sizeof(int) * ncases);
     L.lcur = take(sizeof(int) * ncases);
     L.lcur0 = take(sizeof(int) * ncases);
@@ -1469,10 +1471,10 @@ void batch_stage(lbm_batch* b, int which, int sp) {
     auto tb = btable<R>(b);
     int nc = b->ncases;
     if (which == 0) {
-        lbm::kb_f_fused<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_f_fused<R><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, sp, b->lcur_d);
     } else {
         lbm::kb_h_fused<R><<<b->flow_blocks, NT, 0, b->stream>>>(tb, b->first_flow, nc, sp, b->lcur_d);
-        lbm::kb_g_stream<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, sp, b->lcur_d);
+        lbm::kb_g_stream<R><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, sp, b->lcur_d);
         lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 0);
     }
 }
@@ -1506,7 +1508,7 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     int nc = b->ncases;
     auto& cases = bcases<R>(b);
     cases.resize(nc);
-    std::vector<int> fn(nc), fs(nc), ff(nc);
+    std::vector<int> fn(nc), fs(nc), ff(nc), fg(nc);
     std::vector<double> tol(nc);
     std::vector<int> maxsw(nc);
     Ctl* ctl = (Ctl*)(ws + L.ctl);
@@ -1517,6 +1519,8 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
         fn[c] = b->node_blocks;
         fs[c] = b->sweep_blocks;
         ff[c] = b->flow_blocks;
+        fg[c] = b->fg_blocks;
+        b->fg_blocks += b->dev[c].gx * b->dev[c].hy;
         b->node_blocks += b->dev[c].gx * b->dev[c].gy;
         b->flow_blocks += b->dev[c].hx * b->dev[c].hy;
         b->sweep_blocks += b->dev[c].tbx * b->dev[c].tby;
@@ -1526,6 +1530,7 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     BHIP(b, hipMemcpyAsync(b->table, cases.data(), sizeof(lbm::BatchCase<R>) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->first_node, fn.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->first_flow, ff.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->first_fg, fg.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->first_sw, fs.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->tol_d, tol.data(), sizeof(double) * nc, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->maxsw_d, maxsw.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
@@ -1539,7 +1544,7 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     if (rc) return rc;
     b->init_conv.assign(nc, 1);
     for (int c = 0; c < nc; c++) b->init_conv[c] = b->ctl_h[c].conv;
-    lbm::kb_vl0<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
+    lbm::kb_vl0<R><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, 0, b->lcur_d);
     lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 1);
     BHIP(b, hipGetLastError());
     BHIP(b, hipStreamSynchronize(b->stream));
@@ -1614,6 +1619,7 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
     b->table = ws + L.table;
     b->first_node = (int*)(ws + L.first_node);
     b->first_flow = (int*)(ws + L.first_flow);
+    b->first_fg = (int*)(ws + L.first_fg);
     b->first_sw = (int*)(ws + L.first_sw);
     b->lcur_d = (int*)(ws + L.lcur);
     b->lcur0_d = (int*)(ws + L.lcur0);

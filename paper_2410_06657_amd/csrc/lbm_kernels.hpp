@@ -220,6 +220,64 @@ __device__ __forceinline__ void stage_ring(const Dev& d, int tile, T* ring, F&& 
 __device__ __forceinline__ int ring_self() { return (threadIdx.x / TX + 1) * RX + (threadIdx.x & (TX - 1)) + 1; }
 __device__ __forceinline__ int ring_from(int self, int cx, int cy) { return self - cy * RX - cx; }
 
+// Windows of the stage kernels.  A workgroup owns a strip of WX output columns and a segment
+// of d.hseg rows and walks down it WR rows per pass, one wave per row, keeping what the
+// stencils of the pass need in LDS rings of rows: fields WS = WX + 4 columns wide (the strip
+// with a two-node halo), collision inputs WE = WX + 2 = 64 wide (one lane per column).  The
+// grid columns of the window are tabulated once (x wrapped): window column c is grid column
+// i0 - 3 + c.  Rows behind a pass are never evaluated again, so besides the x halo only a
+// segment's first pass evaluates anything twice.
+constexpr int WX = 62, WE = WX + 2, WS = WX + 4, WQ = WX + 6, WR = 4;
+static_assert(WE == 64 && NT == 64 * WR, "one wave per window row");
+
+// The f and g stages evaluate little per node and stream most of their bytes: their windows are
+// strips of AX = 64 output columns aligned with the rows' cache lines, with collision inputs
+// AE = AX + 2 and fields AS = AX + 4 columns wide (window column c is grid column i0 - 2 + c),
+// d.gx strips by d.hy segments of d.hseg rows.
+constexpr int AX = 64, AE = AX + 2, AS = AX + 4;
+static_assert(WR * AS <= 2 * NT, "two staging items per thread at most");
+
+// Column c (any integer) wrapped onto the periodic grid.
+__device__ __forceinline__ int wrap_col(int c, int nx) {
+    c %= nx;
+    return c < 0 ? c + nx : c;
+}
+__device__ __forceinline__ int clamp_row(int y, int ny) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); }
+// Ring slot of row y in a window whose segment starts at row jb (rows >= jb - 6).
+__device__ __forceinline__ int slot6(int y, int jb) { return (y - jb + 6) % 6; }
+// Blocks of the node-parallel per-block partial sums: enough for the node tiles and the windows.
+__host__ __device__ inline int part_nb(const Dev& d) {
+    const int a = d.gx * d.gy, b = d.hx * d.hy;
+    return a > b ? a : b;
+}
+
+// v[dy+1][dx+1] = row_{dy}[c + dx], rows r0, r1, r2 = y - 1, y, y + 1.
+template <typename T, typename U>
+__device__ __forceinline__ void rows3(const T* r0, const T* r1, const T* r2, int c, U (&v)[3][3]) {
+#pragma unroll
+    for (int dx = -1; dx <= 1; dx++) {
+        v[0][dx + 1] = r0[c + dx];
+        v[1][dx + 1] = r1[c + dx];
+        v[2][dx + 1] = r2[c + dx];
+    }
+}
+
+// A field's value at row y in [-1, ny] from the value `raw` stored at row min(max(y, 0), ny - 1)
+// of the same column: ghosted() split into its read and its ghost rule.
+template <int G, typename R>
+__device__ __forceinline__ R ghost_fix(R raw, const Dev& d, int y) {
+    if (y < 0) {
+        if (G == GWET) return raw + R(d.wet) * raw * (R(1) - raw);
+        if (G == GPHI) return R(2.0 * d.phi_bot) - raw;
+        return raw;
+    }
+    if (y >= d.ny) {
+        if (G == GPHI) return R(2.0 * d.phi_top) - raw;
+        return raw;
+    }
+    return raw;
+}
+
 // Wave-wide lane shifts by one lane on the VALU (DPP wave_shr / wave_shl): lane_up gives lane
 // i the value of lane i - 1, lane_down the value of lane i + 1 (the lane at the end gets 0,
 // written by the DPP bound control, so no register has to be cleared first).
@@ -558,8 +616,8 @@ __global__ void __launch_bounds__(NT) k_init(Dev d, State<R> s) {
 // advances the step counter, and t_fre is the first step with V_l <= 1% of V_l0, interpolated
 // linearly.  sh: NT / 64 doubles.
 __device__ __forceinline__ void vl_finalize_body(const Dev& d, const double* partials, Ctl* c, int mode, double* sh) {
-    int nb = d.gx * d.gy;
-    const double* pv = partials + part_vl(nb);
+    const int nb = d.gx * d.hy;  // one partial per window of the g stage
+    const double* pv = partials + part_vl(part_nb(d));
     double a = 0.0;
     for (int k = threadIdx.x; k < nb; k += NT) a += pv[k];
     a = block_sum(a, sh);
@@ -624,31 +682,24 @@ __device__ __forceinline__ void a_term(const Dev& d, const R (&v)[3][3], R ux, R
     Ay = R((py - (K)puy) + CS2 * lam * ny);
 }
 
-// Stage 1b: f pulled and collided at its source, half-way bounce-back at the
-// walls; psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.  The collision
-// inputs of the tile and its ring are staged in LDS first (`ring`).
+// Stage 1b: f pulled and collided at its source, half-way bounce-back at the walls;
+// psi^{n+1} = sum f / (1 - mdot/2) (Eq. (20)); 1/tau_l for the sweeps.
 // FP64 keeps the populations raw.  The FP32 forms (R = float; H: binary16 storage) keep each
 // population as its deviation from w_i psi of its node and collide in deviation form: a link
 // pulled from node y arrives as w_i psi(y) + e_i with e_i the collided deviation, psi^{n+1} is
 // (sum_i w_i psi(y_i) + sum_i e_i) / (1 - mdot/2), and the stored deviation is
 // w_i (psi(y_i) - psi^{n+1}) + e_i, a difference of neighbouring psi plus a small term.
-// H: returns the largest |deviation| the thread wrote (0 otherwise).
-template <typename R, bool H = false>
-__device__ __forceinline__ float f_collide_stream(const Dev& d, const State<R>& s, int sp, int tile,
-                                                  const FIn<R>* ring, H16Scales hs = {}) {
+// hv[q]: the stored value the pull of direction q reads (f_q at the source, or f_opp(q) at this
+// node where the source is beyond a wall; FP16 storage: the binary16 value, not yet scaled);
+// self, nbr(q): collision inputs of this node and of the source of direction q; mdn, fsn:
+// this node's mdot and f_s.  H: returns the largest |deviation| written (0 otherwise).
+template <typename R, bool H, typename NB>
+__device__ __forceinline__ float f_stream_at(const Dev& d, const State<R>& s, int sp, int i, int j,
+                                             const FIn<R>& self, NB&& nbr, const R (&hv)[9], H16Scales hs,
+                                             R mdn, R fsn) {
     constexpr bool DEV = std::is_same<R, float>::value;
-    const R* md = s.md[sp];
-    int i, j;
-    node_of(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return 0.f;
-    int64_t n = at(d, i, j);
-    const R* fsrc = s.f[sp];
+    const int64_t n = at(d, i, j);
     R* fdst = s.f[sp ^ 1];
-    auto src = [&](int q, int64_t m) -> R {  // the stored value (raw, or the deviation)
-        if constexpr (H) return h16_get((const half_t*)fsrc, q * d.plane + m, 0.f, hs.inv);
-        else return fsrc[q * d.plane + m];
-    };
-    const int me = ring_self();
     R sum = R(0), esum = R(0);
     R ev[DEV ? 9 : 1], pv[DEV ? 9 : 1];
 #pragma unroll
@@ -656,23 +707,24 @@ __device__ __forceinline__ float f_collide_stream(const Dev& d, const State<R>& 
         int jj = j - QY[q];
         const bool wall = jj < 0 || jj >= d.ny;
         const int o = wall ? QOPP[q] : q;  // bounce-back: the node's own opposite link
-        const FIn<R>& a = wall ? ring[me] : ring[ring_from(me, QX[q], QY[q])];
-        const int64_t m = wall ? n : at(d, wrapx(i - QX[q], d.nx), jj);
+        const FIn<R> a = wall ? self : nbr(q);
+        R raw = hv[q];
+        if constexpr (H) raw = 0.f + raw * hs.inv;
         if constexpr (DEV) {
-            const R e = coll_f_dev<R>(o, src(o, m), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            const R e = coll_f_dev<R>(o, raw, a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
             ev[q] = e;
             pv[q] = a.psi;
             sum += f_rest<R>(q, a.psi);
             esum += e;
         } else {
-            const R val = coll_f<R>(o, src(o, m), a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
+            const R val = coll_f<R>(o, raw, a.psi, a.ux, a.uy, a.Ax, a.Ay, a.md, d);
             fdst[q * d.plane + n] = val;
             sum += val;
         }
     }
-    R pn = (sum + esum) / (R(1) - R(0.5) * md[n]);
+    R pn = (sum + esum) / (R(1) - R(0.5) * mdn);
     s.psi[sp ^ 1][n] = pn;
-    R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, pn, s.fs[sp][n]);
+    R sig = mix<R>(d.sig_s, d.sig_l, d.sig_g, pn, fsn);
     s.oml[n] = R(1) / (sig / R(CS2) + R(0.5));
     float mx = 0.f;
     if constexpr (DEV) {
@@ -691,49 +743,133 @@ __device__ __forceinline__ float f_collide_stream(const Dev& d, const State<R>& 
     return mx;
 }
 
-// Stages 1a and 1b in one pass: psi^n (wall ghosts applied) is staged on the tile with a
-// two-node ring (68 x 8) in LDS, A (a_term) is evaluated on the one-node ring from it, and the
-// collision inputs of the ring go to LDS for f_collide_stream (the same arithmetic as
-// evaluating A at every node in a pass of its own; kept bitwise when it was fused).
+// Stages 1a and 1b in one pass over a window (see AX): psi^n (wetting ghost) two rows ahead
+// (AS columns), A and the other collision inputs of f one row ahead (AE columns), then the
+// streaming of rows b .. b + 3.  The global reads of a pass's staging are issued during the
+// previous pass's streaming, the pulls of f before the collision inputs are evaluated.
+template <typename R>
+struct FWin {
+    R ps[6 * AS];      // psi^n, row y at slot slot6(y, jb)
+    R in[6][6 * AE];   // collision inputs member by member (FIn order), rows as ps
+    int col[AS];
+};
+template <typename R>
+__device__ __forceinline__ FIn<R> fin_at(const FWin<R>& L, int o) {
+    return FIn<R>{L.in[0][o], L.in[1][o], L.in[2][o], L.in[3][o], L.in[4][o], L.in[5][o]};
+}
+// Rows of pass t of an f or g window: fields rows [plo, phi), collision inputs rows [elo, ehi),
+// streamed rows b .. b + 3 (t = -1: the rings' first rows only).
+struct SPass {
+    int b, plo, phi, elo, ehi;
+};
+__device__ __forceinline__ SPass s_pass(const Dev& d, int jb, int je, int t) {
+    SPass a;
+    a.b = jb + WR * t;
+    a.plo = max(t < 0 ? jb - 2 : a.b + 2, -1);
+    a.phi = min(min(a.b + 6, je + 2), d.ny + 1);
+    a.elo = max(t < 0 ? jb - 1 : a.b + 1, 0);
+    a.ehi = min(min(a.b + 5, je + 1), d.ny);
+    return a;
+}
 template <typename R, bool H = false>
 __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int sp, int tile) {
-    __shared__ R lps[QN2];
-    __shared__ FIn<R> ring[RN];
-    const int i0 = (tile % d.gx) * TX - 2, j0 = (tile / d.gx) * TY - 2;
+    __shared__ FWin<R> L;
+    const int i0 = (tile % d.gx) * AX, jb = (tile / d.gx) * d.hseg;
+    const int je = min(jb + d.hseg, d.ny);
+    for (int c = threadIdx.x; c < AS; c += NT) L.col[c] = wrap_col(i0 - 2 + c, d.nx);
+    H16Scales hs{};
+    if constexpr (H) hs = h16_scales(s.ctl, PS_F, sp);
+    float mx = 0.f;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const R* psi = s.psi[sp];
-    for (int k = threadIdx.x; k < QN2; k += NT) {
-        const int gj = j0 + k / QX2;
-        if (gj < -1 || gj > d.ny) continue;  // beyond the ghost rows: never read
-        int gi = (i0 + k % QX2) % d.nx;
-        if (gi < 0) gi += d.nx;
-        lps[k] = ghosted<GWET, R>(psi, d, gi, gj);
-    }
-    __syncthreads();
     const R* ux = s.ux[sp];
     const R* uy = s.uy[sp];
     const R* md = s.md[sp];
-    for (int k = threadIdx.x; k < RN; k += NT) {
-        const int rx = k % RX, ry = k / RX, gj = j0 + 1 + ry;
-        if (gj < 0 || gj >= d.ny) continue;
-        int gi = (i0 + 1 + rx) % d.nx;
-        if (gi < 0) gi += d.nx;
-        const int64_t m = at(d, gi, gj);
-        R v[3][3];
+    const R* fsrc = s.f[sp];
+    __syncthreads();  // L.col
+    struct Fetch {
+        R ps[2], ux[2], uy[2], pux[2], puy[2], md[2];
+    } f;
+    auto fetch = [&](int t) {
+        const SPass a = s_pass(d, jb, je, t);
+        const int np = (a.phi - a.plo) * AS, ne = (a.ehi - a.elo) * AE;
 #pragma unroll
-        for (int dy = -1; dy <= 1; dy++)
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k < np) f.ps[u] = psi[at(d, L.col[k % AS], clamp_row(a.plo + k / AS, d.ny))];
+            if (k < ne) {
+                const int64_t m = at(d, L.col[k % AE + 1], a.elo + k / AE);
+                f.ux[u] = ux[m];
+                f.uy[u] = uy[m];
+                f.pux[u] = s.pux[m];
+                f.puy[u] = s.puy[m];
+                f.md[u] = md[m];
+            }
+        }
+    };
+    fetch(-1);
+    for (int t = -1;; t++) {
+        const SPass a = s_pass(d, jb, je, t);
+        const int b = a.b;
+        if (b >= je) break;
+        const int np = (a.phi - a.plo) * AS, ne = (a.ehi - a.elo) * AE;
 #pragma unroll
-            for (int dx = -1; dx <= 1; dx++) v[dy + 1][dx + 1] = lps[(ry + 1 + dy) * QX2 + rx + 1 + dx];
-        R Ax, Ay;
-        a_term<R>(d, v, ux[m], uy[m], s.pux[m], s.puy[m], Ax, Ay);
-        ring[k] = FIn<R>{v[1][1], ux[m], uy[m], Ax, Ay, md[m]};
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k < np) {
+                const int y = a.plo + k / AS;
+                L.ps[slot6(y, jb) * AS + k % AS] = ghost_fix<GWET, R>(f.ps[u], d, y);
+            }
+        }
+        __syncthreads();
+        // this pass's streamed node (row b + wv, column i0 + lane): the nine values its pulls
+        // read, its mdot and f_s
+        const int j = b + wv, i = i0 + lane;
+        const bool gv = t >= 0 && j < je && i < d.nx;
+        R hv[9], mdn = R(0), fsn = R(0);
+        if (gv) {
+            const int64_t n = at(d, i, j);
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                const int jj = j - QY[q];
+                const int64_t k = (jj < 0 || jj >= d.ny) ? QOPP[q] * d.plane + n
+                                                         : q * d.plane + at(d, wrapx(i - QX[q], d.nx), jj);
+                if constexpr (H) hv[q] = (R)((const half_t*)fsrc)[k];
+                else hv[q] = fsrc[k];
+            }
+            mdn = md[n];
+            fsn = s.fs[sp][n];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k >= ne) break;
+            const int y = a.elo + k / AE, c = k % AE;
+            R v[3][3];
+            rows3(L.ps + slot6(y - 1, jb) * AS, L.ps + slot6(y, jb) * AS, L.ps + slot6(y + 1, jb) * AS, c + 1, v);
+            R Ax, Ay;
+            a_term<R>(d, v, f.ux[u], f.uy[u], f.pux[u], f.puy[u], Ax, Ay);
+            const int o = slot6(y, jb) * AE + c;
+            L.in[0][o] = v[1][1];
+            L.in[1][o] = f.ux[u];
+            L.in[2][o] = f.uy[u];
+            L.in[3][o] = Ax;
+            L.in[4][o] = Ay;
+            L.in[5][o] = f.md[u];
+        }
+        __syncthreads();
+        if (b + WR < je) fetch(t + 1);
+        if (gv) {
+            const int c = lane + 1;
+            const int rm = slot6(j - 1, jb) * AE, r0 = slot6(j, jb) * AE, rp = slot6(j + 1, jb) * AE;
+            auto nbr = [&](int q) -> FIn<R> {
+                const int row = QY[q] > 0 ? rm : (QY[q] < 0 ? rp : r0);
+                return fin_at(L, row + c - QX[q]);
+            };
+            mx = fmaxf(mx, f_stream_at<R, H>(d, s, sp, i, j, fin_at(L, r0 + c), nbr, hv, hs, mdn, fsn));
+        }
     }
-    __syncthreads();
-    if constexpr (H) {
-        const H16Scales hs = h16_scales(s.ctl, PS_F, sp);
-        h16_note_max(&s.ctl->hmax[PS_F][sp ^ 1], f_collide_stream<R, true>(d, s, sp, tile, ring, hs));
-    } else {
-        f_collide_stream<R>(d, s, sp, tile, ring);
-    }
+    if constexpr (H) h16_note_max(&s.ctl->hmax[PS_F][sp ^ 1], mx);
 }
 // fin = 1: one extra block finishes the previous step's liquid-volume sum and freezing-time
 // detector meanwhile (a launch less per step; its fields of the control block are not the
@@ -811,7 +947,7 @@ __device__ __forceinline__ bool stop_recompute(const Ctl* c) {
 // the one-workgroup test kernels).
 template <int M, typename R, int NW = NT / 64, int U = 2>
 __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh) {
-    int nbt = d.tbx * d.tby, nb = d.gx * d.gy;
+    int nbt = d.tbx * d.tby, nb = part_nb(d);
     const double* pv = s.partials + part_sweep(nb, nbt, a.prev_slot);
     double acc[2 * M];
 #pragma unroll
@@ -1026,7 +1162,7 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
         }
         // block sums of the 2M parked values: G threads per value, each adding a fixed
         // strided subset, then a butterfly over the G lanes (a fixed order: reproducible)
-        double* pw = s.partials + part_sweep(d.gx * d.gy, nbt, a.slot);
+        double* pw = s.partials + part_sweep(part_nb(d), nbt, a.slot);
         constexpr int G0 = NTH / (2 * M), G = G0 < 64 ? G0 : 64;
         __syncthreads();
         const int t = threadIdx.x;
@@ -1180,9 +1316,6 @@ __global__ void k_ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) 
 // first pass of a segment evaluates anything twice.  WX + 2 = 64: one wave per row of
 // collision inputs.
 
-constexpr int WX = 62, WE = WX + 2, WS = WX + 4, WQ = WX + 6, WR = 4;
-static_assert(WE == 64 && NT == 64 * WR, "one wave per window row");
-
 template <typename R>
 struct HWin {
     R ps[8 * WQ], fs[8 * WQ], rho[8 * WQ];  // row y at slot (y - jb) & 7
@@ -1201,17 +1334,6 @@ template <typename R>
 __device__ __forceinline__ void hin_put(HWin<R>& L, int o, const HIn<R>& a) {
     L.in[0][o] = a.p; L.in[1][o] = a.rho; L.in[2][o] = a.ux; L.in[3][o] = a.uy; L.in[4][o] = a.S;
     L.in[5][o] = a.Ftx; L.in[6][o] = a.Fty; L.in[7][o] = a.Gx; L.in[8][o] = a.Gy; L.in[9][o] = a.om;
-}
-
-// v[dy+1][dx+1] = row_{dy}[c + dx], rows r0, r1, r2 = y - 1, y, y + 1.
-template <typename T, typename U>
-__device__ __forceinline__ void rows3(const T* r0, const T* r1, const T* r2, int c, U (&v)[3][3]) {
-#pragma unroll
-    for (int dx = -1; dx <= 1; dx++) {
-        v[0][dx + 1] = r0[c + dx];
-        v[1][dx + 1] = r1[c + dx];
-        v[2][dx + 1] = r2[c + dx];
-    }
 }
 
 // S = rho mdot + u . grad(rho) at a node with mass source md and velocity (ux, uy); vr is
@@ -1341,29 +1463,6 @@ __device__ __forceinline__ float h_stream_at(const Dev& d, const State<R>& s, in
     }
     return mx;
 }
-
-// Column c (any integer) wrapped onto the periodic grid.
-__device__ __forceinline__ int wrap_col(int c, int nx) {
-    c %= nx;
-    return c < 0 ? c + nx : c;
-}
-
-// A field's value at row y in [-1, ny] from the value `raw` stored at row min(max(y, 0), ny - 1)
-// of the same column: ghosted() split into its read and its ghost rule.
-template <int G, typename R>
-__device__ __forceinline__ R ghost_fix(R raw, const Dev& d, int y) {
-    if (y < 0) {
-        if (G == GWET) return raw + R(d.wet) * raw * (R(1) - raw);
-        if (G == GPHI) return R(2.0 * d.phi_bot) - raw;
-        return raw;
-    }
-    if (y >= d.ny) {
-        if (G == GPHI) return R(2.0 * d.phi_top) - raw;
-        return raw;
-    }
-    return raw;
-}
-__device__ __forceinline__ int clamp_row(int y, int ny) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); }
 
 // Rows of pass t of a window (segment rows [jb, je)): psi, f_s, rho rows [qlo, qhi); p, phi,
 // epsilon, S rows [plo, phi); collision inputs rows [elo, ehi); streamed rows b .. b + 3.
@@ -1564,104 +1663,182 @@ __global__ void __launch_bounds__(NT) k_h_fused(Dev d, State<R> s, int sp, int l
 }
 
 template <typename R>
-__device__ __forceinline__ GIn<R> g_inputs(const Dev& d, const State<R>& s, int sp, int64_t m) {
-    R ps = s.psi[sp ^ 1][m];
-    R fsn = s.fs[sp][m];
+__device__ __forceinline__ GIn<R> g_inputs(const Dev& d, R ps, R fsn, R T, R Hn, R ux, R uy, R md) {
     R C = mix<R>(d.C_s, d.C_l, d.C_g, ps, fsn);
     R k = mix<R>(d.k_s, d.k_l, d.k_g, ps, fsn);
-    R T = s.T[sp][m];
-    return GIn<R>{s.H[sp][m], T, C, s.ux[sp ^ 1][m], s.uy[sp ^ 1][m],
-                  R(1) / (k / (R(d.Cref) * R(CS2)) + R(0.5)), C * T * s.md[sp][m]};
+    return GIn<R>{Hn, T, C, ux, uy, R(1) / (k / (R(d.Cref) * R(CS2)) + R(0.5)), C * T * md};
 }
 
 // Stage 4: g pulled and collided at its source; substrate anti-bounce-back at T_w,
 // adiabatic top; H^{n+1} = sum g + Q/2 (Eq. (30)); Eq. (7) gives T, f_l; new f_s
 // and mdot.  Per-block FP64 liquid volume for the freezing-time detector.
+// One pass over a window (see AX): the collision inputs of g one row ahead (AE columns, from
+// point values read during the previous pass's streaming), then the streaming of rows
+// b .. b + 3 with the pulls read before the inputs are evaluated.
+template <typename R>
+struct GWin {
+    R in[7][6 * AE];  // collision inputs member by member (GIn order), row y at slot slot6(y, jb)
+    int col[AS];
+};
+template <typename R>
+__device__ __forceinline__ GIn<R> gin_at(const GWin<R>& L, int o) {
+    return GIn<R>{L.in[0][o], L.in[1][o], L.in[2][o], L.in[3][o], L.in[4][o], L.in[5][o], L.in[6][o]};
+}
 template <typename R, bool H = false>
 __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int sp, int tile) {
-    __shared__ GIn<R> ring[RN];
-    stage_ring(d, tile, ring, [&](int64_t m) { return g_inputs<R>(d, s, sp, m); });
+    __shared__ GWin<R> L;
+    const int i0 = (tile % d.gx) * AX, jb = (tile / d.gx) * d.hseg;
+    const int je = min(jb + d.hseg, d.ny);
+    for (int c = threadIdx.x; c < AS; c += NT) L.col[c] = wrap_col(i0 - 2 + c, d.nx);
     H16Scales hs{};
     if constexpr (H) hs = h16_scales(s.ctl, PS_G, sp);
     float mx = 0.f;
-    int i, j;
-    node_of(d, tile, i, j);
     double vl = 0.0;
-    if (i < d.nx && j < d.ny) {
-        int64_t n = at(d, i, j);
-        const R* gsrc = s.g[sp];
-        R* gdst = s.g[sp ^ 1];
-        const R Cref = R(d.Cref);
-        auto src = [&](int q, int64_t m, const GIn<R>& a) -> R {
-            if constexpr (H) return h16_get((const half_t*)gsrc, q * d.plane + m, g_rest<R>(q, a.H, a.T, Cref), hs.inv);
-            else return gsrc[q * d.plane + m];
-        };
-        const int me = ring_self();
-        const GIn<R> self = ring[me];
-        R sum = R(0), g0 = R(0);
-        R vals[H ? 9 : 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const R* gsrc = s.g[sp];
+    R* gdst = s.g[sp ^ 1];
+    const R Cref = R(d.Cref);
+    constexpr bool based = std::is_same<R, float>::value;
+    __syncthreads();  // L.col
+    struct Fetch {
+        R ps[2], fs[2], T[2], Hn[2], ux[2], uy[2], md[2];
+    } f;
+    auto fetch = [&](int t) {
+        const SPass a = s_pass(d, jb, je, t);
+        const int ne = (a.ehi - a.elo) * AE;
 #pragma unroll
-        for (int q = 0; q < 9; q++) {
-            int jj = j - QY[q];
-            int o = QOPP[q];
-            R val;
-            if (jj < 0) {
-                val = -coll_g<R>(o, src(o, n, self), self, Cref) + R(2.0 * QW[q] * d.Cref * d.T_w);
-            } else if (jj >= d.ny) {
-                val = coll_g<R>(o, src(o, n, self), self, Cref);
-            } else {
-                int64_t m = at(d, wrapx(i - QX[q], d.nx), jj);
-                const GIn<R>& a = ring[ring_from(me, QX[q], QY[q])];
-                val = coll_g<R>(q, src(q, m, a), a, Cref);
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k < ne) {
+                const int64_t m = at(d, L.col[k % AE + 1], a.elo + k / AE);
+                f.ps[u] = s.psi[sp ^ 1][m];
+                f.fs[u] = s.fs[sp][m];
+                f.T[u] = s.T[sp][m];
+                f.Hn[u] = s.H[sp][m];
+                f.ux[u] = s.ux[sp ^ 1][m];
+                f.uy[u] = s.uy[sp ^ 1][m];
+                f.md[u] = s.md[sp][m];
             }
-            if (q == 0) g0 = val;
-            if constexpr (H) vals[q] = val;
-            else gdst[q * d.plane + n] = val;
-            sum += val;
         }
-        R Hn = sum + R(0.5) * self.Q;
-        R ps = s.psi[sp ^ 1][n];
-        constexpr bool based = std::is_same<R, float>::value;
-        R hb = based ? s.hb[n] : R(0);
-        R T, fl;
-        invert<R>(d, Hn, hb, ps, T, fl);
-        if (based) {
-            // move the base to the new psi: rest link and H re-expressed exactly (the
-            // product is rounded on its own, as in the inversion)
-#pragma clang fp contract(off)
-            R hn = clamp01(ps) * R(d.Lvol);
-            R shift = hb - hn;
-            if constexpr (H) vals[0] = g0 + shift;
-            else gdst[n] = g0 + shift;
-            Hn = Hn + shift;
-            s.hb[n] = hn;
-        }
-        if constexpr (H) {
-            // deviations from the equilibrium of the H and T stored beside them
+    };
+    fetch(-1);
+    for (int t = -1;; t++) {
+        const SPass a = s_pass(d, jb, je, t);
+        const int b = a.b;
+        if (b >= je) break;
+        // this pass's streamed node (row b + wv, column i0 + lane): the nine values its pulls
+        // read and its own fields
+        const int j = b + wv, i = i0 + lane;
+        const bool gv = t >= 0 && j < je && i < d.nx;
+        R hv[9], ps1 = R(0), hb = R(0), ps0 = R(0), ux0 = R(0), uy0 = R(0), fs0 = R(0);
+        if (gv) {
+            const int64_t n = at(d, i, j);
 #pragma unroll
             for (int q = 0; q < 9; q++) {
-                const float dv = vals[q] - g_rest<R>(q, Hn, T, Cref);
-                mx = fmaxf(mx, fabsf(dv));
-                h16_put((half_t*)gdst, q * d.plane + n, dv, hs.sc);
+                const int jj = j - QY[q];
+                const int64_t k = (jj < 0 || jj >= d.ny) ? QOPP[q] * d.plane + n
+                                                         : q * d.plane + at(d, wrapx(i - QX[q], d.nx), jj);
+                if constexpr (H) hv[q] = (R)((const half_t*)gsrc)[k];
+                else hv[q] = gsrc[k];
             }
+            ps1 = s.psi[sp ^ 1][n];
+            if (based) hb = s.hb[n];
+            ps0 = s.psi[sp][n];
+            ux0 = s.ux[sp][n];
+            uy0 = s.uy[sp][n];
+            fs0 = s.fs[sp][n];
         }
-        R fsn = clamp01(ps) * (R(1) - fl);
-        // (psi u)^n for the next step's A (its readers in this step have all run)
-        const R pn = s.psi[sp][n];
-        s.pux[n] = pn * s.ux[sp][n];
-        s.puy[n] = pn * s.uy[sp][n];
-        s.H[sp ^ 1][n] = Hn;
-        s.T[sp ^ 1][n] = T;
-        s.fl[n] = fl;
-        s.md[sp ^ 1][n] = R(d.shrink) * (fsn - s.fs[sp][n]);
-        s.fs[sp ^ 1][n] = fsn;
-        vl = (double)(clamp01(ps) * fl);
+        const int ne = (a.ehi - a.elo) * AE;
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int k = threadIdx.x + u * NT;
+            if (k >= ne) break;
+            const GIn<R> g = g_inputs<R>(d, f.ps[u], f.fs[u], f.T[u], f.Hn[u], f.ux[u], f.uy[u], f.md[u]);
+            const int o = slot6(a.elo + k / AE, jb) * AE + k % AE;
+            L.in[0][o] = g.H;
+            L.in[1][o] = g.T;
+            L.in[2][o] = g.C;
+            L.in[3][o] = g.ux;
+            L.in[4][o] = g.uy;
+            L.in[5][o] = g.om;
+            L.in[6][o] = g.Q;
+        }
+        __syncthreads();
+        if (b + WR < je) fetch(t + 1);
+        if (gv) {
+            const int64_t n = at(d, i, j);
+            const int c = lane + 1;
+            const int rm = slot6(j - 1, jb) * AE, r0 = slot6(j, jb) * AE, rp = slot6(j + 1, jb) * AE;
+            const GIn<R> self = gin_at(L, r0 + c);
+            R sum = R(0), g0 = R(0);
+            R vals[H ? 9 : 1];
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                int jj = j - QY[q];
+                int o = QOPP[q];
+                R val;
+                if (jj < 0) {
+                    R raw = hv[q];
+                    if constexpr (H) raw = g_rest<R>(o, self.H, self.T, Cref) + raw * hs.inv;
+                    val = -coll_g<R>(o, raw, self, Cref) + R(2.0 * QW[q] * d.Cref * d.T_w);
+                } else if (jj >= d.ny) {
+                    R raw = hv[q];
+                    if constexpr (H) raw = g_rest<R>(o, self.H, self.T, Cref) + raw * hs.inv;
+                    val = coll_g<R>(o, raw, self, Cref);
+                } else {
+                    const int row = QY[q] > 0 ? rm : (QY[q] < 0 ? rp : r0);
+                    const GIn<R> an = gin_at(L, row + c - QX[q]);
+                    R raw = hv[q];
+                    if constexpr (H) raw = g_rest<R>(q, an.H, an.T, Cref) + raw * hs.inv;
+                    val = coll_g<R>(q, raw, an, Cref);
+                }
+                if (q == 0) g0 = val;
+                if constexpr (H) vals[q] = val;
+                else gdst[q * d.plane + n] = val;
+                sum += val;
+            }
+            R Hn = sum + R(0.5) * self.Q;
+            R T, fl;
+            invert<R>(d, Hn, hb, ps1, T, fl);
+            if (based) {
+                // move the base to the new psi: rest link and H re-expressed exactly (the
+                // product is rounded on its own, as in the inversion)
+#pragma clang fp contract(off)
+                R hn = clamp01(ps1) * R(d.Lvol);
+                R shift = hb - hn;
+                if constexpr (H) vals[0] = g0 + shift;
+                else gdst[n] = g0 + shift;
+                Hn = Hn + shift;
+                s.hb[n] = hn;
+            }
+            if constexpr (H) {
+                // deviations from the equilibrium of the H and T stored beside them
+#pragma unroll
+                for (int q = 0; q < 9; q++) {
+                    const float dv = vals[q] - g_rest<R>(q, Hn, T, Cref);
+                    mx = fmaxf(mx, fabsf(dv));
+                    h16_put((half_t*)gdst, q * d.plane + n, dv, hs.sc);
+                }
+            }
+            R fsn = clamp01(ps1) * (R(1) - fl);
+            // (psi u)^n for the next step's A (its readers in this step have all run)
+            s.pux[n] = ps0 * ux0;
+            s.puy[n] = ps0 * uy0;
+            s.H[sp ^ 1][n] = Hn;
+            s.T[sp ^ 1][n] = T;
+            s.fl[n] = fl;
+            s.md[sp ^ 1][n] = R(d.shrink) * (fsn - fs0);
+            s.fs[sp ^ 1][n] = fsn;
+            vl += (double)(clamp01(ps1) * fl);
+        }
+        __syncthreads();  // the next pass's inputs go into the rows this pass read
     }
     if constexpr (H) h16_note_max(&s.ctl->hmax[PS_G][sp ^ 1], mx);
     __shared__ double sh[NT / 64];
     double bv = block_sum(vl, sh);
-    if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + tile] = bv;
+    if (threadIdx.x == 0) s.partials[part_vl(part_nb(d)) + tile] = bv;
 }
+
 template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_g_stream(Dev d, State<R> s, int sp, int gate) {
     if (gate && !s.ctl->done) return;
@@ -1677,19 +1854,22 @@ __global__ void __launch_bounds__(NT) k_vl_finalize(Dev d, const double* partial
     vl_finalize_body(d, partials, c, mode, sh);
 }
 
-// Per-block liquid volume of the initial state (finalized by k_vl_finalize, mode 1).
+// Per-window liquid volume of the initial state (finalized by k_vl_finalize, mode 1), over the
+// windows of the g stage so that every liquid-volume sum has the same blocks.
 template <typename R>
 __device__ __forceinline__ void b_vl0(const Dev& d, const State<R>& s, int tile) {
-    int i, j;
-    node_of(d, tile, i, j);
+    const int i0 = (tile % d.gx) * AX, jb = (tile / d.gx) * d.hseg;
+    const int je = min(jb + d.hseg, d.ny);
+    const int lane = threadIdx.x & 63, i = i0 + lane;
     double vl = 0.0;
-    if (i < d.nx && j < d.ny) {
-        int64_t n = at(d, i, j);
-        vl = (double)(clamp01(s.psi[0][n]) * s.fl[n]);
-    }
+    if (i < d.nx)
+        for (int j = jb + (threadIdx.x >> 6); j < je; j += WR) {
+            const int64_t n = at(d, i, j);
+            vl += (double)(clamp01(s.psi[0][n]) * s.fl[n]);
+        }
     __shared__ double sh[NT / 64];
     double bv = block_sum(vl, sh);
-    if (threadIdx.x == 0) s.partials[part_vl(d.gx * d.gy) + tile] = bv;
+    if (threadIdx.x == 0) s.partials[part_vl(part_nb(d)) + tile] = bv;
 }
 template <typename R>
 __global__ void __launch_bounds__(NT) k_vl0(Dev d, State<R> s) {
@@ -1793,7 +1973,7 @@ __device__ __forceinline__ void b_diag(const Dev& d, const State<R>& s, int sp, 
     r[5] = block_max(v[5], sh);
     for (int k = 6; k < DIAG_N; k++) r[k] = block_sum(v[k], sh);
     if (threadIdx.x == 0) {
-        double* pw = s.partials + part_diag(d.gx * d.gy) + DIAG_N * (int64_t)tile;
+        double* pw = s.partials + part_diag(part_nb(d)) + DIAG_N * (int64_t)tile;
         for (int k = 0; k < DIAG_N; k++) pw[k] = r[k];
     }
 }
@@ -1806,7 +1986,7 @@ template <typename R>
 __global__ void __launch_bounds__(NT) k_diag_finalize(Dev d, State<R> s, int sp) {
     __shared__ double sh[NT / 64];
     int nb = d.gx * d.gy;
-    const double* pv = s.partials + part_diag(nb);
+    const double* pv = s.partials + part_diag(part_nb(d));
     double a[DIAG_N] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < nb; k += NT) {
         for (int m = 0; m < 5; m++) a[m] += pv[DIAG_N * k + m];
@@ -2007,8 +2187,8 @@ __global__ void __launch_bounds__(NT) kb_vl_finalize(const BatchCase<R>* __restr
     const Dev& d = bc.d;
     Ctl* c = bc.s.ctl;
     if (c->frozen) return;
-    int nb = d.gx * d.gy;
-    const double* pv = bc.s.partials + part_vl(nb);
+    const int nb = d.gx * d.hy;  // one partial per window of the g stage
+    const double* pv = bc.s.partials + part_vl(part_nb(d));
     double a = 0.0;
     for (int k = threadIdx.x; k < nb; k += NT) a += pv[k];
     a = block_sum(a, sh);
