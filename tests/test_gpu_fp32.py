@@ -5,11 +5,12 @@ CPU oracle.
 
 Bars.  Every field within 2e-5 (relative L2) of the oracle over the first 100 steps and on the
 full-size grid, freezing time within 0.5%, the Stefan strip within 2% of Neumann's front.
-Beyond 100 steps no per-field bar: one FP32 rounding per population and potential link per
-step, injected into the FP64 oracle itself, already drifts this problem by 3e-5 to 2e-4 after
-1000 steps (tests/golden/fp32_envelope_128x64.txt, written from the oracle alone), so no
-FP32-storage form can hold 2e-5 there; the thousand-step test prints the FP32 error beside that
-envelope and holds the integral outcomes (liquid and solid volume, sum psi, sweep counts)."""
+Beyond 100 steps 2e-5 cannot hold: one FP32 rounding per population and potential link per
+step, injected into the FP64 oracle itself, already drifts this problem by 4.6e-5 at step 400
+and 5.9e-4 at step 1000 (tests/golden/fp32_envelope_128x64.txt, written from the oracle alone,
+largest over four injection seeds).  The thousand-step test holds the FP32 error to a fixed
+multiple of that drift at every checkpoint, and the integral outcomes (liquid and solid volume,
+sum psi, sweep counts) to 1e-4 and 1%."""
 import math
 import os
 
@@ -22,6 +23,8 @@ from paper_2410_06657_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL32 = 2e-5
+# bar on the FP32 error relative to the oracle's own drift under one FP32 rounding per step
+ENV_RATIO = 30.0
 FIELDS = ["psi", "ux", "uy", "p", "T", "H", "fs", "phi"]
 ENVELOPE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp32_envelope_128x64.txt")
 
@@ -62,8 +65,11 @@ def envelope():
 
 def test_fp32_thousand_steps_128x64():
     """The 128 x 64 sessile drop, 1000 steps, FP32 against the FP64 oracle: 2e-5 per field up
-    to step 100; liquid and solid volume and sum psi within 1e-4 and the total sweep count
-    within 1% after 1000 steps; the per-field error printed beside the one-rounding envelope."""
+    to step 100; at every checkpoint the worst field within ENV_RATIO times the largest
+    one-rounding drift of the oracle itself (measured 6 to 19 times: the FP32 form leaves about
+    an order of magnitude more than one rounding per population and step, and its error then
+    grows with the problem's own response, not faster); liquid and solid volume and sum psi
+    within 1e-4 and the total sweep count within 1% after 1000 steps."""
     c = inputs.drop_128x64(0)
     g, o = solver32(c), ob.Oracle(c)
     env = envelope()
@@ -74,11 +80,12 @@ def test_fp32_thousand_steps_128x64():
         t = n
         e = errors(g, o)
         worst = max(e, key=e.get)
-        ev = env.get(n, {}).get(worst)
+        ev = max(env[n].values())
         print(f"step {n}: fp32 error {e[worst]:.2e} ({worst}); one-rounding drift of the oracle "
-              f"{ev if ev is None else f'{ev:.2e}'}", flush=True)
+              f"{ev:.2e} (ratio {e[worst] / ev:.1f})", flush=True)
         if n <= 100:
             assert e[worst] <= TOL32, (n, e)
+        assert e[worst] <= ENV_RATIO * ev, (n, e, ev)
     dg, do = g.diag(), o.diag()
     for k in ("V_l", "V_s", "sum_psi"):
         assert dg[k] == pytest.approx(do[k], rel=1e-4), k
