@@ -189,7 +189,7 @@ size_t carve(const Dev& d, char* base, State<R>* s, bool h16 = false) {
     t.hb = based ? c.take<R>(P) : nullptr;
     R** singles[] = {&t.usx[0], &t.usx[1], &t.usy[0], &t.usy[1], &t.pux, &t.puy, &t.oml, &t.fl};
     for (R** q : singles) *q = c.take<R>(P);
-    t.partials = c.take<double>((size_t)lbm::part_total(nb, nbt));
+    t.partials = c.take<double>((size_t)lbm::part_alloc(nb, nbt));
     t.ctl = c.take<Ctl>(1);
     if (s) *s = t;
     return round_up(c.off, ALIGN);
@@ -250,12 +250,14 @@ template <typename R>
 void launch_test(lbm_handle* h, const lbm::SweepLaunch& a, unsigned seq, bool publish = true) {
     State<R>& s = h->st<R>();
     unsigned long long* w = publish ? h->hword : nullptr;
-    switch (h->swm) {
-        case 1: lbm::k_sweep_test<1, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
-        case 2: lbm::k_sweep_test<2, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
-        case 4: lbm::k_sweep_test<4, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
-        default: lbm::k_sweep_test<8, R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, w, seq); break;
-    }
+    // range sums in parallel when there are enough tiles to share out
+    const int nbt = h->dev.tbx * h->dev.tby;
+    const int parts = std::min(lbm::TEST_RANGES, nbt / lbm::TEST_NT);
+    with_shape(h->swm, 4, [&](auto M, auto) {
+        if (parts > 1)
+            lbm::k_sweep_test_part<M(), R><<<parts, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a);
+        lbm::k_sweep_test<M(), R><<<1, lbm::TEST_NT, 0, h->stream>>>(h->dev, s, a, parts > 1 ? parts : 0, w, seq);
+    });
 }
 
 // Outcome of a loop test as published by k_sweep_test.
@@ -294,7 +296,7 @@ int wait_test(lbm_handle* h, unsigned seq, LoopState* out) {
 // Potential loop.  Sweeps go out in blocked launches of up to swm sweeps; an extra block of
 // each launch tests every sweep of the previous launch, and each batch of launches ends
 // with a one-block test of its last launch, after which the host reads the outcome.  The
-// first batch covers the previous solve's count, later batches double from one launch.
+// first batch covers the previous solve's count, later batches double from one sweep.
 // Launches queued after a test ended the loop exit at once.  If the final sweep is not
 // the last of its launch, that launch's sweeps up to it are recomputed from its input
 // (three buffers keep that input intact past the launches that follow it in the batch,
@@ -315,18 +317,21 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
     int next = 1;       // next sweep index
     int buf = h->lcur;  // buffer holding the state before sweep `next`
     const int lcur0 = h->lcur;
-    // first batch: enough launches for the previous solve's count, at most 256 (after a
-    // solve that stopped at its cap the count says little about the next one).  A stop in
-    // the batch's last launch is seen by the batch-end test; a stop earlier is seen only
-    // during the launch after it (the lagged test), which then ran in vain, so no spare
-    // launch is queued: a solve that needs more sweeps than the previous one pays a host
-    // round trip and one more launch instead
-    int nlaunch = h->kprev > 0 ? std::min(256, (h->kprev + h->swm - 1) / h->swm) : 1;
-    int grow = 1;
+    // Sweeps per batch.  A launch costs little more than the traffic of its first sweep (one
+    // read and one write of the links, halo included), so the plan avoids launches rather than
+    // sweeps that run in vain: the first batch covers exactly the previous solve's count,
+    // which changes by a sweep or two from one time step to the next.  A stop before the end
+    // of the batch's last launch costs the recomputation of the stopping launch (the lagged
+    // test in the launch after it sees a stop earlier in the batch); a solve that needs more
+    // costs a host round trip and a short launch: later batches double from one sweep.  A
+    // batch goes out as launches of up to swm sweeps; none straddles an FP32 rebase point.
+    const long long most = 256LL * h->swm;
+    long long budget = h->kprev > 0 ? std::min<long long>(h->kprev, most) : h->swm;
+    long long grow = 1;
     const bool rebasing = std::is_same<R, float>::value;
     for (;;) {
-        for (int c = 0; c < nlaunch && next <= max_sweeps; c++) {
-            // FP32 rebase points (the same sweep counts for every sweeps-per-launch choice):
+        for (int c = 0; budget > 0 && next <= max_sweeps; c++) {
+            // FP32 rebase points (every REBASE_SWEEPS sweeps, whatever the launch sizes):
             // inside a batch, the launch just queued is tested first (nothing published) and
             // the renormalisation and its constants run only if the loop goes on, so a rebase
             // costs no host round trip; at the start of a later batch the loop is known to go on
@@ -346,7 +351,9 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
             }
             lbm::SweepLaunch a{};
             int t = (int)plan.size();
-            a.nsw = std::min(h->swm, max_sweeps + 1 - next);
+            int nsw = (int)std::min<long long>(std::min<long long>(h->swm, budget), max_sweeps + 1 - next);
+            if (rebasing) nsw = std::min(nsw, lbm::REBASE_SWEEPS - (next - 1) % lbm::REBASE_SWEEPS);
+            a.nsw = nsw;
             a.src = buf;
             a.dst = (buf + 1) % 3;
             a.k0 = next;
@@ -359,7 +366,8 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
             }
             launch_sweep<R>(h, a);
             plan.push_back(a);
-            next += a.nsw;
+            next += nsw;
+            budget -= nsw;
             buf = a.dst;
         }
         lbm::SweepLaunch tst{};
@@ -386,8 +394,8 @@ int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* s
         int rc = wait_test(h, seq, &ls);
         if (rc) return rc;
         if (ls.done || next > max_sweeps) break;
-        nlaunch = grow;
-        grow = std::min(grow * 2, 256);
+        budget = grow;
+        grow = std::min(grow * 2, most);
     }
     if (!ls.done) {
         h->err = "potential loop ended without a decision";

@@ -70,6 +70,7 @@ struct Ctl {
     int done, count, conv;           // potential loop: finished, sweeps, converged
     int frozen;                      // batched runs to freezing: the case no longer advances
     int fix_launch, fix_n;           // launch holding the final sweep, and its sweeps up to it
+    int fix_k0, fix_nsw;             // that launch's first sweep and its sweep count
     int min_sweeps, max_sweeps;
     double tol, resid;
     double V_l0, V_prev, t_fre;      // freezing-time detector
@@ -89,6 +90,8 @@ struct Ctl {
 __device__ __forceinline__ void ctl_reset(Ctl* c, double tol, int min_sweeps, int max_sweeps) {
     c->fix_launch = 0;
     c->fix_n = 0;
+    c->fix_k0 = 0;
+    c->fix_nsw = 0;
     c->done = 0;
     c->count = 0;
     c->conv = 0;
@@ -110,6 +113,10 @@ __host__ __device__ constexpr int64_t part_sweep(int nb, int nbt, int slot) {
 }
 __host__ __device__ constexpr int64_t part_total(int nb, int nbt) {
     return (int64_t)(1 + DIAG_N) * nb + (int64_t)2 * SW_MAXM * 2 * nbt;
+}
+constexpr int TEST_RANGES = 64;  // range sums of the convergence test (see k_sweep_test_part)
+__host__ __device__ constexpr int64_t part_alloc(int nb, int nbt) {
+    return part_total(nb, nbt) + (int64_t)2 * SW_MAXM * TEST_RANGES;
 }
 
 template <typename R>
@@ -935,29 +942,26 @@ struct SweepLaunch {
 
 // Buffer of the stopping launch's input, and of the final state, for a loop that started
 // from buffer lcur0 (launch t reads buffer (lcur0 + t) mod 3 and writes the next one; a
-// recomputation writes the third).
+// recomputation writes the third).  The final sweep needs a recomputation unless it is the
+// last of its launch.
 __device__ __forceinline__ int stop_src(const Ctl* c, int lcur0) { return (lcur0 + c->fix_launch) % 3; }
-template <int M>
-__device__ __forceinline__ bool stop_recompute(const Ctl* c) {
-    const int k0 = c->fix_launch * M + 1;
-    return c->fix_n != min(M, c->max_sweeps + 1 - k0);
-}
+__device__ __forceinline__ bool stop_recompute(const Ctl* c) { return c->fix_n != c->fix_nsw; }
 
 // U: tiles fetched ahead (2 inside the sweep kernels, whose register budget it must fit; 4 in
 // the one-workgroup test kernels).
 template <int M, typename R, int NW = NT / 64, int U = 2>
-__device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh) {
+__device__ __forceinline__ void sweep_sums(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh,
+                                           int b0, int b1, double (&acc)[2 * M]) {
     int nbt = d.tbx * d.tby, nb = part_nb(d);
     const double* pv = s.partials + part_sweep(nb, nbt, a.prev_slot);
-    double acc[2 * M];
 #pragma unroll
     for (int m = 0; m < 2 * M; m++) acc[m] = 0.0;
     // U tiles' partials are fetched before any is added (one memory latency per U tiles, not
     // per tile); the additions keep the order b, b + NTH, ..., so the sums are bitwise those
     // of one tile at a time
     constexpr int NTH = 64 * NW;
-    int b = threadIdx.x;
-    for (; b + (U - 1) * NTH < nbt; b += U * NTH) {
+    int b = b0 + threadIdx.x;
+    for (; b + (U - 1) * NTH < b1; b += U * NTH) {
         double v[U][2 * M];
 #pragma unroll
         for (int u = 0; u < U; u++)
@@ -976,7 +980,7 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
                     acc[2 * m + 1] += v[u][2 * m + 1];
                 }
     }
-    for (; b < nbt; b += NTH)
+    for (; b < b1; b += NTH)
 #pragma unroll
         for (int m = 0; m < M; m++)
             if (m < a.prev_nsw) {
@@ -984,8 +988,10 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
                 acc[2 * m + 1] += pv[((int64_t)m * nbt + b) * 2 + 1];
             }
     block_sums_parked<2 * M, NTH>(acc, sh);
-    if (threadIdx.x != 0) return;
-    Ctl* c = s.ctl;
+}
+// The stopping rule on the summed residuals of the tested launch (thread 0 only).
+template <int M>
+__device__ __forceinline__ void sweep_decide(Ctl* c, const SweepLaunch& a, const double (&acc)[2 * M]) {
     for (int m = 0; m < a.prev_nsw && m < M; m++) {
         double da = acc[2 * m], pa = acc[2 * m + 1];
         double r = da == 0.0 ? 0.0 : (pa > 0.0 ? sqrt(da) / sqrt(pa) : INFINITY);
@@ -998,9 +1004,17 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
             c->done = 1;
             c->fix_launch = a.launch - 1;
             c->fix_n = m + 1;
+            c->fix_k0 = a.prev_k0;
+            c->fix_nsw = a.prev_nsw;
             break;
         }
     }
+}
+template <int M, typename R, int NW = NT / 64, int U = 2>
+__device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, const SweepLaunch& a, double* sh) {
+    double acc[2 * M];
+    sweep_sums<M, R, NW, U>(d, s, a, sh, 0, d.tbx * d.tby, acc);
+    if (threadIdx.x == 0) sweep_decide<M>(s.ctl, a, acc);
 }
 
 // The test of the previous launch (a.prev_*) is not made here: the launches carry extra
@@ -1022,10 +1036,10 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
     const Ctl* c = s.ctl;
     SweepLaunch a = ain;
     if (a.devfix) {
-        if (!c->done || !stop_recompute<M>(c)) return;
+        if (!c->done || !stop_recompute(c)) return;
         a.src = stop_src(c, ain.src);
         a.dst = (a.src + 2) % 3;
-        a.k0 = c->fix_launch * M + 1;
+        a.k0 = c->fix_k0;
         a.nsw = c->fix_n;
         a.force = 1;
         a.prev_nsw = 0;
@@ -1266,24 +1280,66 @@ __global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s, int gate) 
     b_sweep_prep<R>(d, s, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-// One block: the convergence test of the last launch of a batch (same rule as above).  256
-// threads: a 1024-thread block spent about 10 us on the reduction itself, at any tile count.
+// The convergence test of the last launch of a batch (same rule as above), in two launches:
+// TEST_RANGES blocks at most sum contiguous ranges of the tile partials (k_sweep_test_part),
+// then one block adds the range sums in order and decides (k_sweep_test; parts = 0: it sums
+// every tile itself).  256 threads a block: a 1024-thread block spent about 10 us on the
+// reduction itself, at any tile count.
 constexpr int TEST_NT = 256;
+__host__ __device__ constexpr int64_t part_test(int nb, int nbt) { return part_total(nb, nbt); }
+template <int M, typename R>
+__global__ void __launch_bounds__(TEST_NT) k_sweep_test_part(Dev d, State<R> s, SweepLaunch a) {
+    __shared__ double sh[2 * M * TEST_NT + 2 * M];
+    if (s.ctl->done) return;
+    const int nbt = d.tbx * d.tby, parts = gridDim.x;
+    const int b0 = (int)((int64_t)nbt * blockIdx.x / parts), b1 = (int)((int64_t)nbt * (blockIdx.x + 1) / parts);
+    double acc[2 * M];
+    sweep_sums<M, R, TEST_NT / 64, 4>(d, s, a, sh, b0, b1, acc);
+    if (threadIdx.x != 0) return;
+    double* out = s.partials + part_test(part_nb(d), nbt) + (int64_t)blockIdx.x * 2 * SW_MAXM;
+#pragma unroll
+    for (int m = 0; m < 2 * M; m++) out[m] = acc[m];
+}
 // The outcome is published to host memory the caller polls: two 64-bit words, each carrying
 // the sequence number `seq` in its upper half (the host waits for both), written with
 // system-scope atomic stores: word 0 = count, word 1 = fix_launch << 6 | fix_n << 2 |
 // conv << 1 | done.
 template <int M, typename R>
-__global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a,
+__global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a, int parts,
                                                         unsigned long long* word, unsigned seq) {
+    static_assert(TEST_RANGES <= TEST_NT, "the range sums fit the block's shared array");
     __shared__ double sh[2 * M * TEST_NT + 2 * M];
-    if (!s.ctl->done) sweep_test<M, R, TEST_NT / 64, 4>(d, s, a, sh);
+    if (!s.ctl->done) {
+        if (parts > 0) {
+            // range sums in block order: every thread stages a share of them in LDS (one
+            // memory latency), then thread v adds value v of every range
+            __shared__ double tot[2 * M];
+            const double* in = s.partials + part_test(part_nb(d), d.tbx * d.tby);
+            for (int k = threadIdx.x; k < parts * 2 * M; k += TEST_NT)
+                sh[k] = in[(int64_t)(k / (2 * M)) * 2 * SW_MAXM + k % (2 * M)];
+            __syncthreads();
+            if (threadIdx.x < 2 * M) {
+                double t = 0.0;
+                for (int b = 0; b < parts; b++) t += sh[b * 2 * M + threadIdx.x];
+                tot[threadIdx.x] = t;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double acc[2 * M];
+#pragma unroll
+                for (int m = 0; m < 2 * M; m++) acc[m] = tot[m];
+                sweep_decide<M>(s.ctl, a, acc);
+            }
+        } else {
+            sweep_test<M, R, TEST_NT / 64, 4>(d, s, a, sh);
+        }
+    }
     if (threadIdx.x != 0 || !word) return;  // no word: a test inside a batch, nothing published
     // a.src: the solve's first buffer; the stage kernels that follow a loop read its final
     // buffer from here
     if (s.ctl->done) {
         const int src = stop_src(s.ctl, a.src);
-        s.ctl->final_buf = stop_recompute<M>(s.ctl) ? (src + 2) % 3 : (src + 1) % 3;
+        s.ctl->final_buf = stop_recompute(s.ctl) ? (src + 2) % 3 : (src + 1) % 3;
     }
     const Ctl* c = s.ctl;
     const unsigned long long hi = (unsigned long long)seq << 32;
@@ -2170,6 +2226,8 @@ __global__ void kb_ctl_reset(const BatchCase<R>* __restrict__ cases, int ncases,
     Ctl* ct = cases[c].s.ctl;
     ct->fix_launch = 0;
     ct->fix_n = 0;
+    ct->fix_k0 = 0;
+    ct->fix_nsw = 0;
     ct->done = ct->frozen;  // a frozen case takes no part in the loop
     ct->count = 0;
     ct->conv = ct->frozen;
