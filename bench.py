@@ -423,9 +423,13 @@ def run_validation():
     return out
 
 
-def run_time_to_freeze(nbatch=8, max_steps=100000):
-    """Time to freeze (R30) of the 128 x 64 sessile drop (R0 = 24, theta = 90, R = 3, S = 1,
-    Ca_E = 0.1, Ste = 0.1): FP64, FP32, FP32 with FP16 population storage, FP64 with the learned warm start of the initial
+TTF_GRIDS = {"128x64": (128, 64, 24.0), "512x256": (512, 256, 96.0)}
+
+
+def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
+    """Time to freeze (R30) of a sessile drop (128 x 64 with R0 = 24, or the same drop four times
+    larger, 512 x 256 with R0 = 96; theta = 90, R = 3, S = 1, Ca_E = 0.1, Ste = 0.1): FP64,
+    FP32, FP32 with FP16 population storage, FP64 with the learned warm start of the initial
     potential, and `nbatch` seeds (centre jitter) in one FP32 batch against the same seeds one
     at a time.  Speedups are quoted with the freezing times they reach."""
     import torch
@@ -442,17 +446,21 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
             s = Solver(dict(case, skip_initial_solve=1), precision)
             s.warm_start(net, factor)
             s.solve_potential(case["poisson_tol"], case["poisson_max_sweeps"])
-        k = s.run_until_frozen(max_steps, 1)
+        k = s.run_until_frozen(max_steps, 20)  # t_fre is detected on the device; the host looks every 20 steps
         torch.cuda.synchronize()
         return time.perf_counter() - t0, s.diag()["t_fre"], k
 
-    c = inputs.drop_128x64(0)
-    out = {"workload": "128x64 sessile drop, R0=24, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"}
+    nx, ny, r0 = TTF_GRIDS[grid]
+    mk = lambda sd: inputs.sessile_drop(nx, ny, r0, 90.0, 3.0, 1.0, 0.1, 0.1, seed=sd)
+    c = mk(0)
+    out = {"workload": f"{grid} sessile drop, R0={r0:g}, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"}
     t64, f64, k64 = one(c, "fp64")
+    print(f"[bench] time to freeze {grid}: fp64 {t64:.2f}s ({k64} steps)", file=sys.stderr, flush=True)
     t32, f32, _ = one(c, "fp32")
+    print(f"[bench] time to freeze {grid}: fp32 {t32:.2f}s", file=sys.stderr, flush=True)
     t16, f16, _ = one(c, "fp16store")
-    f = warm.factor_for(64)
-    net = warm.load((128 // f) * (64 // f))
+    f = warm.factor_for(ny)
+    net = warm.load((nx // f) * (ny // f))
     tw, fw, _ = one(c, "fp64", net, f)
     out["fp64"] = {"wall_s": round(t64, 3), "t_fre": f64, "steps": k64}
     out["fp32"] = {"wall_s": round(t32, 3), "t_fre": f32, "t_fre_rel_diff": abs(f32 - f64) / f64,
@@ -463,7 +471,7 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
                         "speedup_vs_fp64": round(t64 / tw, 3)}
     print(f"[bench] time to freeze: fp64 {t64:.2f}s, fp32 {t32:.2f}s, fp16 storage {t16:.2f}s, warm {tw:.2f}s",
           file=sys.stderr, flush=True)
-    cases = [inputs.drop_128x64(sd) for sd in range(nbatch)]
+    cases = [mk(sd) for sd in range(nbatch)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b = Batch(cases, precision="fp32")
@@ -473,10 +481,11 @@ def run_time_to_freeze(nbatch=8, max_steps=100000):
     fb = [d["t_fre"] for d in b.diag()]
     del b
     ts, fs = 0.0, []
-    for case in cases:
+    for k, case in enumerate(cases):
         dt, fr, _ = one(case, "fp32")
         ts += dt
         fs.append(fr)
+        print(f"[bench] time to freeze: seed {k} alone {dt:.2f}s", file=sys.stderr, flush=True)
     out["batched_fp32"] = {"cases": nbatch, "wall_s": round(tb, 3), "one_at_a_time_wall_s": round(ts, 3),
                            "speedup_vs_one_at_a_time": round(ts / tb, 3),
                            "t_fre_rel_diff_vs_fp64_seed0": abs(fb[0] - f64) / f64,
@@ -550,6 +559,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--no-time-to-freeze", action="store_true", help="skip the time-to-freeze runs")
+    ap.add_argument("--time-to-freeze-grid", default="128x64", choices=sorted(TTF_GRIDS),
+                    help="drop of the time-to-freeze runs (512x256: the same drop four times larger)")
+    ap.add_argument("--time-to-freeze-only", action="store_true",
+                    help="print only the time-to-freeze runs as one JSON object")
     ap.add_argument("--no-validation", action="store_true", help="skip the validation problems")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--batched-cap", type=int, default=2000,
@@ -566,6 +579,10 @@ def main():
 
     if args.nn_probe:
         nn_probe()
+        return
+    if args.time_to_freeze_only:
+        print(json.dumps(finite_or_null(run_time_to_freeze(grid=args.time_to_freeze_grid)), allow_nan=False),
+              flush=True)
         return
     case, desc = workload(args.workload)
     case["sweep_block"] = args.sweep_block
@@ -613,7 +630,7 @@ def main():
                 k: float(np.linalg.norm(cur[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-300)) for k in ref}
             line["forms"][prec] = r
     if not args.no_time_to_freeze:
-        line["time_to_freeze"] = run_time_to_freeze()
+        line["time_to_freeze"] = run_time_to_freeze(grid=args.time_to_freeze_grid)
     if not args.no_validation:
         line["validation"] = run_validation()
     if not args.no_warm:
