@@ -54,6 +54,10 @@ MUTATIONS = {
         "-lt[(size_t)LOPP[q] * N + n] + 2 * LW[q] * p->phi_bot",
         "lt[(size_t)LOPP[q] * N + n] + 2 * LW[q] * p->phi_bot",
         lambda L: potential.check_linear_fixed_point(L)),
+    "top electrode anti-bounce-back sign (Sec. 3.4)": (
+        "-lt[(size_t)LOPP[q] * N + n] + 2 * LW[q] * p->phi_top",
+        "lt[(size_t)LOPP[q] * N + n] + 2 * LW[q] * p->phi_top",
+        lambda L: potential.check_alternating_sum(L)),
     "sign of the gradient-energy term of mu (Eq. (4))": (
         "- kap * lap;", "+ kap * lap;",
         lambda L: physics.check_laplace(L)),

@@ -76,3 +76,54 @@ def test_stop_rule_and_cap():
     assert rc == -2 and k == 3  # cap reached: not converged
     rc, k, r = o.solve_potential(-1.0, 5)
     assert rc == 0 and k == 5  # negative tolerance: fixed count
+
+
+def _checkerboard_sum(links):
+    """Q = sum over nodes of (-1)^(i+j) times the node's moving-link sum."""
+    ny, nx = links.shape[1:]
+    chk = (-1.0) ** (np.arange(ny)[:, None] + np.arange(nx)[None, :])
+    return float((chk * links[1:].sum(axis=0)).sum())
+
+
+def check_alternating_sum(L=None):
+    """Collision keeps each node's moving-link sum (phi is that sum over 1 - w_0), streaming
+    hands it to nodes of the other checkerboard colour and the electrode rule returns it to
+    the same node negated: so Q changes sign exactly every sweep, for any 1/tau_l field (here a
+    drop, sigma varying 3-fold) and any links.  With even nx the electrode sources cancel in Q."""
+    c = inputs.drop_128x64(0)
+    c.update(nx=32, ny=16, R0=6.0, xc=16.0)
+    o = Oracle(c, L=L)
+    rng = np.random.default_rng(3)
+    links = o.pop("l") + 1e-3 * rng.normal(size=(5, 16, 32))
+    o.set_pop("l", links)
+    q = _checkerboard_sum(o.pop("l"))
+    scale = float(np.abs(links[1:]).sum())
+    assert abs(q) > 1e-4 * scale / 32
+    for _ in range(6):
+        o.solve_potential(-1.0, 1)
+        q1 = _checkerboard_sum(o.pop("l"))
+        assert abs(q1 + q) <= 1e-13 * scale, (q, q1)
+        q = q1
+    return o, c
+
+
+def test_checkerboard_sum_alternates_every_sweep():
+    check_alternating_sum()
+
+
+def test_alternating_mode_never_decays():
+    """The mode Q carries is never damped, so links with Q != 0 hold the relative change above
+    any small tolerance for good, while the same links with Q projected out (a checkerboard of
+    amplitude Q / (4 N) taken from each moving link) converge to the rule."""
+    o, c = check_alternating_sum()
+    links = o.pop("l")
+    rc, k, r = o.solve_potential(1e-8, 20000)
+    assert rc == -2 and r > 1e-6
+    q = _checkerboard_sum(links)
+    chk = (-1.0) ** (np.arange(16)[:, None] + np.arange(32)[None, :])
+    fixed = links.copy()
+    fixed[1:] -= q / (4 * 16 * 32) * chk
+    assert abs(_checkerboard_sum(fixed)) < 1e-15 * np.abs(links).sum()
+    o.set_pop("l", fixed)
+    rc, k, r = o.solve_potential(1e-8, 20000)
+    assert rc == 0 and r <= 1e-8, (k, r)
