@@ -109,7 +109,8 @@ typedef struct lbm_params {
     int skip_initial_solve;     /* 1: lbm_init leaves the linear-ramp potential unsolved (sweep
                                    log entry 0) for the caller to seed (lbm_warm_start) and
                                    solve (lbm_solve_potential); 0: solve as in Algorithm 1.
-                                   Single-case handles only. */
+                                   A batch takes it when every case has the same value (then
+                                   lbm_batch_warm_start, lbm_batch_solve_potential). */
 } lbm_params;
 
 /* Scalar fields for lbm_get_field / lbm_set_field. */
@@ -360,8 +361,12 @@ const char* lbm_nn_last_error(const lbm_nn* nn);
 /* Coarse input maps of the handle's current state (device FP32, (ny/f) x (nx/f) x 3), the
    coarse target from its current potential ((ny/f) x (nx/f)), and the seeding of its
    current potential links and phi from a coarse deviation map (bilinear between cell
-   centres, periodic in x, clamped in y; links at their equilibria w_i phi).  Asynchronous on
-   the handle's stream. */
+   centres, periodic in x, clamped in y, taken at the centre of each pair of nodes (2k, 2k+1)
+   of a row so that both get the same value; links at their equilibria w_i phi).  The pairing
+   keeps the seed free of the sweeps' undamped alternating mode: the checkerboard sum of the
+   moving links, sum (-1)^(i+j) (l1 + l2 + l3 + l4), changes sign every sweep and never decays,
+   and a nonzero one would hold the relative change above the stopping rule for good.
+   Asynchronous on the handle's stream. */
 int lbm_nn_features(lbm_handle* h, int factor, float* x);
 int lbm_nn_target(lbm_handle* h, int factor, float* t);
 int lbm_nn_seed(lbm_handle* h, int factor, const float* y);
@@ -374,6 +379,16 @@ int lbm_warm_start(lbm_handle* h, lbm_nn* nn, int factor);
 int lbm_set_warm_start(lbm_handle* h, lbm_nn* nn, int factor);
 /* Training sample of case c of a batch: its input maps and target (device FP32).  Synchronises. */
 int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t);
+/* lbm_warm_start for every case of a batch, one after the other on the batch's stream: case c
+   uses the common divisor f_c of nx_c and ny_c that gives ny_c / f_c nearest coarse_rows coarse
+   rows (ties: the larger f_c); the network's pixel capacity must hold the largest coarse map
+   (LBM_EINVAL otherwise).  Follow with lbm_batch_solve_potential. */
+int lbm_batch_warm_start(lbm_batch* b, lbm_nn* nn, int coarse_rows);
+/* The potential solve of every case to its own stopping rule (poisson_tol, poisson_max_sweeps;
+   Sec. 3.4, R17), 1/tau_l first refreshed from the current psi and f_s, the loops in lockstep
+   launches as in lbm_batch_step; each case's count is appended to its sweep log and
+   *max_sweeps_done (may be NULL) gets the largest.  Synchronises. */
+int lbm_batch_solve_potential(lbm_batch* b, int* max_sweeps_done);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,7 @@ struct lbm_handle {
     int noconv = 0;
     int init_conv = 1;        // the initial potential solve met the stopping rule
     int kprev = 0;            // sweeps of the previous solve (first batch size)
+    int lbswap = 0;           // FP32: the carved base sets have traded places (State::lb, lbx)
     lbm_nn* wnn = nullptr;    // warm-start network used before every step's solve (or none)
     int wfactor = 0;
     Ctl* hctl = nullptr;      // pinned host mirror of the control block
@@ -184,6 +185,7 @@ size_t carve(const Dev& d, char* base, State<R>* s, bool h16 = false) {
     // the deviation bases exist only in the FP32 form
     const bool based = std::is_same<R, float>::value;
     t.lb = based ? c.take<R>(4 * P) : nullptr;
+    t.lbx = based ? c.take<R>(4 * P) : nullptr;
     t.dl = based ? c.take<R>(4 * P) : nullptr;
     t.pbp = based ? c.take<R>(P) : nullptr;
     t.hb = based ? c.take<R>(P) : nullptr;
@@ -306,8 +308,13 @@ template <typename R>
 int run_sweeps(lbm_handle* h, double tol, int min_sweeps, int max_sweeps, int* sweeps, double* resid,
                bool armed = false, const std::function<void()>* tail = nullptr) {
     if (std::is_same<R, float>::value) {
-        lbm::k_rebase<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), h->lcur, 0);
-        lbm::k_sweep_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, h->st<R>(), 0);
+        // renormalised pairs into the next potential buffer and the other base set
+        State<R>& s = h->st<R>();
+        const int lnew = (h->lcur + 1) % 3;
+        lbm::k_rebase_prep<R><<<h->nb, NT, 0, h->stream>>>(h->dev, s, h->lcur, lnew);
+        std::swap(s.lb, s.lbx);
+        h->lbswap ^= 1;
+        h->lcur = lnew;
     }
     // armed: an earlier kernel of the step already reset the loop with these tol/min/max
     if (!armed) lbm::k_ctl_reset<<<1, 1, 0, h->stream>>>(h->dctl, tol, min_sweeps, max_sweeps);
@@ -951,10 +958,10 @@ struct CkptHeader {
     double last_resid;
     uint64_t ws_bytes;
     uint64_t params_digest;  // of every lbm_params value: an image restores only into its own case
-    int32_t init_conv, pad;
+    int32_t init_conv, lbswap;
 };
 constexpr uint64_t CKPT_MAGIC = 0x4c424d434b505431ull;  // "LBMCKPT1"
-constexpr int32_t CKPT_VERSION = 3;
+constexpr int32_t CKPT_VERSION = 4;
 
 // FNV-1a over the values of every lbm_params member (not its padding bytes).
 uint64_t params_digest(const lbm_params& p) {
@@ -1010,6 +1017,7 @@ int lbm_checkpoint(lbm_handle* h, void* host, size_t* bytes) {
     hd.version = CKPT_VERSION;
     hd.params_digest = params_digest(h->prm);
     hd.init_conv = h->init_conv;
+    hd.lbswap = h->lbswap;
     hd.nx = h->dev.nx;
     hd.ny = h->dev.ny;
     hd.precision = h->prec;
@@ -1050,6 +1058,7 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
         return LBM_EINVAL;
     // buffer indices index the handle's plane tables: anything else is a corrupt image
     if (hd.sp < 0 || hd.sp > 1 || hd.lcur < 0 || hd.lcur > 2 || hd.kprev < 0 || hd.noconv < 0 || hd.step < 0 ||
+        hd.lbswap < 0 || hd.lbswap > 1 ||
         hd.params_digest != params_digest(h->prm))
         return LBM_EINVAL;
     const char* in = (const char*)host + sizeof hd;
@@ -1070,6 +1079,10 @@ int lbm_restore(lbm_handle* h, const void* host, size_t bytes) {
     h->step = hd.step;
     h->last_resid = hd.last_resid;
     h->init_conv = hd.init_conv;
+    if (hd.lbswap != h->lbswap) {  // the image's current base set is the handle's other one
+        std::swap(h->sf.lb, h->sf.lbx);
+        h->lbswap = hd.lbswap;
+    }
     h->spent = false;
     h->resid_stale = false;
     h->vl_pending = false;
@@ -1279,6 +1292,8 @@ struct lbm_batch {
     int* first_sw = nullptr;             // device: first sweep-grid block of each case
     int* lcur_d = nullptr;               // device: current potential buffer of each case
     int* lcur0_d = nullptr;              // device: buffer at the start of the running solve
+    int* run_idx_d = nullptr;            // device: cases whose loops run (see batch_running)
+    int* run_first_d = nullptr;          // device: their first sweep tiles in a launch
     double* tol_d = nullptr;
     int* maxsw_d = nullptr;
     lbm::SweepLaunch* fix_d = nullptr;
@@ -1286,6 +1301,8 @@ struct lbm_batch {
     Ctl* ctl_h = nullptr;                // pinned mirror
     int node_blocks = 0, sweep_blocks = 0, flow_blocks = 0, fg_blocks = 0;
     std::vector<int> lcur, kprev;
+    std::vector<int> run_idx_h, run_first_h;
+    int run_blocks = 0;
     std::vector<std::vector<int>> log;
     std::vector<int> frozen_sp;          // buffer parity of a frozen case's final state (-1: running)
     std::vector<int> init_conv;          // each case's initial solve met the stopping rule
@@ -1302,7 +1319,8 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> off;   // byte offset of each case's state
-    size_t table, first_node, first_flow, first_fg, first_sw, lcur, lcur0, tol, maxsw, fix, ctl, total;
+    size_t table, first_node, first_flow, first_fg, first_sw, lcur, lcur0, run_idx, run_first, tol, maxsw, fix, ctl,
+        total;
 };
 
 int batch_validate(int ncases, const lbm_params* cases) {
@@ -1312,7 +1330,8 @@ int batch_validate(int ncases, const lbm_params* cases) {
         if (rc) return rc;
         if (cases[c].precision == LBM_FP32_FP16STORE) return LBM_EINVAL;  // single-case form only
         if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]) ||
-            sweep_w(&cases[c]) != sweep_w(&cases[0]) || cases[c].skip_initial_solve)
+            sweep_w(&cases[c]) != sweep_w(&cases[0]) ||
+            cases[c].skip_initial_solve != cases[0].skip_initial_solve)
             return LBM_EINVAL;
     }
     return LBM_OK;
@@ -1336,6 +1355,8 @@ BatchLayout batch_layout(int ncases, const lbm_params* cases) {
     L.first_sw = take(sizeof(int) * ncases);
     L.lcur = take(sizeof(int) * ncases);
     L.lcur0 = take(sizeof(int) * ncases);
+    L.run_idx = take(sizeof(int) * ncases);
+    L.run_first = take(sizeof(int) * ncases);
     L.tol = take(sizeof(double) * ncases);
     L.maxsw = take(sizeof(int) * ncases);
     L.fix = take(sizeof(lbm::SweepLaunch) * ncases);
@@ -1360,24 +1381,52 @@ template <> std::vector<lbm::BatchCase<float>>& bcases<float>(lbm_batch* b) { re
 template <typename R>
 const lbm::BatchCase<R>* btable(lbm_batch* b) { return (const lbm::BatchCase<R>*)b->table; }
 
+// The loops still running (not done, not frozen) as the host last read the control blocks:
+// their case indices and first sweep tiles go to the device, and the batch's sweep launches
+// and tests cover only them (a batch whose other cases have converged launches no workgroups
+// for those).  The host vectors stay untouched until the stream has drained.
+template <typename R>
+int batch_running(lbm_batch* b, bool fresh) {
+    b->run_idx_h.clear();
+    b->run_first_h.clear();
+    int nb = 0;
+    for (int c = 0; c < b->ncases; c++) {
+        const bool running = b->frozen_sp[c] < 0 && (fresh || !b->ctl_h[c].done);
+        if (!running) continue;
+        b->run_idx_h.push_back(c);
+        b->run_first_h.push_back(nb);
+        nb += b->dev[c].tbx * b->dev[c].tby;
+    }
+    b->run_blocks = nb;
+    const int nr = (int)b->run_idx_h.size();
+    if (nr) {
+        BHIP(b, hipMemcpyAsync(b->run_idx_d, b->run_idx_h.data(), sizeof(int) * nr, hipMemcpyHostToDevice, b->stream));
+        BHIP(b, hipMemcpyAsync(b->run_first_d, b->run_first_h.data(), sizeof(int) * nr, hipMemcpyHostToDevice,
+                               b->stream));
+    }
+    return LBM_OK;
+}
+
 template <typename R>
 void batch_sweep(lbm_batch* b, int t) {
+    const int nr = (int)b->run_idx_h.size();
+    if (!nr) return;
     with_shape(b->swm, b->swv, [&](auto M, auto WV) {
-        // the tiles of every case, then one test block per case
-        lbm::kb_sweep<M, R, WV><<<b->sweep_blocks + b->ncases, 64 * WV, 0, b->stream>>>(
-            btable<R>(b), b->first_sw, b->ncases, b->lcur0_d, t);
+        // the tiles of every running case, then one test block per running case
+        lbm::kb_sweep<M, R, WV><<<b->run_blocks + nr, 64 * WV, 0, b->stream>>>(
+            btable<R>(b), b->run_first_d, nr, b->lcur0_d, t, b->run_idx_d);
     });
 }
 
 template <typename R>
 void batch_test(lbm_batch* b, int t) {
     auto tb = btable<R>(b);
-    switch (b->swm) {
-        case 1: lbm::kb_sweep_test<1, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-        case 2: lbm::kb_sweep_test<2, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-        case 4: lbm::kb_sweep_test<4, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-        default: lbm::kb_sweep_test<8, R><<<b->ncases, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t); break;
-    }
+    const int nr = (int)b->run_idx_h.size();
+    if (!nr) return;
+    with_shape(b->swm, 4, [&](auto M, auto) {
+        lbm::kb_sweep_test<decltype(M)::value, R><<<nr, lbm::TEST_NT, 0, b->stream>>>(tb, b->lcur0_d, t,
+                                                                                    b->run_idx_d);
+    });
 }
 
 template <typename R>
@@ -1404,6 +1453,8 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
     BHIP(b, hipMemcpyAsync(b->lcur0_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     lbm::kb_ctl_reset<R><<<(nc + 63) / 64, 64, 0, b->stream>>>(btable<R>(b), nc, b->tol_d, min_sweeps, b->maxsw_d);
     BHIP(b, hipGetLastError());
+    int rc = batch_running<R>(b, true);
+    if (rc) return rc;
     int kmax = *std::max_element(b->kprev.begin(), b->kprev.end());
     int maxmax = 0;
     for (auto& p : b->prm) maxmax = std::max(maxmax, p.poisson_max_sweeps);
@@ -1428,6 +1479,8 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
             b->err = "potential loops ended without a decision";
             return LBM_EHIP;
         }
+        rc = batch_running<R>(b, false);
+        if (rc) return rc;
         if (rebasing && t % reb == 0) {
             lbm::kb_rebase_running<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, nc,
                                                                             b->lcur0_d, t);
@@ -1548,10 +1601,15 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     lbm::kb_init<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
     lbm::kb_oml<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
     BHIP(b, hipGetLastError());
-    int rc = batch_sweeps<R>(b, 2);
-    if (rc) return rc;
     b->init_conv.assign(nc, 1);
-    for (int c = 0; c < nc; c++) b->init_conv[c] = b->ctl_h[c].conv;
+    if (b->prm[0].skip_initial_solve) {
+        // the caller seeds and solves the potentials (lbm_batch_warm_start, lbm_batch_solve_potential)
+        for (int c = 0; c < nc; c++) b->log[c].push_back(0);
+    } else {
+        int rc = batch_sweeps<R>(b, 2);
+        if (rc) return rc;
+        for (int c = 0; c < nc; c++) b->init_conv[c] = b->ctl_h[c].conv;
+    }
     lbm::kb_vl0<R><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, 0, b->lcur_d);
     lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 1);
     BHIP(b, hipGetLastError());
@@ -1576,6 +1634,15 @@ int batch_step_impl(lbm_batch* b) {
 }
 
 // Diagnostics and field reads reuse the single-case kernels on one case at a time.
+// Potential solve of every case to its own rule, in lockstep launches (tau_l from the current
+// psi and f_s first, as a step does after its f stage).
+template <typename R>
+int batch_solve(lbm_batch* b) {
+    lbm::kb_oml<R><<<b->node_blocks, NT, 0, b->stream>>>(btable<R>(b), b->first_node, b->ncases, b->sp, b->lcur_d);
+    BHIP(b, hipGetLastError());
+    return batch_sweeps<R>(b, 1);
+}
+
 template <typename R>
 int batch_case_handle(lbm_batch* b, int c, lbm_handle* h) {
     h->prm = b->prm[c];
@@ -1631,6 +1698,8 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
     b->first_sw = (int*)(ws + L.first_sw);
     b->lcur_d = (int*)(ws + L.lcur);
     b->lcur0_d = (int*)(ws + L.lcur0);
+    b->run_idx_d = (int*)(ws + L.run_idx);
+    b->run_first_d = (int*)(ws + L.run_first);
     b->tol_d = (double*)(ws + L.tol);
     b->maxsw_d = (int*)(ws + L.maxsw);
     b->fix_d = (lbm::SweepLaunch*)(ws + L.fix);
@@ -1751,6 +1820,22 @@ bool coarse_ok(const lbm_handle* h, int f) {
     return f >= 1 && h->dev.nx % f == 0 && h->dev.ny % f == 0;
 }
 
+// The common divisor f of nx and ny that gives ny / f nearest `rows` coarse rows (ties: the
+// larger f).
+int coarse_factor(int nx, int ny, int rows) {
+    int best = 1;
+    double err = 1e300;
+    for (int f = 1; f <= ny; f++) {
+        if (nx % f || ny % f) continue;
+        const double e = std::fabs((double)ny / f - rows);
+        if (e <= err) {
+            err = e;
+            best = f;
+        }
+    }
+    return best;
+}
+
 template <typename R>
 int nn_features(lbm_handle* h, int f, float* x) {
     int nc = (h->dev.nx / f) * (h->dev.ny / f);
@@ -1835,6 +1920,34 @@ int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t) {
     if (rc) b->err = h.err;
     h.hctl = nullptr;
     return rc;
+}
+
+int lbm_batch_warm_start(lbm_batch* b, lbm_nn* nnh, int coarse_rows) {
+    if (!b || !nnh) return LBM_ESTATE;
+    if (coarse_rows < 1) return LBM_EINVAL;
+    for (int c = 0; c < b->ncases; c++) {
+        lbm_handle h;
+        if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+        int rc = lbm_warm_start(&h, nnh, coarse_factor(h.dev.nx, h.dev.ny, coarse_rows));
+        h.hctl = nullptr;
+        if (rc) {
+            b->err = h.err;
+            return rc;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_solve_potential(lbm_batch* b, int* max_sweeps_done) {
+    if (!b) return LBM_ESTATE;
+    int rc = b->prec == LBM_FP32 ? batch_solve<float>(b) : batch_solve<double>(b);
+    if (rc) return rc;
+    if (max_sweeps_done) {
+        int k = 0;
+        for (int c = 0; c < b->ncases; c++) k = std::max(k, b->log[c].empty() ? 0 : b->log[c].back());
+        *max_sweeps_done = k;
+    }
+    return LBM_OK;
 }
 
 }  // extern "C"

@@ -537,6 +537,7 @@ struct State {
     R* md[2];
     R* phi[3];         // raw phi
     R* lb;             // 4 base planes of the FP32 potential links (unused in FP64)
+    R* lbx;            // FP32: the other base set (written by the solve-start renormalisation)
     R* dl;             // FP32: the 4 pulled base increments D of the current bases (see k_sweep_prep)
     R* pbp;            // FP32: the base potential phi_B = sum b / (1 - w_0)
     R* hb;             // enthalpy base of the FP32 rest link and H (unused in FP64)
@@ -1247,6 +1248,31 @@ __global__ void __launch_bounds__(NT) k_rebase(Dev d, State<R> s, int lcur, int 
 // D = C(y) - b(x), and at an electrode the anti-bounce-back remainder is D - A with
 // D = 2 w phi_wall - C_opp(x) - b(x).  D is formed in FP64 and rounded once (a small
 // difference of nearly equal bases).
+// node(dx, dy, b, om): the four link bases b[0..3] and omega of node (i + dx, j + dy), for the
+// four neighbours and the node itself.
+template <typename R, typename NodeAt>
+__device__ __forceinline__ void sweep_consts(const Dev& d, const State<R>& s, int i, int j, NodeAt&& node) {
+    const int64_t P = d.plane;
+    auto cq = [&](int q, int dx, int dy) -> double {  // C of link q at node (i + dx, j + dy)
+        double b[4], om;
+        node(dx, dy, b, om);
+        const double pb = ((b[0] + b[1]) + (b[2] + b[3])) * INV_1MW0;
+        const double bq = b[q - 1];
+        return bq - om * (bq - LWA * pb);
+    };
+    double b[4], om;
+    node(0, 0, b, om);
+    const int64_t n = at(d, i, j);
+    const double d1 = cq(1, -1, 0) - b[0];
+    const double d3 = cq(3, 1, 0) - b[2];
+    const double d2 = (j == 0 ? 2.0 * LWA * d.phi_bot - cq(4, 0, 0) : cq(2, 0, -1)) - b[1];
+    const double d4 = (j == d.ny - 1 ? 2.0 * LWA * d.phi_top - cq(2, 0, 0) : cq(4, 0, 1)) - b[3];
+    s.dl[n] = R(d1);
+    s.dl[P + n] = R(d2);
+    s.dl[2 * P + n] = R(d3);
+    s.dl[3 * P + n] = R(d4);
+    s.pbp[n] = R(((b[0] + b[1]) + (b[2] + b[3])) * INV_1MW0);
+}
 template <typename R>
 __device__ __forceinline__ void b_sweep_prep(const Dev& d, const State<R>& s, int tile) {
     if constexpr (!std::is_same<R, float>::value) return;  // FP64 keeps no bases
@@ -1254,25 +1280,63 @@ __device__ __forceinline__ void b_sweep_prep(const Dev& d, const State<R>& s, in
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     const int64_t P = d.plane;
-    auto cq = [&](int q, int ii, int jj) -> double {  // C of link q at node (ii, jj)
-        const int64_t m = at(d, ii, jj);
-        const double b1 = s.lb[m], b2 = s.lb[P + m], b3 = s.lb[2 * P + m], b4 = s.lb[3 * P + m];
-        const double pb = ((b1 + b2) + (b3 + b4)) * INV_1MW0;
-        const double om = (double)s.oml[m];
-        const double bq = q == 1 ? b1 : q == 2 ? b2 : q == 3 ? b3 : b4;
-        return bq - om * (bq - LWA * pb);
-    };
+    sweep_consts<R>(d, s, i, j, [&](int dx, int dy, double (&b)[4], double& om) {
+        const int64_t m = at(d, wrapx(i + dx, d.nx), j + dy);
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] = s.lb[q * P + m];
+        om = s.oml[m];
+    });
+}
+// FP32 form, at a solve's start: the renormalisation of k_rebase and the constants of
+// k_sweep_prep in one pass.  The renormalised pairs go to the idle potential buffer lnew and the
+// other base set s.lbx, so the pairs of the neighbours this pass reads stay those of buffer
+// lcur; a node's renormalised base is its pair's rounded sum (the high part of the two-sum),
+// staged with omega for the tile and its one-node ring in LDS, so the constants are those of
+// the two passes, bitwise.
+template <typename R>
+struct RebasedNode {
+    R b[4];
+    R om;
+};
+template <typename R>
+__device__ __forceinline__ void b_rebase_prep(const Dev& d, const State<R>& s, int lcur, int lnew, int tile) {
+#pragma clang fp contract(off)
+    if constexpr (!std::is_same<R, float>::value) return;  // FP64 keeps no bases
+    __shared__ RebasedNode<R> ring[RN];
+    const int64_t P = d.plane;
+    const R* l = s.l[lcur];
+    stage_ring(d, tile, ring, [&](int64_t m) {
+        RebasedNode<R> v;
+#pragma unroll
+        for (int q = 0; q < 4; q++) v.b[q] = s.lb[q * P + m] + l[q * P + m];
+        v.om = s.oml[m];
+        return v;
+    });
+    int i, j;
+    node_of(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
     const int64_t n = at(d, i, j);
-    const double b1 = s.lb[n], b2 = s.lb[P + n], b3 = s.lb[2 * P + n], b4 = s.lb[3 * P + n];
-    const double d1 = cq(1, wrapx(i - 1, d.nx), j) - b1;
-    const double d3 = cq(3, wrapx(i + 1, d.nx), j) - b3;
-    const double d2 = (j == 0 ? 2.0 * LWA * d.phi_bot - cq(4, i, j) : cq(2, i, j - 1)) - b2;
-    const double d4 = (j == d.ny - 1 ? 2.0 * LWA * d.phi_top - cq(2, i, j) : cq(4, i, j + 1)) - b4;
-    s.dl[n] = R(d1);
-    s.dl[P + n] = R(d2);
-    s.dl[2 * P + n] = R(d3);
-    s.dl[3 * P + n] = R(d4);
-    s.pbp[n] = R(((b1 + b2) + (b3 + b4)) * INV_1MW0);
+    R* lo_out = s.l[lnew];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        R b = s.lb[q * P + n], r = l[q * P + n];
+        R hi = b + r;
+        R bv = hi - b;
+        R lo = (b - (hi - bv)) + (r - bv);
+        s.lbx[q * P + n] = hi;
+        lo_out[q * P + n] = lo;
+    }
+    const int me = ring_self();
+    sweep_consts<R>(d, s, i, j, [&](int dx, int dy, double (&b)[4], double& om) {
+        const RebasedNode<R>& v = ring[ring_from(me, -dx, -dy)];
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] = v.b[q];
+        om = v.om;
+    });
+}
+template <typename R>
+__global__ void __launch_bounds__(NT) k_rebase_prep(Dev d, State<R> s, int lcur, int lnew) {
+    b_rebase_prep<R>(d, s, lcur, lnew, xcd_tile(blockIdx.x, gridDim.x));
 }
 template <typename R>
 __global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s, int gate) {
@@ -2173,23 +2237,28 @@ __device__ __forceinline__ SweepLaunch lockstep_launch(const Ctl* c, int lcur0, 
 
 template <int M, typename R, int WV>
 __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3))) kb_sweep(const BatchCase<R>* __restrict__ cases, const int* __restrict__ first,
-                                                    int ncases, const int* __restrict__ lcur0, int t) {
-    // the last ncases blocks test each case's previous launch while the others sweep (as
-    // in the single-case launch: the test is off the critical path)
+                                                    int ncases, const int* __restrict__ lcur0, int t,
+                                                    const int* __restrict__ idx) {
+    // The launch covers the ncases cases listed in idx (the loops still running when the
+    // batch of launches was queued; first: their first sweep tiles in the launch).  The last
+    // ncases blocks test each case's previous launch while the others sweep (as in the
+    // single-case launch: the test is off the critical path).
     const int ntiles = gridDim.x - ncases;
     __shared__ double shm[SWEEP_SHM<M, WV>];
     if ((int)blockIdx.x >= ntiles) {
-        const BatchCase<R>& bc = cases[blockIdx.x - ntiles];
-        SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x - ntiles], t);
+        const int c = idx[blockIdx.x - ntiles];
+        const BatchCase<R>& bc = cases[c];
+        SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t);
         if (a.nsw > 0 && a.prev_nsw > 0 && !bc.s.ctl->done) sweep_test<M, R, WV>(bc.d, bc.s, a, shm);
         return;
     }
     int b = xcd_tile(blockIdx.x, ntiles);
-    int c = find_case(first, ncases, b);
+    int cc = find_case(first, ncases, b);
+    const int c = idx[cc];
     const BatchCase<R>& bc = cases[c];
     SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t);
     if (a.nsw == 0) return;
-    b_sweep_tb<M, R, WV>(bc.d, bc.s, a, b - first[c], shm);
+    b_sweep_tb<M, R, WV>(bc.d, bc.s, a, b - first[cc], shm);
 }
 
 // Recomputation of each finished case's last launch up to its final sweep (fix[c].nsw = 0:
@@ -2209,11 +2278,13 @@ __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)
 // One block per case: test the case's launch t (the last of a batch).
 template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) kb_sweep_test(const BatchCase<R>* __restrict__ cases,
-                                                         const int* __restrict__ lcur0, int t) {
+                                                         const int* __restrict__ lcur0, int t,
+                                                         const int* __restrict__ idx) {
     __shared__ double sh[2 * M * TEST_NT + 2 * M];
-    const BatchCase<R>& bc = cases[blockIdx.x];
+    const int c = idx[blockIdx.x];
+    const BatchCase<R>& bc = cases[c];
     if (bc.s.ctl->done) return;
-    SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[blockIdx.x], t + 1);
+    SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t + 1);
     if (a.prev_nsw <= 0) return;
     sweep_test<M, R, TEST_NT / 64, 4>(bc.d, bc.s, a, sh);
 }
@@ -2321,7 +2392,14 @@ __device__ __forceinline__ void b_nn_seed(const Dev& d, const State<R>& s, int l
     node_of(d, tile, i, j);
     if (i >= d.nx || j >= d.ny) return;
     const int nxc = d.nx / f, nyc = d.ny / f;
-    const double X = (i + 0.5) / f - 0.5, Y = (j + 0.5) / f - 0.5;
+    // The sweeps conserve the moving links' sum at every node and carry it to a neighbour of
+    // the other colour of the checkerboard (a wall returns it negated to the same node), so
+    // Q = sum over nodes of (-1)^(i+j) (l1 + l2 + l3 + l4) changes sign every sweep whatever
+    // 1/tau_l is: a mode that never decays, and a seed with Q != 0 leaves a relative change
+    // that never meets the stopping rule.  The seed is therefore evaluated once per pair of
+    // nodes (2k, 2k+1) of a row, at the pair's centre: the two nodes get identical links
+    // and Q = 0 exactly for even nx (for odd nx the periodic rows have no such mode).
+    const double X = ((i & ~1) + 1.0) / f - 0.5, Y = (j + 0.5) / f - 0.5;
     const int i0 = (int)floor(X), j0 = (int)floor(Y);
     const double fx = X - i0, fy = Y - j0;
     const int ia = (i0 % nxc + nxc) % nxc, ib = (ia + 1) % nxc;

@@ -31,7 +31,8 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_nn_destroy", "lbm_nn_last_error", "lbm_nn_features", "lbm_nn_target", "lbm_nn_seed",
            "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample", "lbm_checkpoint", "lbm_restore",
            "lbm_run_until_frozen", "lbm_batch_run_until_frozen", "lbm_autotune_workspace_bytes",
-           "lbm_get_field_device", "lbm_nn_forward_noalloc", "lbm_time_stages", "lbm_stage_name"]
+           "lbm_get_field_device", "lbm_nn_forward_noalloc", "lbm_time_stages", "lbm_stage_name",
+           "lbm_batch_warm_start", "lbm_batch_solve_potential"]
 
 LBM_TUNE_FORCE = 1
 
@@ -154,6 +155,8 @@ def lib():
         L.lbm_run_until_frozen.argtypes = [vp, C.c_int, C.c_int, ip]
         L.lbm_batch_run_until_frozen.argtypes = [vp, C.c_int, ip]
         L.lbm_batch_nn_sample.argtypes = [vp, C.c_int, C.c_int, vp, vp]
+        L.lbm_batch_warm_start.argtypes = [vp, vp, C.c_int]
+        L.lbm_batch_solve_potential.argtypes = [vp, ip]
         _lib = L
     return _lib
 
@@ -478,6 +481,20 @@ class Batch:
         rc = lib().lbm_batch_run_until_frozen(self._h, int(max_steps), C.byref(k))
         if rc != LBM_OK:
             raise LbmError("lbm_batch_run_until_frozen", rc)
+        return k.value
+
+    def warm_start(self, net: "Net", coarse_rows: int = 32):
+        """Seed every case's potential from the network (lbm_batch_warm_start)."""
+        rc = lib().lbm_batch_warm_start(self._h, net._h, int(coarse_rows))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_warm_start", rc)
+
+    def solve_potential(self) -> int:
+        """Every case's potential solve to its own rule; returns the largest sweep count."""
+        k = C.c_int()
+        rc = lib().lbm_batch_solve_potential(self._h, C.byref(k))
+        if rc != LBM_OK:
+            raise LbmError("lbm_batch_solve_potential", rc)
         return k.value
 
     def nn_sample(self, c: int, factor: int):

@@ -35,6 +35,19 @@ def factor_for(ny: int) -> int:
     return ny // COARSE_ROWS
 
 
+def coarse_factor(nx: int, ny: int, rows: int = COARSE_ROWS) -> int:
+    """The common divisor f of nx and ny that gives ny / f nearest `rows` coarse rows (ties: the
+    larger f); the rule lbm_batch_warm_start applies to every case of a batch."""
+    best, err = 1, float("inf")
+    for f in range(1, ny + 1):
+        if nx % f or ny % f:
+            continue
+        e = abs(ny / f - rows)
+        if e <= err:
+            best, err = f, e
+    return best
+
+
 def training_cases(rng, count: int, ny: int = 128, deformed: bool = False) -> list:
     from . import inputs
     cases = []

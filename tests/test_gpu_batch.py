@@ -96,3 +96,30 @@ def test_batch_run_until_frozen_matches_single_runs():
             assert np.array_equal(b.field(c, name), s.field(name)), (c, name)
     print("freezing steps", steps, "batch steps", nb)
     assert nb == max(steps) and len(set(steps)) > 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_warm_start_equals_single_runs(precision):
+    """Cases initialised without a solve, seeded by the learned warm start in one batch call
+    (each with its own coarse factor) and solved to the stopping rule in lockstep, then stepped:
+    every case equals its single-case run with the same start, bitwise."""
+    from paper_2410_06657_amd import warm
+    from paper_2410_06657_amd.lbm import Batch, Solver
+    cases = [dict(c, skip_initial_solve=1) for c in mixed_cases() if c["nx"] > 4]
+    factors = [warm.coarse_factor(c["nx"], c["ny"]) for c in cases]
+    net = warm.load(max((c["nx"] // f) * (c["ny"] // f) for c, f in zip(cases, factors)))
+    b = Batch(cases, precision=precision)
+    b.warm_start(net)
+    kmax = b.solve_potential()
+    b.step(5)
+    for c, (case, f) in enumerate(zip(cases, factors)):
+        s = Solver(case, precision=precision)
+        s.warm_start(net, f)
+        s.solve_potential(case["poisson_tol"], case["poisson_max_sweeps"])
+        s.step(5)
+        assert list(b.sweep_log(c)) == list(s.sweep_log()), c
+        assert b.sweep_log(c)[1] <= kmax
+        for k in ("psi", "ux", "uy", "p", "T", "H", "fs", "phi"):
+            assert np.array_equal(b.field(c, k), s.field(k)), (c, k)
+        print(f"case {c} {case['nx']}x{case['ny']} factor {f}: equal, initial solve {int(s.sweep_log()[1])} sweeps",
+              flush=True)

@@ -130,12 +130,13 @@ def test_coarse_maps_and_seed():
     ramp = c["phi_bot"] + (c["phi_top"] - c["phi_bot"]) * (np.arange(64)[:, None] + 0.5) / 64
     t = s.nn_target(f).cpu().numpy()
     assert np.allclose(t, cells(phi - ramp) / (c["phi_top"] - c["phi_bot"]), atol=1e-6)
-    # seed from a known coarse map and read phi back: bilinear between cell centres
+    # seed from a known coarse map and read phi back: bilinear between cell centres, at the
+    # centre of each node pair (2k, 2k+1) of a row
     rng = np.random.default_rng(0)
     yc = rng.normal(0, 0.05, (64 // f, 128 // f)).astype(np.float32)
     s.nn_seed(f, torch.tensor(yc, device="cuda"))
     got = s.field("phi")
-    X = (np.arange(128) + 0.5) / f - 0.5
+    X = (2 * (np.arange(128) // 2) + 1.0) / f - 0.5
     Y = (np.arange(64) + 0.5) / f - 0.5
     i0 = np.floor(X).astype(int)
     j0 = np.floor(Y).astype(int)
@@ -148,6 +149,9 @@ def test_coarse_maps_and_seed():
     assert np.allclose(got, ramp + v * (c["phi_top"] - c["phi_bot"]), atol=1e-12)
     links = s.pop("l")
     assert np.allclose(links, np.broadcast_to(got / 6.0, links.shape), atol=1e-15)
+    # no component along the sweeps' alternating mode: the checkerboard sum of the links is 0
+    chk = (-1.0) ** (np.arange(64)[:, None] + np.arange(128)[None, :])
+    assert float((chk * links.sum(axis=0)).sum()) == 0.0
     # the sweeps then take over from the seeded state
     rc, k, r = s.solve_potential(1e-8, 200000)
     assert rc == 0 and k > 1 and math.isfinite(r)
