@@ -50,6 +50,7 @@ KERNEL_BYTES = {
 }
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernels_4096x2048_counters.md")
+BATCH_STAGE_ROWS = 32
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2410_06657_amd", "csrc", "lbm_kernels.hpp")
 
 
@@ -59,13 +60,14 @@ def kernel_source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel, precision, workload_name):
+def measured_traffic(kernel, precision, workload_name, shapes=None):
     """HBM bytes per launch of a kernel from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE passes scaled by a copy kernel's), or None when the summary is missing, covers
-    another workload, or was taken from a different kernel source."""
+    another workload, was taken from a different kernel source or with other launch shapes
+    (sweep block, sweep waves, stage rows)."""
     if workload_name != "4096x2048" or not os.path.exists(COUNTERS_FILE):
         return None
-    sha, table = None, {}
+    sha, table, taken = None, {}, {}
     with open(COUNTERS_FILE) as f:
         for line in f:
             parts = line.split()
@@ -73,9 +75,28 @@ def measured_traffic(kernel, precision, workload_name):
                 sha = parts[1]
             elif len(parts) >= 4 and parts[0] == "traffic_bytes_per_launch":
                 table[(parts[1], parts[2])] = int(parts[3])
+            elif len(parts) == 5 and parts[0] == "launch_shapes":
+                taken[parts[1]] = tuple(int(v) for v in parts[2:])
     if sha is None or sha != kernel_source_digest():
         return None
+    if shapes is not None and taken.get(precision) != shape_key(shapes):
+        return None
     return table.get((kernel, precision))
+
+
+def shape_key(shapes):
+    return (int(shapes["sweep_block"]), int(shapes["sweep_waves"]), int(shapes["stage_rows"]))
+
+
+def launch_shapes(case, precision, tune=True):
+    """Launch shapes for a grid and precision: the library's autotuner (timed here, not taken
+    from a file), or the library's defaults with tune=False."""
+    if not tune:
+        from paper_2410_06657_amd.lbm import launch_shapes as defaults
+        return defaults(case, precision)
+    from paper_2410_06657_amd.lbm import autotune
+    r = autotune(dict(case, poisson_max_sweeps=2000), precision, launches=10, persist=False)
+    return {"sweep_block": r["sweep_block"], "sweep_waves": r["sweep_waves"], "stage_rows": r["stage_rows"]}
 
 
 def workload(name):
@@ -142,13 +163,13 @@ def cpu_baseline(case, k_sweeps, budget_s=25.0):
             "step_s": step_s}
 
 
-def roofline_of(kernel, precision, n, seconds, workload_name, bytes_per_node, sweeps=None):
+def roofline_of(kernel, precision, n, seconds, workload_name, bytes_per_node, sweeps=None, shapes=None):
     """HBM roofline of one kernel launch: algorithmic bytes over its live average duration."""
     per_launch = bytes_per_node * n
     achieved = per_launch / seconds / 1e9
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": round(achieved / HBM_PEAK_GBS, 4),
-         "traffic": measured_traffic(kernel, precision, workload_name),
+         "traffic": measured_traffic(kernel, precision, workload_name, shapes),
          "kernel": kernel, "avg_launch_us": round(seconds * 1e6, 2),
          "algorithmic_bytes_per_launch": per_launch,
          "working_set_fits_infinity_cache": per_launch <= INFINITY_CACHE_BYTES}
@@ -174,13 +195,16 @@ def solver_converged(case, precision, net, factor, cap):
     return s, k, dt
 
 
-def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net, factor, init_cap):
+def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net, factor, init_cap, tune=True):
     """Time `steps` coupled steps of one precision form from a converged potential, then each
-    kernel of the step."""
+    kernel of the step, with the launch shapes the autotuner picks for this precision."""
     import numpy as np
     import torch
 
     n = case["nx"] * case["ny"]
+    shapes = launch_shapes(case, precision, tune)
+    print(f"[bench] {precision}: launch shapes {shapes}", file=sys.stderr, flush=True)
+    case = dict(case, **shapes)
     s, k_init, init_s = solver_converged(case, precision, net, factor, init_cap)
     s.step(warmup)
     torch.cuda.synchronize()
@@ -199,11 +223,11 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net,
           f"{capped} capped solves", file=sys.stderr, flush=True)
     fields = {k: s.field(k) for k in ("psi", "ux", "uy", "p", "T", "phi")}
     # the sweep kernel, timed with HIP events on the solver's stream over full launches
-    m = case.get("sweep_block") or 8
+    m = case["sweep_block"]
     launch_s = s.time_sweeps(sweep_launches * m) * 1e-3 / sweep_launches
-    sweep_kernel = f"k_sweep_tb<{m},{'double' if precision == 'fp64' else 'float'}>"
+    sweep_kernel = f"k_sweep_tb<{m}, {'double' if precision == 'fp64' else 'float'}, {case['sweep_waves']}, 1>"
     rooflines = {"k_sweep_tb": roofline_of("k_sweep_tb", precision, n, launch_s, workload_name,
-                                           SWEEP_COMPULSORY[precision], sweeps=m)}
+                                           SWEEP_COMPULSORY[precision], sweeps=m, shapes=shapes)}
     rooflines["k_sweep_tb"]["kernel"] = sweep_kernel
     rooflines["k_sweep_tb"]["bytes"] = "compulsory: one read and one write of the links and fields per launch"
     # the other kernels of the step (HIP events around back-to-back launches; leaves the state
@@ -211,7 +235,8 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net,
     stage_ms = s.time_stages(5)
     per_step = {"k_sweep_tb": kmean / m * launch_s * 1e3}
     for name, ms in stage_ms.items():
-        rooflines[name] = roofline_of(name, precision, n, ms * 1e-3, workload_name, KERNEL_BYTES[name][precision])
+        rooflines[name] = roofline_of(name, precision, n, ms * 1e-3, workload_name, KERNEL_BYTES[name][precision],
+                                      shapes=shapes)
         per_step[name] = ms
     stage_total = sum(stage_ms.values()) * 1e-3
     dominant = max(per_step, key=per_step.get)
@@ -232,6 +257,7 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net,
         "coupled_hbm_roofline_frac": round(coupled_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "initial_solve": {"sweeps": int(k_init), "seconds": round(init_s, 2), "start": "learned warm start",
                           "converged": True},
+        "launch_shapes": shapes,
         "roofline": rooflines[dominant], "rooflines": rooflines,
         "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"],
                   "op_resid_over_ramp": d["op_resid"] / d["op_resid_ramp"] if d["op_resid_ramp"] else None},
@@ -257,11 +283,17 @@ def run_batched(steps, warmup, seed=4, ncases=96, cap=400000):
     tune = autotune(dict(big, poisson_max_sweeps=2000), "fp32", launches=10, persist=False)
     shape = {"sweep_block": tune["sweep_block"], "sweep_waves": tune["sweep_waves"]}
     cases = [dict(c, poisson_max_sweeps=cap, skip_initial_solve=1, **shape) for c in cases]
+    # Stage segments: the library's default lowers a small grid's segment height until its own
+    # launch has 2048 workgroups; a batch has those many times over, so its cases take 32-row
+    # segments (less halo re-reading; 14% faster steps than the per-case default on this
+    # batch).  Each case alone keeps the default, which its autotuner finds within a few % of
+    # its best.
+    batch_cases = [dict(c, stage_rows=BATCH_STAGE_ROWS) for c in cases]
     nodes = sum(c["nx"] * c["ny"] for c in cases)
     factors = [warm.coarse_factor(c["nx"], c["ny"]) for c in cases]
     net = warm.load(max((c["nx"] // f) * (c["ny"] // f) for c, f in zip(cases, factors)))
     t0 = time.perf_counter()
-    b = Batch(cases, precision="fp32")
+    b = Batch(batch_cases, precision="fp32")
     b.warm_start(net)
     kinit = b.solve_potential()
     torch.cuda.synchronize()
@@ -307,6 +339,7 @@ def run_batched(steps, warmup, seed=4, ncases=96, cap=400000):
             "initial_solve": {"start": "learned warm start", "max_sweeps": kinit,
                               "batch_seconds": round(t_init, 2)},
             "dtype": "f32", "sweep_shape": shape,
+            "stage_rows": {"batched": BATCH_STAGE_ROWS, "one_at_a_time": "library default of each case"},
             "sweeps_total": sw_b, "sweeps_total_one_at_a_time": sw_s,
             "workload": "96 sessile drops, Ny~U{128..768 step 16}, Nx=2Ny, R0=0.3125Ny, "
                         "Ca_E~U[0,0.4], theta~U[45,135], R~logU[0.3,5], S~logU[0.5,3], Ste=0.1, seed 4"}
@@ -509,11 +542,12 @@ def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
     return out
 
 
-def counters_probe(case, launches=20):
+def counters_probe(case, launches=20, tune=True):
     """Short run for hardware-counter passes (rocprofv3 --pmc): a plain copy kernel of known
     size (the calibration of the byte counters), then `launches` blocked sweep launches and
-    three steps per precision (FP64, FP32, FP16 storage) on the workload's grid.  The initial potential solve is capped at 16 sweeps so
-    the run stays short; a launch's memory traffic does not depend on convergence."""
+    three steps per precision (FP64, FP32, FP16 storage) on the workload's grid, with the
+    launch shapes the benchmark takes (printed).  The initial potential solve is capped at 16
+    sweeps so the run stays short; a launch's memory traffic does not depend on convergence."""
     import torch
 
     from paper_2410_06657_amd.lbm import Solver
@@ -526,9 +560,12 @@ def counters_probe(case, launches=20):
     torch.cuda.synchronize()
     print(f"[counters] copy kernel: 3 x {nbytes} bytes read and written", file=sys.stderr, flush=True)
     del src, dst
-    c = dict(case, poisson_max_sweeps=16, poisson_tol=-1.0)
-    m = c.get("sweep_block") or 8
     for precision in ("fp64", "fp32", "fp16store"):
+        shapes = launch_shapes(case, precision, tune)
+        print(f"[counters] launch_shapes {precision} {shapes['sweep_block']} {shapes['sweep_waves']} "
+              f"{shapes['stage_rows']}", file=sys.stderr, flush=True)
+        c = dict(case, poisson_max_sweeps=16, poisson_tol=-1.0, **shapes)
+        m = c["sweep_block"]
         s = Solver(c, precision=precision)
         s.time_sweeps(launches * m)
         s.step(3)  # the stage kernels of a step (with 16-sweep solves)
@@ -569,8 +606,9 @@ def main():
                     help="sweep cap of the warm-started initial potential solve (the run fails if it is reached)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 forms (FP32 and FP16 storage)")
-    ap.add_argument("--sweep-block", type=int, default=0,
-                    help="potential sweeps per kernel launch (1, 2, 4, 8; 0 = library default 8)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default launch shapes instead of the autotuner's (sweeps 8 x 4 waves, "
+                         "default stage rows)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--no-time-to-freeze", action="store_true", help="skip the time-to-freeze runs")
@@ -580,7 +618,7 @@ def main():
                     help="print only the time-to-freeze runs as one JSON object")
     ap.add_argument("--batched-only", action="store_true", help="print only the batched form as one JSON object")
     ap.add_argument("--no-validation", action="store_true", help="skip the validation problems")
-    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc passes (copy calibration + sweep launches)")
     ap.add_argument("--nn-probe", action="store_true",
@@ -602,9 +640,8 @@ def main():
               flush=True)
         return
     case, desc = workload(args.workload)
-    case["sweep_block"] = args.sweep_block
     if args.counters:
-        counters_probe(case)
+        counters_probe(case, tune=not args.no_tune)
         return
     import numpy as np
 
@@ -613,7 +650,7 @@ def main():
     factor = warm.factor_for(case["ny"])
     net = warm.load((case["nx"] // factor) * (case["ny"] // factor))
     run = lambda prec: run_form(case, prec, args.steps, args.warmup, args.sweep_launches, args.workload,
-                                net, factor, args.init_cap)
+                                net, factor, args.init_cap, tune=not args.no_tune)
     f64 = run("fp64")
     ref = f64.pop("_fields")
     line = {
@@ -622,7 +659,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "nx": case["nx"], "ny": case["ny"], "precision": "fp64",
-                   "poisson_tol": case["poisson_tol"], "sweeps_per_launch": case["sweep_block"] or 8,
+                   "poisson_tol": case["poisson_tol"], "launch_shapes": f64.get("launch_shapes"),
                    "initial_potential": "learned warm start, then sweeps to the same stopping rule"},
         "sweeps_per_step": f64["sweeps_per_step"],
         "sweeps_per_step_distribution": f64["sweeps_per_step_distribution"],

@@ -111,6 +111,13 @@ typedef struct lbm_params {
                                    solve (lbm_solve_potential); 0: solve as in Algorithm 1.
                                    A batch takes it when every case has the same value (then
                                    lbm_batch_warm_start, lbm_batch_solve_potential). */
+    int stage_rows;             /* rows of the segment each workgroup of the f, flow and g
+                                   stages walks down its strip: a multiple of 4 from 4 to 512
+                                   (0: 32, lowered in steps of 4 while the flow launch would
+                                   have fewer than 2048 workgroups).  A launch-shape choice
+                                   (lbm_autotune picks one): every field is the same for any
+                                   value; only the order in which the liquid-volume partial
+                                   sums are added, hence the last bits of V_l, depends on it. */
 } lbm_params;
 
 /* Scalar fields for lbm_get_field / lbm_set_field. */
@@ -155,6 +162,11 @@ typedef struct lbm_handle lbm_handle;
    LBM_EINVAL on bad parameters (tau <= 1/2 cannot occur: every relaxation time
    is 1/2 plus a positive transport coefficient, so positivity is what is checked). */
 int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* The launch shapes a handle of these parameters takes, defaults resolved: potential sweeps
+   per launch, waves per sweep workgroup and stage segment rows.  Host only; LBM_EINVAL on bad
+   parameters or a null output. */
+int lbm_launch_shapes(const lbm_params* p, int* sweep_block, int* sweep_waves, int* stage_rows);
 
 /* Initialise (Algorithm 1, first block): psi from the tanh profile of the initial
    shape, u = u* = p = 0, T = T_g in fully liquid drops, phi a linear ramp between
@@ -246,24 +258,33 @@ int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
 int lbm_time_stages(lbm_handle* h, int n, float* ms, int cap, int* nstages);
 const char* lbm_stage_name(int k);
 
-/* Autotuner of the potential-sweep launch shape (sweeps per launch x waves per
-   workgroup) for one grid size and precision; the shape changes no result, only speed.
-   Every candidate in {2, 4, 8} x {4, 8} is initialised in the caller's device workspace
+/* Autotuner of the launch shapes for one grid size and precision; the shapes change no
+   field, only speed.  (1) Potential sweeps (sweeps per launch x waves per workgroup): every
+   candidate in {2, 4, 8} x {4, 8} is initialised in the caller's device workspace
    (`workspace`, 256-byte aligned, at least lbm_autotune_workspace_bytes() bytes; its
    contents are overwritten; the library allocates nothing), then `launches` launches of it
-   are timed twice on `stream` (the faster pass counts).  Results are cached per (nx, ny,
-   precision) for the life of the process; flags & LBM_TUNE_FORCE re-times (a cached answer
-   needs no workspace: pass NULL).  Other fields of *p only shape the timed state.
-   LBM_ESPACE if the workspace is smaller than needed.  Synchronises the stream. */
+   are timed twice on `stream` (the faster pass counts).  (2) Stage segments (stage_rows):
+   the default of lbm_params.stage_rows = 0 and those of 8, 16, 32, 64 and 128 rows below the
+   grid's height, each timed as the f, flow and g stages, `launches` launches of each, twice.
+   In both, the default (8 sweeps x 4 waves; stage_rows = 0's height, candidate 0) is kept
+   unless the fastest candidate beats it by more than 3%, so near ties do not flip the choice
+   from run to run.  Results are cached
+   per (nx, ny, precision) for the life of the process; flags & LBM_TUNE_FORCE re-times (a
+   cached answer needs no workspace: pass NULL).  Other fields of *p only shape the timed
+   state.  LBM_ESPACE if the workspace is smaller than needed.  Synchronises the stream. */
 #define LBM_TUNE_FORCE 1
 #define LBM_TUNE_MAXCAND 8
 typedef struct {
-    int sweep_block, sweep_waves;          /* the fastest shape */
+    int sweep_block, sweep_waves;          /* the fastest sweep shape */
     int cached;                            /* 1: taken from the cache */
     int ncand;
     int cand_block[LBM_TUNE_MAXCAND];
     int cand_waves[LBM_TUNE_MAXCAND];
     float us_per_sweep[LBM_TUNE_MAXCAND];  /* measured time per sweep */
+    int stage_rows;                        /* the fastest stage segment */
+    int nrows;
+    int cand_rows[LBM_TUNE_MAXCAND];
+    float us_per_step_stages[LBM_TUNE_MAXCAND];  /* f + flow + g stage time per step */
 } lbm_tune;
 int lbm_autotune_workspace_bytes(const lbm_params* p, size_t* bytes);
 int lbm_autotune(const lbm_params* p, void* workspace, size_t bytes, void* stream, int launches, int flags,

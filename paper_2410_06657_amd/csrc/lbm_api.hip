@@ -89,6 +89,7 @@ int validate(const lbm_params* p) {
         return LBM_EINVAL;
     if (p->sweep_waves != 0 && p->sweep_waves != 4 && p->sweep_waves != 8) return LBM_EINVAL;
     if (p->skip_initial_solve != 0 && p->skip_initial_solve != 1) return LBM_EINVAL;
+    if (p->stage_rows < 0 || p->stage_rows > 512 || p->stage_rows % lbm::WR) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -123,10 +124,14 @@ Dev make_dev(const lbm_params* p) {
     d.tbx = (p->nx + (64 - 2 * m) - 1) / (64 - 2 * m);
     int ry = lbm::SW_NPT * sweep_w(p);
     d.tby = (p->ny + (ry - 2 * m) - 1) / (ry - 2 * m);
-    // flow step: segments as tall as 32 rows while the launch keeps at least 2048 workgroups
+    // stage segments: the caller's height, else as tall as 32 rows while the flow launch
+    // keeps at least 2048 workgroups
     d.hx = (p->nx + lbm::WX - 1) / lbm::WX;
-    d.hseg = 32;
-    while (d.hseg > lbm::WR && (int64_t)d.hx * ((p->ny + d.hseg - 1) / d.hseg) < 2048) d.hseg -= lbm::WR;
+    d.hseg = p->stage_rows;
+    if (d.hseg == 0) {
+        d.hseg = 32;
+        while (d.hseg > lbm::WR && (int64_t)d.hx * ((p->ny + d.hseg - 1) / d.hseg) < 2048) d.hseg -= lbm::WR;
+    }
     d.hy = (p->ny + d.hseg - 1) / d.hseg;
     double tauf = p->M / lbm::CS2 + 0.5;  // Sec. 3.1
     d.omf = 1.0 / tauf;
@@ -807,6 +812,16 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
     return LBM_OK;
 }
 
+int lbm_launch_shapes(const lbm_params* p, int* sweep_block, int* sweep_waves, int* stage_rows) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!sweep_block || !sweep_waves || !stage_rows) return LBM_EINVAL;
+    *sweep_block = sweep_m(p);
+    *sweep_waves = sweep_w(p);
+    *stage_rows = make_dev(p).hseg;
+    return LBM_OK;
+}
+
 int lbm_init(const lbm_params* p, void* workspace, size_t bytes, void* stream, lbm_handle** out) {
     int rc = validate(p);
     if (rc) return rc;
@@ -961,7 +976,7 @@ struct CkptHeader {
     int32_t init_conv, lbswap;
 };
 constexpr uint64_t CKPT_MAGIC = 0x4c424d434b505431ull;  // "LBMCKPT1"
-constexpr int32_t CKPT_VERSION = 4;
+constexpr int32_t CKPT_VERSION = 5;
 
 // FNV-1a over the values of every lbm_params member (not its padding bytes).
 uint64_t params_digest(const lbm_params& p) {
@@ -986,7 +1001,7 @@ uint64_t params_digest(const lbm_params& p) {
     d(p.phi_top); d(p.phi_bot); d(p.theta_deg);
     i(p.shape); d(p.R0); d(p.xc); d(p.yc); d(p.h0);
     d(p.poisson_tol); i(p.poisson_max_sweeps); i(p.readings);
-    i(p.sweep_block); i(p.sweep_waves);
+    i(p.sweep_block); i(p.sweep_waves); i(p.stage_rows);
     return x;
 }
 
@@ -1169,6 +1184,24 @@ std::map<TuneKey, lbm_tune> tune_cache;
 
 constexpr int TUNE_M[] = {2, 4, 8};
 constexpr int TUNE_W[] = {4, 8};
+constexpr int TUNE_ROWS[] = {8, 16, 32, 64, 128};
+// A candidate replaces the default shape only when the default is slower by more than this
+// factor (the spread of repeated timings is about 1-2%): the choice then does not flip from
+// run to run on near ties.
+constexpr float TUNE_KEEP = 1.03f;
+
+// Stage segment heights worth timing for this grid: the default first, then every candidate
+// below the grid's height.
+std::vector<int> tune_rows(const lbm_params* p) {
+    lbm_params q = *p;
+    q.stage_rows = 0;
+    const Dev d0 = make_dev(&q);
+    std::vector<int> rows{d0.hseg};
+    for (int r : TUNE_ROWS)
+        if (r != d0.hseg && r < p->ny) rows.push_back(r);
+    if ((int)rows.size() > LBM_TUNE_MAXCAND) rows.resize(LBM_TUNE_MAXCAND);
+    return rows;
+}
 
 // Workspace that holds any candidate's state (the largest over the shapes tried).
 int tune_bytes(const lbm_params* p, size_t* need) {
@@ -1183,6 +1216,14 @@ int tune_bytes(const lbm_params* p, size_t* need) {
             if (rc) return rc;
             *need = std::max(*need, b);
         }
+    for (int r : tune_rows(p)) {
+        lbm_params q = *p;
+        q.stage_rows = r;
+        size_t b = 0;
+        int rc = lbm_workspace_bytes(&q, &b);
+        if (rc) return rc;
+        *need = std::max(*need, b);
+    }
     return LBM_OK;
 }
 
@@ -1223,6 +1264,43 @@ int tune_shapes(const lbm_params* p, void* ws, size_t need, hipStream_t stream, 
             }
         }
     if (rc) return rc;
+    // the default shape stays unless another is faster by more than timing noise
+    for (int k = 0; k < r.ncand; k++)
+        if (r.cand_block[k] == 8 && r.cand_waves[k] == 4 && r.us_per_sweep[k] <= TUNE_KEEP * best) {
+            r.sweep_block = 8;
+            r.sweep_waves = 4;
+        }
+    // stage segments, each timed as one f, flow and g stage (lbm_time_stages' launches)
+    best = 0.f;
+    for (int rows : tune_rows(p)) {
+        lbm_params q = *p;
+        q.stage_rows = rows;
+        q.poisson_tol = -1.0;
+        q.poisson_max_sweeps = 2;
+        q.skip_initial_solve = 0;
+        lbm_handle* h = nullptr;
+        rc = lbm_init(&q, ws, need, stream, &h);
+        if (rc) break;
+        float ms[NSTAGES], total[2] = {0.f, 0.f};
+        for (int pass = 0; pass < 2 && !rc; pass++) {
+            rc = h->prec == LBM_FP32_FP16STORE ? time_stages<float, true>(h, launches, ms)
+                 : h->prec == LBM_FP32          ? time_stages<float>(h, launches, ms)
+                                                : time_stages<double>(h, launches, ms);
+            for (int k = 0; k < NSTAGES; k++) total[pass] += ms[k];
+        }
+        lbm_destroy(h);
+        if (rc) break;
+        float us = std::min(total[0], total[1]) * 1e3f;
+        int k = r.nrows++;
+        r.cand_rows[k] = rows;
+        r.us_per_step_stages[k] = us;
+        if (k == 0 || us < best) {
+            best = us;
+            r.stage_rows = rows;
+        }
+    }
+    if (rc) return rc;
+    if (r.nrows > 0 && r.us_per_step_stages[0] <= TUNE_KEEP * best) r.stage_rows = r.cand_rows[0];  // the default
     *out = r;
     return LBM_OK;
 }

@@ -32,7 +32,7 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample", "lbm_checkpoint", "lbm_restore",
            "lbm_run_until_frozen", "lbm_batch_run_until_frozen", "lbm_autotune_workspace_bytes",
            "lbm_get_field_device", "lbm_nn_forward_noalloc", "lbm_time_stages", "lbm_stage_name",
-           "lbm_batch_warm_start", "lbm_batch_solve_potential"]
+           "lbm_batch_warm_start", "lbm_batch_solve_potential", "lbm_launch_shapes"]
 
 LBM_TUNE_FORCE = 1
 
@@ -58,10 +58,11 @@ class LbmParams(C.Structure):
         ("sweep_block", C.c_int),
         ("sweep_waves", C.c_int),
         ("skip_initial_solve", C.c_int),
+        ("stage_rows", C.c_int),
     ]
 
 
-LAUNCH_DEFAULTS = {"sweep_block": 0, "sweep_waves": 0, "skip_initial_solve": 0}
+LAUNCH_DEFAULTS = {"sweep_block": 0, "sweep_waves": 0, "skip_initial_solve": 0, "stage_rows": 0}
 
 
 class LbmDiag(C.Structure):
@@ -80,6 +81,8 @@ class LbmTune(C.Structure):
     _fields_ = [
         ("sweep_block", C.c_int), ("sweep_waves", C.c_int), ("cached", C.c_int), ("ncand", C.c_int),
         ("cand_block", C.c_int * 8), ("cand_waves", C.c_int * 8), ("us_per_sweep", C.c_float * 8),
+        ("stage_rows", C.c_int), ("nrows", C.c_int), ("cand_rows", C.c_int * 8),
+        ("us_per_step_stages", C.c_float * 8),
     ]
 
 
@@ -105,6 +108,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
         L.lbm_workspace_bytes.argtypes = [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]
+        L.lbm_launch_shapes.argtypes = [C.POINTER(LbmParams), ip, ip, ip]
         L.lbm_init.argtypes = [C.POINTER(LbmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
         L.lbm_step.argtypes = [vp, C.c_int]
         L.lbm_solve_potential.argtypes = [vp, C.c_double, C.c_int, ip, dp]
@@ -183,19 +187,29 @@ def workspace_bytes(case: dict, precision: str = "fp64") -> int:
     return n.value
 
 
+def launch_shapes(case: dict, precision: str = "fp64") -> dict:
+    """The launch shapes a solver of this case takes (lbm_launch_shapes), defaults resolved."""
+    p = make_params(case, precision)
+    m, w, r = C.c_int(), C.c_int(), C.c_int()
+    rc = lib().lbm_launch_shapes(C.byref(p), C.byref(m), C.byref(w), C.byref(r))
+    if rc != LBM_OK:
+        raise LbmError("lbm_launch_shapes", rc)
+    return {"sweep_block": m.value, "sweep_waves": w.value, "stage_rows": r.value}
+
+
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
 def tune_cache_path() -> str:
     return os.environ.get("LBM_TUNE_CACHE") or os.path.join(
-        os.path.expanduser("~"), ".cache", "paper_2410_06657_amd", "sweep_shapes.json")
+        os.path.expanduser("~"), ".cache", "paper_2410_06657_amd", "launch_shapes.json")
 
 
 def autotune(case: dict, precision: str = "fp64", launches: int = 20, force: bool = False,
              device: str = "cuda:0", persist: bool = True) -> dict:
-    """Fastest potential-sweep launch shape for this grid size and precision, from the
-    library's autotuner (lbm_autotune).  Choices are kept in the process (by the library) and
+    """Fastest launch shapes (potential-sweep shape and stage segment rows) for this grid
+    size and precision, from the library's autotuner (lbm_autotune).  Choices are kept in the process (by the library) and
     in a small JSON file (tune_cache_path(), key "nx x ny / precision"), so a shape is timed
     once per machine; force=True re-times."""
     import json
@@ -227,9 +241,12 @@ def autotune(case: dict, precision: str = "fp64", launches: int = 20, force: boo
         del ws
     if rc != LBM_OK:
         raise LbmError("lbm_autotune", rc)
-    res = {"sweep_block": out.sweep_block, "sweep_waves": out.sweep_waves,
+    res = {"sweep_block": out.sweep_block, "sweep_waves": out.sweep_waves, "stage_rows": out.stage_rows,
            "candidates": [{"sweep_block": out.cand_block[k], "sweep_waves": out.cand_waves[k],
-                           "us_per_sweep": round(float(out.us_per_sweep[k]), 4)} for k in range(out.ncand)]}
+                           "us_per_sweep": round(float(out.us_per_sweep[k]), 4)} for k in range(out.ncand)],
+           "stage_candidates": [{"stage_rows": out.cand_rows[k],
+                                 "us_per_step": round(float(out.us_per_step_stages[k]), 2)}
+                                for k in range(out.nrows)]}
     if persist:
         table[key] = res
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -53,10 +53,20 @@ def test_workspace_size_and_validation(liblbm):
     assert big > 6e9
     for bad in (dict(c, nx=1), dict(c, ny=2), dict(c, M=0.0), dict(c, sig_l=-1.0),
                 dict(c, poisson_max_sweeps=0), dict(c, shape=3), dict(c, sweep_block=3),
-                dict(c, sweep_waves=2)):
+                dict(c, sweep_waves=2), dict(c, stage_rows=-4), dict(c, stage_rows=6),
+                dict(c, stage_rows=516)):
         with pytest.raises(liblbm.LbmError) as e:
             liblbm.workspace_bytes(bad)
         assert e.value.code == liblbm.LBM_EINVAL
+    # stage segment rows: any multiple of 4 up to 512 (taller than the grid included)
+    for rows in (4, 8, 200, 512):
+        assert liblbm.workspace_bytes(dict(c, stage_rows=rows)) > 0
+    # the shapes a handle takes, defaults resolved: 32-row segments while the flow launch keeps
+    # 2048 workgroups (67 strips of 62 columns at 4096 x 2048), lower on smaller grids
+    assert liblbm.launch_shapes(inputs.drop_4096x2048()) == {"sweep_block": 8, "sweep_waves": 4, "stage_rows": 32}
+    assert liblbm.launch_shapes(c)["stage_rows"] == 4  # 3 strips x 16 segments at 128 x 64
+    assert liblbm.launch_shapes(dict(c, stage_rows=16, sweep_block=4)) == {
+        "sweep_block": 4, "sweep_waves": 4, "stage_rows": 16}
 
 
 def test_error_strings(liblbm):

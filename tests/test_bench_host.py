@@ -41,6 +41,13 @@ def test_traffic_only_for_the_profiled_source(monkeypatch, tmp_path):
     assert bench.measured_traffic("k_h_stream", "fp64", "4096x2048") == 123456
     assert bench.measured_traffic("k_h_stream", "fp32", "4096x2048") is None
     assert bench.measured_traffic("k_h_stream", "fp64", "1024x512") is None
+    # with the launch shapes it was taken with on record, other shapes get no figure
+    f.write_text(f"kernel_source_sha256 {bench.kernel_source_digest()}\n"
+                 "launch_shapes fp64 8 4 32\n"
+                 "traffic_bytes_per_launch k_h_stream fp64 123456\n")
+    same = {"sweep_block": 8, "sweep_waves": 4, "stage_rows": 32}
+    assert bench.measured_traffic("k_h_stream", "fp64", "4096x2048", same) == 123456
+    assert bench.measured_traffic("k_h_stream", "fp64", "4096x2048", dict(same, stage_rows=16)) is None
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 64)
     assert bench.measured_traffic("k_h_stream", "fp64", "4096x2048") is None
 
@@ -63,7 +70,7 @@ def test_main_line_contract(monkeypatch, capsys):
 
     import numpy as np
 
-    def fake_form(case, precision, steps, warmup, sweep_launches, workload_name, net, factor, init_cap):
+    def fake_form(case, precision, steps, warmup, sweep_launches, workload_name, net, factor, init_cap, tune=True):
         rl = {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 1.25e-4, "traffic": None}
         return {"value": 1000.0, "ms_per_step": 0.5, "sweeps_per_step": 10.0,
                 "sweeps_per_step_distribution": {"min": 9, "p10": 9.0, "p50": 10.0, "p90": 11.0, "max": 12},

@@ -1,6 +1,8 @@
-"""Autotuner of the potential-sweep launch shape: it picks one of the timed candidates, a
-repeated call is served from the cache, and a solver run with the chosen shape equals the
-default-shape run bitwise (the shape changes speed only)."""
+"""Autotuner of the launch shapes (potential-sweep shape, stage segment rows): it picks one of
+the timed candidates, a repeated call is served from the cache, and a solver run with the
+chosen shapes equals the default-shape run bitwise (the shapes change speed only; the
+liquid volume's partial sums are added in another order, so V_l may differ in its last
+bits)."""
 import numpy as np
 import pytest
 
@@ -19,16 +21,42 @@ def test_autotune_choice_cache_and_invariance(precision, tmp_path, monkeypatch):
     cands = {(k["sweep_block"], k["sweep_waves"]): k["us_per_sweep"] for k in r["candidates"]}
     assert len(cands) == 6 and all(v > 0 for v in cands.values())
     best = (r["sweep_block"], r["sweep_waves"])
-    assert cands[best] == min(cands.values())
+    # the fastest, or the default when it is within 3% of the fastest
+    assert cands[best] == min(cands.values()) or (best == (8, 4) and cands[best] <= 1.03 * min(cands.values()))
+    rows = {k["stage_rows"]: k["us_per_step"] for k in r["stage_candidates"]}
+    assert len(rows) >= 2 and all(v > 0 for v in rows.values())
+    default_rows = r["stage_candidates"][0]["stage_rows"]
+    assert default_rows == lbm.launch_shapes(c, precision)["stage_rows"]
+    chosen = r["stage_rows"]
+    assert rows[chosen] == min(rows.values()) or (chosen == default_rows and rows[chosen] <= 1.03 * min(rows.values()))
     again = lbm.autotune(c, precision, launches=10)
     assert again["cached"] == "file" and (again["sweep_block"], again["sweep_waves"]) == best
+    assert again["stage_rows"] == r["stage_rows"]
     lib_cached = lbm.autotune(c, precision, launches=10, persist=False)
     assert lib_cached["cached"] == "library"
     assert (lib_cached["sweep_block"], lib_cached["sweep_waves"]) == best
     a = lbm.Solver(c, precision)
-    b = lbm.Solver(dict(c, sweep_block=best[0], sweep_waves=best[1]), precision)
+    b = lbm.Solver(dict(c, sweep_block=best[0], sweep_waves=best[1], stage_rows=r["stage_rows"]), precision)
     a.step(6)
     b.step(6)
     assert list(a.sweep_log()) == list(b.sweep_log())
     for k in ("psi", "ux", "p", "T", "phi"):
         assert np.array_equal(a.field(k), b.field(k)), k
+
+
+@pytest.mark.parametrize("rows", [4, 8, 64, 200])
+def test_stage_rows_change_no_field(rows):
+    """Every stage segment height gives bitwise the fields of the default, over steps that
+    freeze part of the drop (segments of 200 rows: one segment covers the 128-row grid)."""
+    from paper_2410_06657_amd import lbm
+    c = inputs.scaled(inputs.drop_128x64(1), 192, 128)
+    a = lbm.Solver(c)
+    b = lbm.Solver(dict(c, stage_rows=rows))
+    a.step(25)
+    b.step(25)
+    assert list(a.sweep_log()) == list(b.sweep_log())
+    for k in ("psi", "ux", "uy", "p", "T", "H", "fs", "phi"):
+        assert np.array_equal(a.field(k), b.field(k)), k
+    da, db = a.diag(), b.diag()
+    assert db["V_l"] == pytest.approx(da["V_l"], rel=1e-13)
+
