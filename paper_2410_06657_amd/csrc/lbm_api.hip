@@ -248,7 +248,7 @@ void launch_sweep(lbm_handle* h, const lbm::SweepLaunch& a) {
     int nbt = h->dev.tbx * h->dev.tby;
     State<R>& s = h->st<R>();
     with_shape(h->swm, h->swv, [&](auto M, auto WV) {
-        // one block per tile and one for the test of the previous launch
+        // one block for the test of the previous launch and one per tile
         lbm::k_sweep_tb<M, R, WV, Tag><<<nbt + 1, 64 * WV, 0, h->stream>>>(h->dev, s, a);
     });
 }
@@ -1490,7 +1490,7 @@ void batch_sweep(lbm_batch* b, int t) {
     const int nr = (int)b->run_idx_h.size();
     if (!nr) return;
     with_shape(b->swm, b->swv, [&](auto M, auto WV) {
-        // the tiles of every running case, then one test block per running case
+        // one test block per running case, then the tiles of every running case
         lbm::kb_sweep<M, R, WV><<<b->run_blocks + nr, 64 * WV, 0, b->stream>>>(
             btable<R>(b), b->run_first_d, nr, b->lcur0_d, t, b->run_idx_d);
     });

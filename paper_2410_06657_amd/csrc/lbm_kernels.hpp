@@ -1064,10 +1064,16 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
         // OMC = 1 - omega: the collision l - omega (l - w phi) is evaluated as
         // (1 - omega) l + omega w phi, the second term once per node
         R L1[SW_NPT], L2[SW_NPT], L3[SW_NPT], L4[SW_NPT], OMC[SW_NPT], PB[SW_NPT], PH[SW_NPT];
+        // a launch of nsw < M sweeps needs only the rows within nsw of the written ones: the
+        // others stay zero (never read from memory), which changes no written node
+        auto needed = [&](int k) {
+            const int r = w * SW_NPT + k, gj = y0 + k;
+            return gj >= 0 && gj < d.ny && r >= M - a.nsw && r < M + OY + a.nsw;
+        };
 #pragma unroll
         for (int k = 0; k < SW_NPT; k++) {
             int gj = y0 + k;
-            if (gj >= 0 && gj < d.ny) {
+            if (needed(k)) {
                 int64_t n = at(d, gi, gj);
                 L1[k] = ls[n];
                 L2[k] = ls[P + n];
@@ -1087,7 +1093,7 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
 #pragma unroll
             for (int k = 0; k < SW_NPT; k++) {
                 int gj = y0 + k;
-                if (gj >= 0 && gj < d.ny) {
+                if (needed(k)) {
                     int64_t n = at(d, gi, gj);
                     D1[k] = s.dl[n];
                     D2[k] = s.dl[P + n];
@@ -1192,12 +1198,13 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
     }
 }
 
-// One launch of the single-case loop: blocks 0 .. nb-1 sweep their tiles and one extra
-// block tests the previous launch meanwhile (its partial sums are complete when the launch
-// starts), which takes the test off the launch's critical path (20.2 us against 25.4 us per
-// 8-sweep FP64 launch at 1024 x 512).  A block that starts after that test has ended the
-// loop exits at once, as the whole launch would have: its output is never used (the final
-// state is the previous launch's, or recomputed from its input).
+// One launch of the single-case loop: block 0 tests the previous launch (its partial sums are
+// complete when the launch starts) and blocks 1 .. nb sweep their tiles meanwhile, which takes
+// the test off the launch's critical path (20.2 us against 25.4 us per 8-sweep FP64 launch at
+// 1024 x 512).  Blocks are dispatched in order, so the test starts first: the blocks that
+// start after it has ended the loop exit at once, as the whole launch would have (their
+// output is never used: the final state is the previous launch's, or recomputed from its
+// input).
 // Tag only separates launches in a profile (1: the timing entry point, 2: the autotuner),
 // so they appear under their own names; the code is the same.
 template <int M, typename R, int WV, int Tag = 0>
@@ -1205,11 +1212,11 @@ __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)
 k_sweep_tb(Dev d, State<R> s, SweepLaunch a) {
     __shared__ double shm[SWEEP_SHM<M, WV>];
     const int nb = gridDim.x - 1;
-    if ((int)blockIdx.x == nb) {
+    if (blockIdx.x == 0) {
         if (a.prev_nsw > 0 && !a.devfix && !s.ctl->done) sweep_test<M, R, WV>(d, s, a, shm);
         return;
     }
-    b_sweep_tb<M, R, WV>(d, s, a, xcd_tile(blockIdx.x, nb), shm);
+    b_sweep_tb<M, R, WV>(d, s, a, xcd_tile((int)blockIdx.x - 1, nb), shm);
 }
 
 // FP32 form: renormalise every link pair (b, l) by Knuth's two-sum, b' = fl(b + l) and
@@ -2240,19 +2247,20 @@ __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(3)
                                                     int ncases, const int* __restrict__ lcur0, int t,
                                                     const int* __restrict__ idx) {
     // The launch covers the ncases cases listed in idx (the loops still running when the
-    // batch of launches was queued; first: their first sweep tiles in the launch).  The last
+    // batch of launches was queued; first: their first sweep tiles in the launch).  The first
     // ncases blocks test each case's previous launch while the others sweep (as in the
-    // single-case launch: the test is off the critical path).
+    // single-case launch: dispatched first, the tests are off the critical path and a case
+    // they end skips the blocks that start later).
     const int ntiles = gridDim.x - ncases;
     __shared__ double shm[SWEEP_SHM<M, WV>];
-    if ((int)blockIdx.x >= ntiles) {
-        const int c = idx[blockIdx.x - ntiles];
+    if ((int)blockIdx.x < ncases) {
+        const int c = idx[blockIdx.x];
         const BatchCase<R>& bc = cases[c];
         SweepLaunch a = lockstep_launch<M>(bc.s.ctl, lcur0[c], t);
         if (a.nsw > 0 && a.prev_nsw > 0 && !bc.s.ctl->done) sweep_test<M, R, WV>(bc.d, bc.s, a, shm);
         return;
     }
-    int b = xcd_tile(blockIdx.x, ntiles);
+    int b = xcd_tile((int)blockIdx.x - ncases, ntiles);
     int cc = find_case(first, ncases, b);
     const int c = idx[cc];
     const BatchCase<R>& bc = cases[c];
