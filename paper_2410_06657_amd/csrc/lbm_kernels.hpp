@@ -879,20 +879,21 @@ __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int s
     }
     if constexpr (H) h16_note_max(&s.ctl->hmax[PS_F][sp ^ 1], mx);
 }
-// fin = 1: one extra block finishes the previous step's liquid-volume sum and freezing-time
-// detector meanwhile (a launch less per step; its fields of the control block are not the
-// loop's).
+// fin = 1: one extra block, dispatched first so that it overlaps the others, finishes the
+// previous step's liquid-volume sum and freezing-time detector meanwhile (a launch less per
+// step; its fields of the control block are not the loop's).
 template <typename R, bool H = false>
 __global__ void __launch_bounds__(NT) k_f_fused_arm(Dev d, State<R> s, int sp, double tol, int min_sweeps,
                                                     int max_sweeps, int fin) {
     const int nb = gridDim.x - fin;
-    if ((int)blockIdx.x >= nb) {
+    if ((int)blockIdx.x < fin) {
         __shared__ double sh[NT / 64];
         vl_finalize_body(d, s.partials, s.ctl, 0, sh);
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
-    b_f_fused<R, H>(d, s, sp, xcd_tile(blockIdx.x, nb));
+    const int b = (int)blockIdx.x - fin;
+    if (b == 0 && threadIdx.x == 0) ctl_reset(s.ctl, tol, min_sweeps, max_sweeps);
+    b_f_fused<R, H>(d, s, sp, xcd_tile(b, nb));
 }
 
 // 1/tau_l = 1/(sigma/c_s^2 + 1/2) from the current psi and f_s (Sec. 3.4).
