@@ -224,6 +224,32 @@ def test_sweep_block_invariance():
                 assert np.array_equal(state[k], ref[k]), (m, w, k)
 
 
+@pytest.mark.parametrize("m", [1, 8])
+def test_checkerboard_link_sum_alternates_on_the_gpu(m):
+    """The sweep kernel keeps the D2Q5 scheme's undamped mode as the oracle does (its pin is in
+    test_oracle_potential.py): from random links, the checkerboard sum of the four moving links
+    changes sign exactly, sweep after sweep, in launches of one and of eight sweeps, and the
+    links after 8 sweeps equal the oracle's."""
+    c = small_drop(2, 96, 48)
+    c.update(poisson_tol=-1.0, poisson_max_sweeps=2)
+    g, o = solver(dict(c, sweep_block=m)), ob.Oracle(c)
+    rng = np.random.default_rng(7)
+    links = o.pop("l") + 1e-3 * rng.normal(size=(5, 48, 96))
+    o.set_pop("l", links)
+    g.set_pop("l", links[1:])
+    chk = (-1.0) ** (np.arange(48)[:, None] + np.arange(96)[None, :])
+    q = float((chk * g.pop("l").sum(axis=0)).sum())
+    scale = float(np.abs(links[1:]).sum())
+    assert abs(q) > 1e-5 * scale
+    for k in range(8):
+        g.solve_potential(-1.0, 1)
+        q1 = float((chk * g.pop("l").sum(axis=0)).sum())
+        assert abs(q1 + q) <= 1e-13 * scale, (k, q, q1)
+        q = q1
+    o.solve_potential(-1.0, 8)
+    assert np.allclose(g.pop("l"), o.pop("l")[1:], rtol=0, atol=1e-13)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_checkpoint_restore_continues_bitwise(precision):
     """A checkpoint taken mid-run, restored into a fresh handle of the same case, continues
