@@ -65,8 +65,7 @@ extern "C" {
    zero-velocity equilibria of their nodes' stored moments (Eqs. (18), (22), (29)), each set
    scaled by a power of two that follows its largest deviation one step earlier; the
    potential links keep the FP32 base/remainder pairs (a binary16 link could not resolve the
-   1e-8 stopping rule).  Single-case handles only (lbm_batch_init returns LBM_EINVAL);
-   lbm_get_pop decodes the binary16 sets on the host, lbm_set_pop returns LBM_EINVAL for f, h
+   1e-8 stopping rule); each case of a batch keeps its own scales.  lbm_get_pop decodes the binary16 sets on the host, lbm_set_pop returns LBM_EINVAL for f, h
    and g (a write would have to be encoded against the running scales).  Because its populations are stored
    relative to the node's stored psi, p, H and T, lbm_set_field of one of those fields also
    moves that node's f, h or g populations by the change of their zero-velocity equilibria;

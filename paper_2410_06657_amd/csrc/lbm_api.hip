@@ -1406,7 +1406,6 @@ int batch_validate(int ncases, const lbm_params* cases) {
     for (int c = 0; c < ncases; c++) {
         int rc = validate(&cases[c]);
         if (rc) return rc;
-        if (cases[c].precision == LBM_FP32_FP16STORE) return LBM_EINVAL;  // single-case form only
         if (cases[c].precision != cases[0].precision || sweep_m(&cases[c]) != sweep_m(&cases[0]) ||
             sweep_w(&cases[c]) != sweep_w(&cases[0]) ||
             cases[c].skip_initial_solve != cases[0].skip_initial_solve)
@@ -1418,11 +1417,11 @@ int batch_validate(int ncases, const lbm_params* cases) {
 BatchLayout batch_layout(int ncases, const lbm_params* cases) {
     BatchLayout L;
     size_t off = 0;
-    bool f32 = cases[0].precision == LBM_FP32;
+    const bool f32 = cases[0].precision != LBM_FP64, h16 = cases[0].precision == LBM_FP32_FP16STORE;
     for (int c = 0; c < ncases; c++) {
         L.off.push_back(off);
         Dev d = make_dev(&cases[c]);
-        off = round_up(off + (f32 ? carve<float>(d, nullptr, nullptr) : carve<double>(d, nullptr, nullptr)), ALIGN);
+        off = round_up(off + (f32 ? carve<float>(d, nullptr, nullptr, h16) : carve<double>(d, nullptr, nullptr)), ALIGN);
     }
     size_t cs = f32 ? sizeof(lbm::BatchCase<float>) : sizeof(lbm::BatchCase<double>);
     auto take = [&](size_t bytes) { size_t r = off; off = round_up(off + bytes, ALIGN); return r; };
@@ -1604,37 +1603,38 @@ int batch_sweeps(lbm_batch* b, int min_sweeps) {
     return LBM_OK;
 }
 
-// The stages before (A) and after (B) the potential loop, for buffer parity sp.
-template <typename R>
+// The stages before (A) and after (B) the potential loop, for buffer parity sp (H: the f, h
+// and g sets in binary16).
+template <typename R, bool H = false>
 void batch_stage(lbm_batch* b, int which, int sp) {
     auto tb = btable<R>(b);
     int nc = b->ncases;
     if (which == 0) {
-        lbm::kb_f_fused<R><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, sp, b->lcur_d);
+        lbm::kb_f_fused<R, H><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, sp, b->lcur_d);
     } else {
-        lbm::kb_h_fused<R><<<b->flow_blocks, NT, 0, b->stream>>>(tb, b->first_flow, nc, sp, b->lcur_d);
-        lbm::kb_g_stream<R><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, sp, b->lcur_d);
+        lbm::kb_h_fused<R, H><<<b->flow_blocks, NT, 0, b->stream>>>(tb, b->first_flow, nc, sp, b->lcur_d);
+        lbm::kb_g_stream<R, H><<<b->fg_blocks, NT, 0, b->stream>>>(tb, b->first_fg, nc, sp, b->lcur_d);
         lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 0);
     }
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int batch_run_stage(lbm_batch* b, int which) {
     if (b->graphs) {
         BHIP(b, hipGraphLaunch(b->gexec[which][b->sp], b->stream));
     } else {
-        batch_stage<R>(b, which, b->sp);
+        batch_stage<R, H>(b, which, b->sp);
         BHIP(b, hipGetLastError());
     }
     return LBM_OK;
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int batch_capture(lbm_batch* b) {
     for (int which = 0; which < 2; which++)
         for (int sp = 0; sp < 2; sp++) {
             BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            batch_stage<R>(b, which, sp);
+            batch_stage<R, H>(b, which, sp);
             BHIP(b, hipStreamEndCapture(b->stream, &b->graph[which][sp]));
             BHIP(b, hipGraphInstantiate(&b->gexec[which][sp], b->graph[which][sp], nullptr, nullptr, 0));
         }
@@ -1642,7 +1642,7 @@ int batch_capture(lbm_batch* b) {
     return LBM_OK;
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     int nc = b->ncases;
     auto& cases = bcases<R>(b);
@@ -1653,7 +1653,7 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     Ctl* ctl = (Ctl*)(ws + L.ctl);
     for (int c = 0; c < nc; c++) {
         cases[c].d = b->dev[c];
-        carve<R>(b->dev[c], ws + L.off[c], &cases[c].s);
+        carve<R>(b->dev[c], ws + L.off[c], &cases[c].s, H);
         cases[c].s.ctl = ctl + c;
         fn[c] = b->node_blocks;
         fs[c] = b->sweep_blocks;
@@ -1676,7 +1676,7 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     BHIP(b, hipMemcpyAsync(b->lcur_d, b->lcur.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream));
     for (int c = 0; c < nc; c++) k_ctl_zero<<<1, 1, 0, b->stream>>>(ctl + c);
     auto tb = btable<R>(b);
-    lbm::kb_init<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
+    lbm::kb_init<R, H><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
     lbm::kb_oml<R><<<b->node_blocks, NT, 0, b->stream>>>(tb, b->first_node, nc, 0, b->lcur_d);
     BHIP(b, hipGetLastError());
     b->init_conv.assign(nc, 1);
@@ -1692,17 +1692,17 @@ int batch_init_impl(lbm_batch* b, char* ws, const BatchLayout& L) {
     lbm::kb_vl_finalize<R><<<nc, NT, 0, b->stream>>>(tb, 1);
     BHIP(b, hipGetLastError());
     BHIP(b, hipStreamSynchronize(b->stream));
-    if (b->stream) return batch_capture<R>(b);
+    if (b->stream) return batch_capture<R, H>(b);
     return LBM_OK;
 }
 
-template <typename R>
+template <typename R, bool H = false>
 int batch_step_impl(lbm_batch* b) {
-    int rc = batch_run_stage<R>(b, 0);
+    int rc = batch_run_stage<R, H>(b, 0);
     if (rc) return rc;
     rc = batch_sweeps<R>(b, 1);
     if (rc) return rc;
-    rc = batch_run_stage<R>(b, 1);
+    rc = batch_run_stage<R, H>(b, 1);
     if (rc) return rc;
     b->sp ^= 1;
     b->step++;
@@ -1791,7 +1791,9 @@ int lbm_batch_init(int ncases, const lbm_params* cases, void* workspace, size_t 
         delete b;
         return LBM_EHIP;
     }
-    rc = b->prec == LBM_FP32 ? batch_init_impl<float>(b, ws, L) : batch_init_impl<double>(b, ws, L);
+    rc = b->prec == LBM_FP32_FP16STORE ? batch_init_impl<float, true>(b, ws, L)
+         : b->prec == LBM_FP32          ? batch_init_impl<float>(b, ws, L)
+                                        : batch_init_impl<double>(b, ws, L);
     if (rc) {
         lbm_batch_destroy(b);
         return rc;
@@ -1804,7 +1806,9 @@ int lbm_batch_step(lbm_batch* b, int n) {
     if (!b) return LBM_ESTATE;
     if (n < 0) return LBM_EINVAL;
     for (int k = 0; k < n; k++) {
-        int rc = b->prec == LBM_FP32 ? batch_step_impl<float>(b) : batch_step_impl<double>(b);
+        int rc = b->prec == LBM_FP32_FP16STORE ? batch_step_impl<float, true>(b)
+                 : b->prec == LBM_FP32          ? batch_step_impl<float>(b)
+                                                : batch_step_impl<double>(b);
         if (rc) return rc;
     }
     return LBM_OK;
@@ -1818,7 +1822,9 @@ int lbm_batch_run_until_frozen(lbm_batch* b, int max_steps, int* steps_done) {
         bool all = true;
         for (int c = 0; c < b->ncases; c++) all = all && b->frozen_sp[c] >= 0;
         if (all) break;
-        int rc = b->prec == LBM_FP32 ? batch_step_impl<float>(b) : batch_step_impl<double>(b);
+        int rc = b->prec == LBM_FP32_FP16STORE ? batch_step_impl<float, true>(b)
+                 : b->prec == LBM_FP32          ? batch_step_impl<float>(b)
+                                                : batch_step_impl<double>(b);
         if (rc) return rc;
         // freezing detector of every case, after this step's liquid-volume update
         BHIP(b, hipMemcpyAsync(b->ctl_h, b->ctl_d, sizeof(Ctl) * b->ncases, hipMemcpyDeviceToHost, b->stream));
@@ -1841,7 +1847,7 @@ int lbm_batch_diagnostics(lbm_batch* b, lbm_diag* per_case) {
     int worst = LBM_OK;
     for (int c = 0; c < b->ncases; c++) {
         lbm_handle h;
-        if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+        if (b->prec != LBM_FP64) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
         h.log = b->log[c];
         h.last_sweeps = b->log[c].empty() ? 0 : b->log[c].back();
         h.last_resid = b->ctl_h[c].resid;
@@ -1858,7 +1864,7 @@ int lbm_batch_get_field(lbm_batch* b, int c, int field, double* dst) {
     if (!b) return LBM_ESTATE;
     if (c < 0 || c >= b->ncases) return LBM_EINVAL;
     lbm_handle h;
-    if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+    if (b->prec != LBM_FP64) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
     int rc = lbm_get_field(&h, field, dst);
     h.hctl = nullptr;
     return rc;
@@ -1990,7 +1996,7 @@ int lbm_batch_nn_sample(lbm_batch* b, int c, int factor, float* x, float* t) {
     if (!b) return LBM_ESTATE;
     if (c < 0 || c >= b->ncases || !x || !t) return LBM_EINVAL;
     lbm_handle h;
-    if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+    if (b->prec != LBM_FP64) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
     if (!coarse_ok(&h, factor)) return LBM_EINVAL;
     int rc = lbm_nn_features(&h, factor, x);
     if (!rc) rc = lbm_nn_target(&h, factor, t);
@@ -2005,7 +2011,7 @@ int lbm_batch_warm_start(lbm_batch* b, lbm_nn* nnh, int coarse_rows) {
     if (coarse_rows < 1) return LBM_EINVAL;
     for (int c = 0; c < b->ncases; c++) {
         lbm_handle h;
-        if (b->prec == LBM_FP32) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
+        if (b->prec != LBM_FP64) batch_case_handle<float>(b, c, &h); else batch_case_handle<double>(b, c, &h);
         int rc = lbm_warm_start(&h, nnh, coarse_factor(h.dev.nx, h.dev.ny, coarse_rows));
         h.hctl = nullptr;
         if (rc) {
@@ -2018,7 +2024,7 @@ int lbm_batch_warm_start(lbm_batch* b, lbm_nn* nnh, int coarse_rows) {
 
 int lbm_batch_solve_potential(lbm_batch* b, int* max_sweeps_done) {
     if (!b) return LBM_ESTATE;
-    int rc = b->prec == LBM_FP32 ? batch_solve<float>(b) : batch_solve<double>(b);
+    int rc = b->prec != LBM_FP64 ? batch_solve<float>(b) : batch_solve<double>(b);
     if (rc) return rc;
     if (max_sweeps_done) {
         int k = 0;

@@ -505,16 +505,17 @@ __device__ __forceinline__ void h16_note_max(unsigned* word, float m) {
         if (u > *word) atomicMax(word, u);
     }
 }
-// Scales of one stage's read (buffer sp) and write (buffer sp ^ 1) of a set; thread 0 of
-// block 0 records the write's exponent.  The write's exponent follows the running maximum of
-// the writes into buffer sp, which no block of this launch changes (they fold into the other
-// buffer's word), so every block derives the same exponent.
+// Scales of one stage's read (buffer sp) and write (buffer sp ^ 1) of a set; thread 0 of the
+// workgroup of the case's first tile (`first`) records the write's exponent (not block 0,
+// which may serve another case or another task).  The write's exponent follows the running
+// maximum of the writes into buffer sp, which no block of this launch changes (they fold into
+// the other buffer's word), so every block derives the same exponent.
 struct H16Scales {
     float inv, sc;
 };
-__device__ __forceinline__ H16Scales h16_scales(Ctl* c, int set, int sp) {
+__device__ __forceinline__ H16Scales h16_scales(Ctl* c, int set, int sp, bool first) {
     const int eo = h16_exp(c->hmax[set][sp]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) c->hexp[set][sp ^ 1] = eo;
+    if (first && threadIdx.x == 0) c->hexp[set][sp ^ 1] = eo;
     return H16Scales{ldexpf(1.f, -c->hexp[set][sp]), ldexpf(1.f, eo)};
 }
 
@@ -554,7 +555,7 @@ struct State {
 template <typename R, bool H = false>
 __device__ __forceinline__ void b_init(const Dev& d, const State<R>& s, int tile) {
 #pragma clang fp contract(off)
-    if (H && blockIdx.x == 0 && threadIdx.x == 0)
+    if (H && tile == 0 && threadIdx.x == 0)
         for (int k = 0; k < 3; k++) s.ctl->hexp[k][0] = HS_EMAX;  // the deviations written here are 0
     int i, j;
     node_of(d, tile, i, j);
@@ -786,7 +787,7 @@ __device__ __forceinline__ void b_f_fused(const Dev& d, const State<R>& s, int s
     const int je = min(jb + d.hseg, d.ny);
     for (int c = threadIdx.x; c < AS; c += NT) L.col[c] = wrap_col(i0 - 2 + c, d.nx);
     H16Scales hs{};
-    if constexpr (H) hs = h16_scales(s.ctl, PS_F, sp);
+    if constexpr (H) hs = h16_scales(s.ctl, PS_F, sp, tile == 0);
     float mx = 0.f;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const R* psi = s.psi[sp];
@@ -1627,7 +1628,7 @@ __device__ __forceinline__ void b_h_fused(const Dev& d, const State<R>& s, int s
     const int je = min(jb + d.hseg, d.ny);
     for (int c = threadIdx.x; c < WQ; c += NT) L.col[c] = wrap_col(i0 - 3 + c, d.nx);
     H16Scales hs{};
-    if constexpr (H) hs = h16_scales(s.ctl, PS_H, sp);
+    if constexpr (H) hs = h16_scales(s.ctl, PS_H, sp, tile == 0);
     float mx = 0.f;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const R* psi = s.psi[sp ^ 1];
@@ -1819,7 +1820,7 @@ __device__ __forceinline__ void b_g_stream(const Dev& d, const State<R>& s, int 
     const int je = min(jb + d.hseg, d.ny);
     for (int c = threadIdx.x; c < AS; c += NT) L.col[c] = wrap_col(i0 - 2 + c, d.nx);
     H16Scales hs{};
-    if constexpr (H) hs = h16_scales(s.ctl, PS_G, sp);
+    if constexpr (H) hs = h16_scales(s.ctl, PS_G, sp, tile == 0);
     float mx = 0.f;
     double vl = 0.0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -2200,15 +2201,30 @@ __device__ __forceinline__ int find_case(const int* __restrict__ first, int ncas
         body<R>(bc.d, bc.s, ##__VA_ARGS__, b - first[c]);                                   \
     }
 
-LBM_BATCHED(kb_init, b_init)
 LBM_BATCHED(kb_oml, b_oml, sp)
-LBM_BATCHED(kb_f_fused, b_f_fused, sp)
 LBM_BATCHED(kb_rebase, b_rebase, lcur[c])
 LBM_BATCHED(kb_sweep_prep, b_sweep_prep)
-LBM_BATCHED(kb_h_fused, b_h_fused, sp, lcur[c])
-LBM_BATCHED(kb_g_stream, b_g_stream, sp)
 LBM_BATCHED(kb_vl0, b_vl0)
 #undef LBM_BATCHED
+
+// The same for the stage bodies that also serve the FP16-storage form (H).
+#define LBM_BATCHED_H(name, body, ...)                                                      \
+    template <typename R, bool H = false>                                                   \
+    __global__ void __launch_bounds__(NT) name(const BatchCase<R>* __restrict__ cases,      \
+                                               const int* __restrict__ first, int ncases,  \
+                                               int sp, const int* __restrict__ lcur) {     \
+        int b = xcd_tile(blockIdx.x, gridDim.x);                                            \
+        int c = find_case(first, ncases, b);                                                \
+        const BatchCase<R>& bc = cases[c];                                                  \
+        if (bc.s.ctl->frozen) return;                                                       \
+        body<R, H>(bc.d, bc.s, ##__VA_ARGS__, b - first[c]);                                \
+    }
+
+LBM_BATCHED_H(kb_init, b_init)
+LBM_BATCHED_H(kb_f_fused, b_f_fused, sp)
+LBM_BATCHED_H(kb_h_fused, b_h_fused, sp, lcur[c])
+LBM_BATCHED_H(kb_g_stream, b_g_stream, sp)
+#undef LBM_BATCHED_H
 
 // FP32 rebase of the cases whose potential loop is still running after launch t - 1 (their
 // state is in buffer (lcur0 + t) mod 3).

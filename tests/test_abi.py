@@ -87,8 +87,16 @@ def test_batch_validation(liblbm):
         arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in bad])
         n = C.c_size_t()
         assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_EINVAL
-    # the FP16-storage form is single-case only
+    # the FP16-storage form batches too (binary16 sets: smaller than the FP32 batch), but every
+    # case takes the same precision
     arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c, "fp16store") for c in (a, a)])
+    n16 = C.c_size_t()
+    assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n16)) == liblbm.LBM_OK
+    arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c, "fp32") for c in (a, a)])
+    n32 = C.c_size_t()
+    assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n32)) == liblbm.LBM_OK
+    assert n16.value < n32.value
+    arr = (liblbm.LbmParams * 2)(liblbm.make_params(a, "fp16store"), liblbm.make_params(a, "fp32"))
     n = C.c_size_t()
     assert liblbm.lib().lbm_batch_workspace_bytes(2, arr, C.byref(n)) == liblbm.LBM_EINVAL
     arr = (liblbm.LbmParams * 2)(*[liblbm.make_params(c) for c in (a, inputs.scaled(a, 64, 32))])

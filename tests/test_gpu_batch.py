@@ -1,6 +1,7 @@
 """Batched form: every case of a batch advanced with one launch per stage (stages outside
 the potential loop replayed from HIP graphs) equals its own single-case run bitwise, in
-FP64 and in FP32, and the FP64 batch equals the oracle to the FP64 bar."""
+FP64, in FP32 and with FP16 population storage, and the FP64 batch equals the oracle to the
+FP64 bar."""
 import math
 import os
 
@@ -24,7 +25,8 @@ def mixed_cases():
     ]
 
 
-@pytest.mark.parametrize("precision,shape", [("fp64", (8, 4)), ("fp32", (8, 4)), ("fp32", (4, 8))])
+@pytest.mark.parametrize("precision,shape", [("fp64", (8, 4)), ("fp32", (8, 4)), ("fp32", (4, 8)),
+                                             ("fp16store", (8, 4))])
 def test_batch_equals_single_runs(precision, shape):
     from paper_2410_06657_amd.lbm import Batch, Solver
     cases = [dict(c, sweep_block=shape[0], sweep_waves=shape[1]) for c in mixed_cases()]
@@ -73,19 +75,21 @@ def test_batch_freezing_times():
         assert d[c]["V_s"] == ds["V_s"], c
 
 
-def test_batch_run_until_frozen_matches_single_runs():
+@pytest.mark.parametrize("precision", ["fp64", "fp16store"])
+def test_batch_run_until_frozen_matches_single_runs(precision):
     """Cases freezing at different steps: each stops at its own freezing step inside the batch
-    (its workgroups idle from then on) and ends bitwise where its single-case run stops."""
+    (its workgroups idle from then on) and ends bitwise where its single-case run stops (with
+    FP16 storage too: every case keeps its own binary16 scales)."""
     from paper_2410_06657_amd.lbm import Batch, Solver
     cases = [inputs.stefan_strip(4, 24 + 8 * k, h0=8.0 + 2 * k, Ste=0.4 + 0.1 * k, rho_ratio_sl=0.9)
              for k in range(3)]
     cases.append(inputs.sessile_drop(64, 32, 10.0, 90.0, 3.0, 1.0, 0.1, 0.5, seed=5))
-    b = Batch(cases, precision="fp64")
+    b = Batch(cases, precision=precision)
     nb = b.run_until_frozen(5000)
     d = b.diag()
     steps = []
     for c, case in enumerate(cases):
-        s = Solver(case)
+        s = Solver(case, precision=precision)
         k = s.run_until_frozen(5000, 1)
         ds = s.diag()
         steps.append(k)
