@@ -478,8 +478,9 @@ def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
     """Time to freeze (R30) of a sessile drop (128 x 64 with R0 = 24, or the same drop four times
     larger, 512 x 256 with R0 = 96; theta = 90, R = 3, S = 1, Ca_E = 0.1, Ste = 0.1): FP64,
     FP32, FP32 with FP16 population storage, FP64 with the learned warm start of the initial
-    potential, and `nbatch` seeds (centre jitter) in one FP32 batch against the same seeds one
-    at a time.  Speedups are quoted with the freezing times they reach."""
+    potential, `nbatch` seeds (centre jitter) in one FP32 batch against the same seeds one
+    at a time, and the same seeds as one FP16-storage batch.  Speedups are quoted with the
+    freezing times they reach."""
     import torch
 
     from paper_2410_06657_amd import inputs, warm
@@ -539,6 +540,20 @@ def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
                            "t_fre_rel_diff_vs_fp64_seed0": abs(fb[0] - f64) / f64,
                            "t_fre_equal_to_single_runs": fb == fs}
     print(f"[bench] time to freeze: batch of {nbatch} {tb:.2f}s, one at a time {ts:.2f}s", file=sys.stderr, flush=True)
+    # the same seeds as one batch with FP16 population storage (seed 0's single run: above)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = Batch(cases, precision="fp16store")
+    b.run_until_frozen(max_steps)
+    torch.cuda.synchronize()
+    th = time.perf_counter() - t0
+    fh = [d["t_fre"] for d in b.diag()]
+    del b
+    out["batched_fp16store"] = {"cases": nbatch, "wall_s": round(th, 3),
+                                "speedup_vs_fp32_batch": round(tb / th, 3),
+                                "t_fre_rel_diff_vs_fp64_seed0": abs(fh[0] - f64) / f64,
+                                "seed0_t_fre_equal_to_single_run": fh[0] == f16}
+    print(f"[bench] time to freeze: FP16-storage batch of {nbatch} {th:.2f}s", file=sys.stderr, flush=True)
     return out
 
 
