@@ -102,7 +102,7 @@ def test_batch_run_until_frozen_matches_single_runs(precision):
     assert nb == max(steps) and len(set(steps)) > 1
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16store"])
 def test_batch_warm_start_equals_single_runs(precision):
     """Cases initialised without a solve, seeded by the learned warm start in one batch call
     (each with its own coarse factor) and solved to the stopping rule in lockstep, then stepped:
