@@ -115,6 +115,28 @@ def workload(name):
     return c, desc
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """HBM rate of a plain device-to-device copy (torch's copy kernel, `reps` copies of
+    `nbytes`, HIP events on the current stream): what a streaming kernel can reach on this
+    GPU, beside the 8 TB/s peak the rooflines are quoted against."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "avg_copy_us": round(ms * 1e3, 1),
+            "achieved": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+            "frac_of_peak": round(2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def host_cpu():
     """The host's CPU model (first "model name" of /proc/cpuinfo) and the cores this process
     may use."""
@@ -687,6 +709,7 @@ def main():
         "initial_solve": f64["initial_solve"],
         "roofline": f64["roofline"],
         "rooflines": f64["rooflines"],
+        "hbm_copy": copy_bandwidth(),
         "state": f64["state"],
     }
     if not args.no_fp32:

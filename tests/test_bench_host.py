@@ -83,6 +83,7 @@ def test_main_line_contract(monkeypatch, capsys):
                 "_fields": {"psi": np.zeros((2, 2))}}
 
     monkeypatch.setattr(bench, "run_form", fake_form)
+    monkeypatch.setattr(bench, "copy_bandwidth", lambda: {"achieved": 1.0, "unit": "GB/s"})
     monkeypatch.setitem(sys.modules, "paper_2410_06657_amd.warm",
                         types.SimpleNamespace(factor_for=lambda ny: 64, load=lambda px: None))
     import paper_2410_06657_amd
