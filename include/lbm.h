@@ -257,6 +257,14 @@ int lbm_time_sweeps(lbm_handle* h, int n, float* ms);
 int lbm_time_stages(lbm_handle* h, int n, float* ms, int cap, int* nstages);
 const char* lbm_stage_name(int k);
 
+/* Measurement (no part of the method): the HBM rate a plain streaming kernel reaches on this
+   GPU, as a reference beside the published peak for the rooflines.  Copies `bytes` from the
+   device buffer src to the device buffer dst (both 16-byte aligned, bytes a positive multiple
+   of 16; the buffers must not overlap) reps times back to back on `stream` with 16-byte loads
+   and stores, bracketed by HIP events; *ms gets the average duration of one copy.  LBM_EINVAL
+   on bad arguments.  Synchronises the stream. */
+int lbm_time_copy(void* dst, const void* src, size_t bytes, void* stream, int reps, float* ms);
+
 /* Autotuner of the launch shapes for one grid size and precision; the shapes change no
    field, only speed.  (1) Potential sweeps (sweeps per launch x waves per workgroup): every
    candidate in {2, 4, 8} x {4, 8} is initialised in the caller's device workspace

@@ -801,6 +801,21 @@ int get_pop16(lbm_handle* h, int set, double* host) {
 
 }  // namespace
 
+// Streaming copy for lbm_time_copy: each thread moves four 16-byte words per pass, all loads
+// issued before the stores.
+__global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * 256 * 4;
+    for (size_t i = (size_t)blockIdx.x * 256 * 4 + threadIdx.x; i < n; i += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (i + (size_t)k * 256 < n) v[k] = src[i + (size_t)k * 256];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (i + (size_t)k * 256 < n) dst[i + (size_t)k * 256] = v[k];
+    }
+}
+
 extern "C" {
 
 int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
@@ -1141,6 +1156,39 @@ int lbm_time_stages(lbm_handle* h, int n, float* ms, int cap, int* nstages) {
 }
 
 const char* lbm_stage_name(int k) { return k >= 0 && k < NSTAGES ? STAGE_NAMES[k] : ""; }
+
+int lbm_time_copy(void* dst, const void* src, size_t bytes, void* stream, int reps, float* ms) {
+    if (!dst || !src || !ms || reps < 1 || bytes == 0 || bytes % 16 || (uintptr_t)dst % 16 ||
+        (uintptr_t)src % 16)
+        return LBM_EINVAL;
+    const char *d0 = (const char*)dst, *s0 = (const char*)src;
+    if (d0 < s0 + bytes && s0 < d0 + bytes) return LBM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = bytes / 16;
+    // enough workgroups for 8 per CU, each thread moving 4 x 16 B per pass
+    const int blocks = (int)std::min<size_t>(2048, (n + 4 * 256 - 1) / (4 * 256));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LBM_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LBM_EHIP;
+    }
+    k_copy16<<<blocks, 256, 0, st>>>((const uint4*)src, (uint4*)dst, n);  // warm-up
+    hipError_t err = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && err == hipSuccess; r++) {
+        k_copy16<<<blocks, 256, 0, st>>>((const uint4*)src, (uint4*)dst, n);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return LBM_EHIP;
+    *ms = t / (float)reps;
+    return LBM_OK;
+}
 
 int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;

@@ -32,7 +32,7 @@ SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_solve_potential",
            "lbm_warm_start", "lbm_set_warm_start", "lbm_batch_nn_sample", "lbm_checkpoint", "lbm_restore",
            "lbm_run_until_frozen", "lbm_batch_run_until_frozen", "lbm_autotune_workspace_bytes",
            "lbm_get_field_device", "lbm_nn_forward_noalloc", "lbm_time_stages", "lbm_stage_name",
-           "lbm_batch_warm_start", "lbm_batch_solve_potential", "lbm_launch_shapes"]
+           "lbm_batch_warm_start", "lbm_batch_solve_potential", "lbm_launch_shapes", "lbm_time_copy"]
 
 LBM_TUNE_FORCE = 1
 
@@ -109,6 +109,7 @@ def lib():
         vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
         L.lbm_workspace_bytes.argtypes = [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]
         L.lbm_launch_shapes.argtypes = [C.POINTER(LbmParams), ip, ip, ip]
+        L.lbm_time_copy.argtypes = [vp, vp, C.c_size_t, vp, C.c_int, C.POINTER(C.c_float)]
         L.lbm_init.argtypes = [C.POINTER(LbmParams), vp, C.c_size_t, vp, C.POINTER(vp)]
         L.lbm_step.argtypes = [vp, C.c_int]
         L.lbm_solve_potential.argtypes = [vp, C.c_double, C.c_int, ip, dp]
@@ -195,6 +196,22 @@ def launch_shapes(case: dict, precision: str = "fp64") -> dict:
     if rc != LBM_OK:
         raise LbmError("lbm_launch_shapes", rc)
     return {"sweep_block": m.value, "sweep_waves": w.value, "stage_rows": r.value}
+
+
+def time_copy(nbytes: int, reps: int = 10, device: str = "cuda:0") -> float:
+    """Average milliseconds of one device-to-device copy of nbytes by the library's streaming
+    copy kernel (lbm_time_copy), on fresh torch buffers."""
+    import torch
+    with torch.cuda.device(torch.device(device)):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+        dst = torch.empty_like(src)
+        ms = C.c_float()
+        rc = lib().lbm_time_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream), int(reps), C.byref(ms))
+        del src, dst
+    if rc != LBM_OK:
+        raise LbmError("lbm_time_copy", rc)
+    return ms.value
 
 
 def _dp(a):

@@ -69,6 +69,19 @@ def test_workspace_size_and_validation(liblbm):
         "sweep_block": 4, "sweep_waves": 4, "stage_rows": 16}
 
 
+def test_time_copy_argument_checks(liblbm):
+    """The copy-bandwidth entry rejects misaligned, odd-sized and overlapping buffers before
+    touching the device."""
+    import ctypes as C
+    L, ms = liblbm.lib(), C.c_float()
+    ok_src, ok_dst = C.c_void_p(1 << 20), C.c_void_p(1 << 24)
+    assert L.lbm_time_copy(C.c_void_p((1 << 24) + 8), ok_src, 4096, None, 1, C.byref(ms)) == liblbm.LBM_EINVAL
+    assert L.lbm_time_copy(ok_dst, ok_src, 4100, None, 1, C.byref(ms)) == liblbm.LBM_EINVAL
+    assert L.lbm_time_copy(ok_dst, ok_src, 0, None, 1, C.byref(ms)) == liblbm.LBM_EINVAL
+    assert L.lbm_time_copy(ok_dst, ok_src, 4096, None, 0, C.byref(ms)) == liblbm.LBM_EINVAL
+    assert L.lbm_time_copy(C.c_void_p((1 << 20) + 2048), ok_src, 4096, None, 1, C.byref(ms)) == liblbm.LBM_EINVAL
+
+
 def test_error_strings(liblbm):
     L = liblbm.lib()
     for code in range(0, -7, -1):
