@@ -104,3 +104,12 @@ def test_host_cpu():
     h = bench.host_cpu()
     assert h["nproc"] >= 1
     assert h["cpu_model"] is None or isinstance(h["cpu_model"], str)
+
+
+def test_untuned_launch_shapes_are_the_library_defaults():
+    """bench.py --no-tune takes the shapes a handle takes by default (host-only query), the
+    same the committed counter summary records for 4096 x 2048."""
+    from paper_2410_06657_amd import inputs
+    shapes = bench.launch_shapes(inputs.drop_4096x2048(), "fp64", tune=False)
+    assert shapes == {"sweep_block": 8, "sweep_waves": 4, "stage_rows": 32}
+    assert bench.shape_key(shapes) == (8, 4, 32)
