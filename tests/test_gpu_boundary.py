@@ -118,3 +118,39 @@ def test_restore_rejects_foreign_or_corrupt_images():
     with pytest.raises(LbmError) as e:
         other.restore(bytes(img))
     assert e.value.code == -1
+
+
+def test_checkpoint_refuses_other_stage_rows():
+    """The stage segment height is part of the parameter digest: an image restores only into a
+    handle with the same value (the fields would not change, but the volume sums' order would)."""
+    from paper_2410_06657_amd.lbm import LbmError, Solver
+    c = small_drop(6)
+    a = Solver(dict(c, stage_rows=8))
+    a.step(2)
+    img = a.checkpoint()
+    with pytest.raises(LbmError) as e:
+        Solver(dict(c, stage_rows=16)).restore(img)
+    assert e.value.code == -1
+    b = Solver(dict(c, stage_rows=8))
+    b.restore(img)
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.field("psi"), b.field("psi"))
+
+
+def test_time_copy_copies_and_times():
+    """lbm_time_copy moves the bytes it is given (the last of its copies is checked) and reports
+    a positive duration."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2410_06657_amd import lbm
+    n = (64 << 20) + 48  # not a multiple of the 4 x 16-byte pass of a thread
+    src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    ms = C.c_float()
+    rc = lbm.lib().lbm_time_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), n,
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream), 3, C.byref(ms))
+    assert rc == lbm.LBM_OK and ms.value > 0
+    assert torch.equal(dst, src)
