@@ -1,7 +1,9 @@
 """The 1024 x 512 sessile-drop workload (R0 = 160, Ste = 0.1, rho_l/rho_g = 10, k_s/k_l = 2)
 at its own size against the FP64 oracle: the oblate drop (R = 0.5, S = 2) at theta = 60 and
 120 degrees and the prolate drop (R = 3, S = 1) at 120 degrees, all at Ca_E = 0.3, and the
-prolate drop without a field at 90 degrees.
+prolate drop without a field at 90 degrees, with 400-sweep solves; the other 14 cases of the
+matrix (theta in {60, 90, 120} x prolate/oblate x Ca_E in {0, 0.1, 0.3}) with 100-sweep
+solves; and one drop run to its freezing time.
 
 The potential solves from the linear ramp need a few 10^5 sweeps at this size, far more than
 the oracle can afford inside the test (2.5 ms per oracle sweep on 16 cores), so both sides cap
@@ -66,6 +68,28 @@ def test_fp64_matches_oracle(theta, kind, Ca):
     dg, do = g.diag(), o.diag()
     for k in ("V_l", "V_s", "sum_psi", "op_resid"):
         assert dg[k] == pytest.approx(do[k], rel=1e-10, abs=1e-300), k
+
+
+MATRIX = [(theta, kind, Ca) for theta in (60.0, 90.0, 120.0) for kind in ("prolate", "oblate")
+          for Ca in inputs.DROP_1024_CAE]
+
+
+@pytest.mark.parametrize("theta,kind,Ca", [m for m in MATRIX if m not in CASES])
+def test_fp64_case_matrix_short(theta, kind, Ca):
+    """The other 14 cases of the 1024 x 512 matrix (theta in {60, 90, 120}, prolate and oblate,
+    Ca_E in {0, 0.1, 0.3}): ten steps with every solve capped at 100 sweeps on both sides, FP64
+    bar as above (relative L2 and max-abs <= 1e-10 per field, equal sweep logs)."""
+    from paper_2410_06657_amd.lbm import Solver
+    c = dict(inputs.drop_1024x512(theta, kind, Ca), poisson_max_sweeps=100)
+    print(f"1024x512 {kind} theta={theta} Ca_E={Ca}", flush=True)
+    g, o = Solver(c), ob.Oracle(c)
+    g.step(10)
+    o.step(10)
+    assert list(g.sweep_log()) == list(o.sweep_log())
+    e = {k: (rel_l2(g.field(k), o.field(k)), max_abs(g.field(k), o.field(k))) for k in FIELDS}
+    print({k: f"{a:.1e}/{b:.1e}" for k, (a, b) in e.items()}, flush=True)
+    bad = {k: v for k, v in e.items() if not (v[0] <= 1e-10 and v[1] <= 1e-10)}
+    assert not bad, bad
 
 
 def _freeze(case, label, chunk=50000):
