@@ -5,9 +5,11 @@ A step is one full time step of Algorithm 1 on the 4096 x 2048 sessile-drop work
 potential swept to a relative change of 1e-8, h, g and every coupling term), all in the HIP
 library; inputs are resident in HBM before the timed region.  The initial potential is seeded
 by the learned warm start and swept to the same stopping rule before anything is timed (the
-run fails if that solve reaches its cap).  Prints one JSON line with the coupled MLUPS, the
-roofline of the kernel that takes the most time per step, the rooflines of every kernel of the
-step, the precision forms at the same size, and the CPU oracle timed on a bounded sample.
+run fails if that solve reaches its cap).  Each form runs with the launch shapes the library's
+autotuner picks for it.  Prints one JSON line with the coupled MLUPS, the roofline of the kernel
+that takes the most time per step, the rooflines of every kernel of the step, a plain copy's HBM
+rate beside the peak, the precision forms at the same size, and the CPU oracle timed on a
+bounded sample.
 """
 import argparse
 import hashlib
