@@ -1782,8 +1782,15 @@ __device__ __forceinline__ void b_h_fused(const Dev& d, const State<R>& s, int s
 // Stage kernels queued behind a potential loop before the host knows its outcome are gated:
 // with lcur < 0 the kernel runs only if the loop has ended (else the host queues it again
 // once it has) and takes the final potential buffer from the control block.
+// Waves per SIMD the flow step is compiled for: three in FP32 (its 33 KB of LDS would allow
+// four; the registers alone give two, and three spill 6 of them: 406 against 420 us at
+// 4096 x 2048), two otherwise (FP16 storage would spill 18 and run 15% slower at three; the
+// FP64 window's 63 KB of LDS holds it at two workgroups per CU anyway).
+template <typename R, bool H>
+constexpr int H_WAVES = (sizeof(R) == 4 && !H) ? 3 : 2;
 template <typename R, bool H = false>
-__global__ void __launch_bounds__(NT) k_h_fused(Dev d, State<R> s, int sp, int lcur) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(H_WAVES<R, H>)))
+k_h_fused(Dev d, State<R> s, int sp, int lcur) {
     if (lcur < 0) {
         if (!s.ctl->done) return;
         lcur = s.ctl->final_buf;
