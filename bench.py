@@ -503,13 +503,14 @@ def run_validation():
 TTF_GRIDS = {"128x64": (128, 64, 24.0), "512x256": (512, 256, 96.0)}
 
 
-def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
+def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64", tune=True):
     """Time to freeze (R30) of a sessile drop (128 x 64 with R0 = 24, or the same drop four times
     larger, 512 x 256 with R0 = 96; theta = 90, R = 3, S = 1, Ca_E = 0.1, Ste = 0.1): FP64,
     FP32, FP32 with FP16 population storage, FP64 with the learned warm start of the initial
     potential, `nbatch` seeds (centre jitter) in one FP32 batch against the same seeds one
     at a time, and the same seeds as one FP16-storage batch.  Speedups are quoted with the
-    freezing times they reach."""
+    freezing times they reach.  Every run takes its precision's autotuned sweep shape (the
+    batches too; tune=False: the library defaults), which changes no result."""
     import torch
 
     from paper_2410_06657_amd import inputs, warm
@@ -529,17 +530,23 @@ def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
         return time.perf_counter() - t0, s.diag()["t_fre"], k
 
     nx, ny, r0 = TTF_GRIDS[grid]
-    mk = lambda sd: inputs.sessile_drop(nx, ny, r0, 90.0, 3.0, 1.0, 0.1, 0.1, seed=sd)
-    c = mk(0)
-    out = {"workload": f"{grid} sessile drop, R0={r0:g}, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0"}
-    t64, f64, k64 = one(c, "fp64")
+    base = lambda sd: inputs.sessile_drop(nx, ny, r0, 90.0, 3.0, 1.0, 0.1, 0.1, seed=sd)
+    # the sweep shape of each precision (timed before any clock starts)
+    sweep = {}
+    for p in ("fp64", "fp32", "fp16store"):
+        sh = launch_shapes(base(0), p, tune)
+        sweep[p] = {"sweep_block": sh["sweep_block"], "sweep_waves": sh["sweep_waves"]}
+    mk = lambda sd, p="fp32": dict(base(sd), **sweep[p])
+    out = {"workload": f"{grid} sessile drop, R0={r0:g}, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0",
+           "sweep_shapes": sweep}
+    t64, f64, k64 = one(mk(0, "fp64"), "fp64")
     print(f"[bench] time to freeze {grid}: fp64 {t64:.2f}s ({k64} steps)", file=sys.stderr, flush=True)
-    t32, f32, _ = one(c, "fp32")
+    t32, f32, _ = one(mk(0, "fp32"), "fp32")
     print(f"[bench] time to freeze {grid}: fp32 {t32:.2f}s", file=sys.stderr, flush=True)
-    t16, f16, _ = one(c, "fp16store")
+    t16, f16, _ = one(mk(0, "fp16store"), "fp16store")
     f = warm.factor_for(ny)
     net = warm.load((nx // f) * (ny // f))
-    tw, fw, _ = one(c, "fp64", net, f)
+    tw, fw, _ = one(mk(0, "fp64"), "fp64", net, f)
     out["fp64"] = {"wall_s": round(t64, 3), "t_fre": f64, "steps": k64}
     out["fp32"] = {"wall_s": round(t32, 3), "t_fre": f32, "t_fre_rel_diff": abs(f32 - f64) / f64,
                    "speedup_vs_fp64": round(t64 / t32, 3)}
@@ -572,7 +579,7 @@ def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64"):
     # the same seeds as one batch with FP16 population storage (seed 0's single run: above)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b = Batch(cases, precision="fp16store")
+    b = Batch([mk(sd, "fp16store") for sd in range(nbatch)], precision="fp16store")
     b.run_until_frozen(max_steps)
     torch.cuda.synchronize()
     th = time.perf_counter() - t0
@@ -680,7 +687,8 @@ def main():
         print(json.dumps(finite_or_null(run_batched(args.batched_steps, 2)), allow_nan=False), flush=True)
         return
     if args.time_to_freeze_only:
-        print(json.dumps(finite_or_null(run_time_to_freeze(grid=args.time_to_freeze_grid)), allow_nan=False),
+        print(json.dumps(finite_or_null(run_time_to_freeze(grid=args.time_to_freeze_grid, tune=not args.no_tune)),
+                         allow_nan=False),
               flush=True)
         return
     case, desc = workload(args.workload)
@@ -729,7 +737,7 @@ def main():
                 k: float(np.linalg.norm(cur[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-300)) for k in ref}
             line["forms"][prec] = r
     if not args.no_time_to_freeze:
-        line["time_to_freeze"] = run_time_to_freeze(grid=args.time_to_freeze_grid)
+        line["time_to_freeze"] = run_time_to_freeze(grid=args.time_to_freeze_grid, tune=not args.no_tune)
     if not args.no_validation:
         line["validation"] = run_validation()
     if not args.no_warm:

@@ -99,9 +99,9 @@ typedef struct lbm_params {
     double poisson_tol;         /* relative sweep-to-sweep change that ends a solve; < 0: fixed count */
     int poisson_max_sweeps;     /* cap per solve */
     unsigned readings;          /* LBM_R_* bits */
-    int sweep_block;            /* potential sweeps per kernel launch: 1, 2, 4 or 8 (0: 8).
-                                   A launch keeps every sweep's residual, so the stopping
-                                   sweep is the same for any value. */
+    int sweep_block;            /* potential sweeps per kernel launch: 1, 2, 4, 8 or 16 (0: 8;
+                                   16 only with sweep_waves 8).  A launch keeps every sweep's
+                                   residual, so the stopping sweep is the same for any value. */
     int sweep_waves;            /* 64-lane waves per sweep workgroup, 4 or 8 (0: 4): the
                                    region a workgroup sweeps is 64 x (8 * sweep_waves) nodes.
                                    Results do not depend on it (nor on sweep_block). */

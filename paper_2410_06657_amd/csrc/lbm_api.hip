@@ -85,9 +85,11 @@ int validate(const lbm_params* p) {
     if (!(p->latent >= 0) || p->poisson_max_sweeps < 1) return LBM_EINVAL;
     if (p->shape != 0 && p->shape != 1) return LBM_EINVAL;
     if (p->sweep_block != 0 && p->sweep_block != 1 && p->sweep_block != 2 && p->sweep_block != 4 &&
-        p->sweep_block != 8)
+        p->sweep_block != 8 && p->sweep_block != 16)
         return LBM_EINVAL;
     if (p->sweep_waves != 0 && p->sweep_waves != 4 && p->sweep_waves != 8) return LBM_EINVAL;
+    // 16 sweeps shrink a 64-row tile to 32 written rows; a 32-row tile would write none
+    if (p->sweep_block == 16 && p->sweep_waves != 8) return LBM_EINVAL;
     if (p->skip_initial_solve != 0 && p->skip_initial_solve != 1) return LBM_EINVAL;
     if (p->stage_rows < 0 || p->stage_rows > 512 || p->stage_rows % lbm::WR) return LBM_EINVAL;
     return LBM_OK;
@@ -108,6 +110,7 @@ void with_shape(int m, int wv, F&& f) {
         case 1: with_waves<1>(wv, f); break;
         case 2: with_waves<2>(wv, f); break;
         case 4: with_waves<4>(wv, f); break;
+        case 16: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 8>{}); break;
         default: with_waves<8>(wv, f); break;
     }
 }
@@ -295,8 +298,8 @@ int wait_test(lbm_handle* h, unsigned seq, LoopState* out) {
     const unsigned b = (unsigned)w1;
     out->done = b & 1u;
     out->conv = (b >> 1) & 1u;
-    out->fix_n = (b >> 2) & 15u;
-    out->fix_launch = (int)(b >> 6);
+    out->fix_n = (b >> 2) & 31u;  // up to 16
+    out->fix_launch = (int)(b >> 7);
     return LBM_OK;
 }
 
@@ -1230,8 +1233,9 @@ struct TuneKey {
 std::mutex tune_mu;
 std::map<TuneKey, lbm_tune> tune_cache;
 
-constexpr int TUNE_M[] = {2, 4, 8};
-constexpr int TUNE_W[] = {4, 8};
+// Sweep shapes (sweeps per launch, waves per workgroup) worth timing: 16 sweeps need the
+// 64-row tile.  Fewer launches pay where the grid is small and a launch is mostly fixed cost.
+constexpr int TUNE_MW[][2] = {{2, 4}, {2, 8}, {4, 4}, {4, 8}, {8, 4}, {8, 8}, {16, 8}};
 constexpr int TUNE_ROWS[] = {8, 16, 32, 64, 128};
 // A candidate replaces the default shape only when the default is slower by more than this
 // factor (the spread of repeated timings is about 1-2%): the choice then does not flip from
@@ -1254,16 +1258,15 @@ std::vector<int> tune_rows(const lbm_params* p) {
 // Workspace that holds any candidate's state (the largest over the shapes tried).
 int tune_bytes(const lbm_params* p, size_t* need) {
     *need = 0;
-    for (int m : TUNE_M)
-        for (int w : TUNE_W) {
-            lbm_params q = *p;
-            q.sweep_block = m;
-            q.sweep_waves = w;
-            size_t b = 0;
-            int rc = lbm_workspace_bytes(&q, &b);
-            if (rc) return rc;
-            *need = std::max(*need, b);
-        }
+    for (const auto& mw : TUNE_MW) {
+        lbm_params q = *p;
+        q.sweep_block = mw[0];
+        q.sweep_waves = mw[1];
+        size_t b = 0;
+        int rc = lbm_workspace_bytes(&q, &b);
+        if (rc) return rc;
+        *need = std::max(*need, b);
+    }
     for (int r : tune_rows(p)) {
         lbm_params q = *p;
         q.stage_rows = r;
@@ -1279,38 +1282,38 @@ int tune_shapes(const lbm_params* p, void* ws, size_t need, hipStream_t stream, 
     lbm_tune r{};
     int rc = LBM_OK;
     float best = 0.f;
-    for (int m : TUNE_M)
-        for (int w : TUNE_W) {
-            lbm_params q = *p;
-            q.sweep_block = m;
-            q.sweep_waves = w;
-            q.poisson_tol = -1.0;  // a short fixed initial solve: the timing needs no convergence
-            q.poisson_max_sweeps = 2 * m;
-            q.skip_initial_solve = 0;
-            lbm_handle* h = nullptr;
-            rc = lbm_init(&q, ws, need, stream, &h);
-            if (rc) break;
-            // launches tagged 2: a profile shows them apart from lbm_time_sweeps' (tag 1)
-            float t0 = 0.f, t1 = 0.f;
-            auto timed = [&](float* ms) {
-                return h->prec != LBM_FP64 ? time_sweeps<float, 2>(h, launches * m, ms)
-                                           : time_sweeps<double, 2>(h, launches * m, ms);
-            };
-            rc = timed(&t0);  // the first pass warms caches and code
-            if (!rc) rc = timed(&t1);
-            lbm_destroy(h);
-            if (rc) break;
-            float us = std::min(t0, t1) * 1e3f / (float)(launches * m);
-            int k = r.ncand++;
-            r.cand_block[k] = m;
-            r.cand_waves[k] = w;
-            r.us_per_sweep[k] = us;
-            if (k == 0 || us < best) {
-                best = us;
-                r.sweep_block = m;
-                r.sweep_waves = w;
-            }
+    for (const auto& mw : TUNE_MW) {
+        const int m = mw[0], w = mw[1];
+        lbm_params q = *p;
+        q.sweep_block = m;
+        q.sweep_waves = w;
+        q.poisson_tol = -1.0;  // a short fixed initial solve: the timing needs no convergence
+        q.poisson_max_sweeps = 2 * m;
+        q.skip_initial_solve = 0;
+        lbm_handle* h = nullptr;
+        rc = lbm_init(&q, ws, need, stream, &h);
+        if (rc) break;
+        // launches tagged 2: a profile shows them apart from lbm_time_sweeps' (tag 1)
+        float t0 = 0.f, t1 = 0.f;
+        auto timed = [&](float* ms) {
+            return h->prec != LBM_FP64 ? time_sweeps<float, 2>(h, launches * m, ms)
+                                       : time_sweeps<double, 2>(h, launches * m, ms);
+        };
+        rc = timed(&t0);  // the first pass warms caches and code
+        if (!rc) rc = timed(&t1);
+        lbm_destroy(h);
+        if (rc) break;
+        float us = std::min(t0, t1) * 1e3f / (float)(launches * m);
+        int k = r.ncand++;
+        r.cand_block[k] = m;
+        r.cand_waves[k] = w;
+        r.us_per_sweep[k] = us;
+        if (k == 0 || us < best) {
+            best = us;
+            r.sweep_block = m;
+            r.sweep_waves = w;
         }
+    }
     if (rc) return rc;
     // the default shape stays unless another is faster by more than timing noise
     for (int k = 0; k < r.ncand; k++)

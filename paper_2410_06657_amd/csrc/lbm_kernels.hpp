@@ -102,7 +102,7 @@ __device__ __forceinline__ void ctl_reset(Ctl* c, double tol, int min_sweeps, in
 }
 
 // Offsets into the partial-sum array (nb = blocks of a node-parallel launch).
-constexpr int SW_MAXM = 8;  // most sweeps one blocked launch performs
+constexpr int SW_MAXM = 16;  // most sweeps one blocked launch performs
 // FP32 potential base moves every REBASE_SWEEPS sweeps of a long solve (multiple of SW_MAXM)
 constexpr int REBASE_SWEEPS = 256;
 constexpr int DIAG_N = 9;  // per-tile diagnostics partials
@@ -344,6 +344,27 @@ __device__ __forceinline__ void block_sums_parked(double (&v)[N], double* sh) {
     if (t == 0)
 #pragma unroll
         for (int k = 0; k < N; k++) v[k] = sh[N * NTH + k];
+}
+// The same sums for many values (N = 2M of a 16-sweep launch), in LDS of N doubles per wave:
+// a butterfly over each wave, then thread 0 adds the waves in order.
+template <int N, int NTH>
+__device__ __forceinline__ void block_sums_waves(double (&v)[N], double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[w * N + k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            double x = sh[k];
+            for (int q = 1; q < NTH / 64; q++) x += sh[q * N + k];
+            v[k] = x;
+        }
 }
 __device__ __forceinline__ double block_max(double v, double* sh) {
 #pragma unroll
@@ -964,10 +985,12 @@ __device__ __forceinline__ void sweep_sums(const Dev& d, const State<R>& s, cons
     // of one tile at a time
     constexpr int NTH = 64 * NW;
     int b = b0 + threadIdx.x;
-    for (; b + (U - 1) * NTH < b1; b += U * NTH) {
-        double v[U][2 * M];
+    // one tile a pass for M > 8 (32 sums take as many registers as U = 2 at M = 8)
+    constexpr int UU = M > 8 ? 1 : U;
+    for (; b + (UU - 1) * NTH < b1; b += UU * NTH) {
+        double v[UU][2 * M];
 #pragma unroll
-        for (int u = 0; u < U; u++)
+        for (int u = 0; u < UU; u++)
 #pragma unroll
             for (int m = 0; m < M; m++) {
                 const double* q = pv + ((int64_t)m * nbt + b + u * NTH) * 2;
@@ -975,7 +998,7 @@ __device__ __forceinline__ void sweep_sums(const Dev& d, const State<R>& s, cons
                 v[u][2 * m + 1] = m < a.prev_nsw ? q[1] : 0.0;
             }
 #pragma unroll
-        for (int u = 0; u < U; u++)
+        for (int u = 0; u < UU; u++)
 #pragma unroll
             for (int m = 0; m < M; m++)
                 if (m < a.prev_nsw) {
@@ -990,27 +1013,43 @@ __device__ __forceinline__ void sweep_sums(const Dev& d, const State<R>& s, cons
                 acc[2 * m] += pv[((int64_t)m * nbt + b) * 2];
                 acc[2 * m + 1] += pv[((int64_t)m * nbt + b) * 2 + 1];
             }
-    block_sums_parked<2 * M, NTH>(acc, sh);
+    if constexpr (M > 8) block_sums_waves<2 * M, NTH>(acc, sh);
+    else block_sums_parked<2 * M, NTH>(acc, sh);
 }
 // The stopping rule on the summed residuals of the tested launch (thread 0 only).
 template <int M>
 __device__ __forceinline__ void sweep_decide(Ctl* c, const SweepLaunch& a, const double (&acc)[2 * M]) {
-    for (int m = 0; m < a.prev_nsw && m < M; m++) {
-        double da = acc[2 * m], pa = acc[2 * m + 1];
-        double r = da == 0.0 ? 0.0 : (pa > 0.0 ? sqrt(da) / sqrt(pa) : INFINITY);
-        int j = a.prev_k0 + m;
-        c->resid = r;
-        c->count = j;
-        int conv = c->tol >= 0.0 && j >= c->min_sweeps && r <= c->tol;
-        if (conv || j >= c->max_sweeps) {
-            c->conv = conv;
-            c->done = 1;
-            c->fix_launch = a.launch - 1;
-            c->fix_n = m + 1;
-            c->fix_k0 = a.prev_k0;
-            c->fix_nsw = a.prev_nsw;
-            break;
+    // a loop without early exits, unrolled: acc stays in registers (a run-time index would put
+    // it in scratch memory); the sweeps after the stopping one are skipped
+    const double tol = c->tol;
+    const int min_sweeps = c->min_sweeps, max_sweeps = c->max_sweeps;
+    double resid = 0.0;
+    int count = 0, seen = 0, stop = 0, conv = 0, fix_n = 0;
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        if (stop || m >= a.prev_nsw) continue;
+        const double da = acc[2 * m], pa = acc[2 * m + 1];
+        const double r = da == 0.0 ? 0.0 : (pa > 0.0 ? sqrt(da) / sqrt(pa) : INFINITY);
+        const int j = a.prev_k0 + m;
+        resid = r;
+        count = j;
+        seen = 1;
+        conv = tol >= 0.0 && j >= min_sweeps && r <= tol;
+        if (conv || j >= max_sweeps) {
+            stop = 1;
+            fix_n = m + 1;
         }
+    }
+    if (!seen) return;
+    c->resid = resid;
+    c->count = count;
+    if (stop) {
+        c->conv = conv;
+        c->done = 1;
+        c->fix_launch = a.launch - 1;
+        c->fix_n = fix_n;
+        c->fix_k0 = a.prev_k0;
+        c->fix_nsw = a.prev_nsw;
     }
 }
 template <int M, typename R, int NW = NT / 64, int U = 2>
@@ -1024,7 +1063,11 @@ __device__ __forceinline__ void sweep_test(const Dev& d, const State<R>& s, cons
 // blocks for it (k_sweep_tb, kb_sweep).
 // Shared doubles a sweep workgroup (or the test block beside it) uses for its sums.
 template <int M, int WV>
-constexpr int SWEEP_SHM = 2 * M * 64 * WV + 2 * M;
+constexpr int SWEEP_SHM = M > 8 ? 2 * 8 * 64 * WV : 2 * M * 64 * WV + 2 * M;
+// Sweeps whose residual sums a sweep workgroup parks at once: a launch of more sweeps sums
+// and empties the parking after every eighth (LDS for all 16 would halve the occupancy).
+template <int M>
+constexpr int SW_PARK = M > 8 ? 8 : M;
 
 template <int M, typename R, int WV>
 __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, const SweepLaunch& ain, int tile,
@@ -1035,7 +1078,7 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
     __shared__ R bup[2][WV][64], bdn[2][WV][64];
     // accs: each thread's FP64 residual sums of every sweep, parked at the end of the sweep
     // instead of in registers (16 accumulators would cost the kernel a wave per SIMD)
-    constexpr int NTH = 64 * WV;
+    constexpr int NTH = 64 * WV, PK = SW_PARK<M>;
     const Ctl* c = s.ctl;
     SweepLaunch a = ain;
     if (a.devfix) {
@@ -1108,65 +1151,91 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
             }
         }
         const R wbot0 = R(2.0 * LWA * d.phi_bot), wtop0 = R(2.0 * LWA * d.phi_top);
+        // block sums of the parked values of sweeps m0 .. m0 + PK - 1: G threads per value, each
+        // adding a fixed strided subset, then a butterfly over the G lanes (a fixed order:
+        // reproducible)
+        double* pw = s.partials + part_sweep(part_nb(d), nbt, a.slot);
+        auto park_sums = [&](int m0) {
+            constexpr int G0 = NTH / (2 * PK), G = G0 < 64 ? G0 : 64;
+            __syncthreads();
+            const int t = threadIdx.x;
+            if (t < 2 * PK * G) {
+                const int v = t / G, p = t % G, m = m0 + v / 2;
+                double sum = 0.0;
+                for (int q = p; q < NTH; q += G) sum += accs[v * NTH + q];
+#pragma unroll
+                for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+                if (p == 0 && m < a.nsw) pw[((int64_t)m * nbt + tile) * 2 + (v & 1)] = sum;
+            }
+        };
         double rw[SW_NPT];  // 1: the row is written by this block (inner rows inside the domain)
 #pragma unroll
         for (int k = 0; k < SW_NPT; k++) {
             const int r = w * SW_NPT + k, gj = y0 + k;
             rw[k] = (r >= M && r < M + OY && gj >= 0 && gj < d.ny) ? 1.0 : 0.0;
         }
+        // M > 8: chunks of PK sweeps, each unrolled as a launch of PK sweeps
+#pragma unroll 1
+        for (int c0 = 0; c0 < M; c0 += PK) {
 #pragma unroll
-        for (int m = 0; m < M; m++) {
-            if (m >= a.nsw) break;
-            R A1[SW_NPT], A2[SW_NPT], A3[SW_NPT], A4[SW_NPT];
-            double accd = 0.0, accp = 0.0;
+            for (int mm = 0; mm < PK; mm++) {
+                const int m = c0 + mm;
+                if (m >= a.nsw) break;
+                R A1[SW_NPT], A2[SW_NPT], A3[SW_NPT], A4[SW_NPT];
+                double accd = 0.0, accp = 0.0;
 #pragma unroll
-            for (int k = 0; k < SW_NPT; k++) {
-                // PH: phi of the current links (from the load, then from the previous sweep)
-                R e = lw * PH[k];
-                R q = fma_r(-OMC[k], e, e);  // omega w phi
-                // explicit fused multiply-adds, so every launch shape rounds them the same way
-                A1[k] = fma_r(OMC[k], L1[k], q);
-                A2[k] = fma_r(OMC[k], L2[k], q);
-                A3[k] = fma_r(OMC[k], L3[k], q);
-                A4[k] = fma_r(OMC[k], L4[k], q);
-            }
-            int par = m & 1;
-            bup[par][w][lane] = A2[SW_NPT - 1];
-            bdn[par][w][lane] = A4[0];
-            __syncthreads();
-            R below = w > 0 ? bup[par][w - 1][lane] : R(0);
-            R above = w < WV - 1 ? bdn[par][w + 1][lane] : R(0);
-#pragma unroll
-            for (int k = 0; k < SW_NPT; k++) {
-                int gj = y0 + k;
-                R n1 = lane_up(A1[k]);
-                R n3 = lane_down(A3[k]);
-                R n2 = k > 0 ? A2[k - 1] : below;
-                R n4 = k < SW_NPT - 1 ? A4[k + 1] : above;
-                if constexpr (based) {
-                    n1 = n1 + D1[k];
-                    n3 = n3 + D3[k];
-                    n2 = gj == 0 ? D2[k] - A4[k] : n2 + D2[k];
-                    n4 = gj == d.ny - 1 ? D4[k] - A2[k] : n4 + D4[k];
-                } else {
-                    if (gj == 0) n2 = wbot0 - A4[k];
-                    if (gj == d.ny - 1) n4 = wtop0 - A2[k];
+                for (int k = 0; k < SW_NPT; k++) {
+                    // PH: phi of the current links (from the load, then from the previous sweep)
+                    R e = lw * PH[k];
+                    R q = fma_r(-OMC[k], e, e);  // omega w phi
+                    // explicit fused multiply-adds, so every launch shape rounds them the same way
+                    A1[k] = fma_r(OMC[k], L1[k], q);
+                    A2[k] = fma_r(OMC[k], L2[k], q);
+                    A3[k] = fma_r(OMC[k], L3[k], q);
+                    A4[k] = fma_r(OMC[k], L4[k], q);
                 }
-                L1[k] = n1;
-                L2[k] = n2;
-                L3[k] = n3;
-                L4[k] = n4;
-                const R ph = (n1 + n2 + n3 + n4) * inv;
-                // rows count with the wave-uniform weight rw[k] (1 or 0: a scalar operand, no
-                // per-node select); the column mask ownx is applied when the sums are parked
-                double dd = (double)(ph - PH[k]);
-                double pr = based ? (double)ph + (double)PB[k] : (double)ph;
-                accd = __builtin_fma(dd * rw[k], dd, accd);
-                accp = __builtin_fma(pr * rw[k], pr, accp);
-                PH[k] = ph;
+                int par = mm & 1;  // = m & 1: c0 is a multiple of PK, which is even or M
+                bup[par][w][lane] = A2[SW_NPT - 1];
+                bdn[par][w][lane] = A4[0];
+                __syncthreads();
+                R below = w > 0 ? bup[par][w - 1][lane] : R(0);
+                R above = w < WV - 1 ? bdn[par][w + 1][lane] : R(0);
+#pragma unroll
+                for (int k = 0; k < SW_NPT; k++) {
+                    int gj = y0 + k;
+                    R n1 = lane_up(A1[k]);
+                    R n3 = lane_down(A3[k]);
+                    R n2 = k > 0 ? A2[k - 1] : below;
+                    R n4 = k < SW_NPT - 1 ? A4[k + 1] : above;
+                    if constexpr (based) {
+                        n1 = n1 + D1[k];
+                        n3 = n3 + D3[k];
+                        n2 = gj == 0 ? D2[k] - A4[k] : n2 + D2[k];
+                        n4 = gj == d.ny - 1 ? D4[k] - A2[k] : n4 + D4[k];
+                    } else {
+                        if (gj == 0) n2 = wbot0 - A4[k];
+                        if (gj == d.ny - 1) n4 = wtop0 - A2[k];
+                    }
+                    L1[k] = n1;
+                    L2[k] = n2;
+                    L3[k] = n3;
+                    L4[k] = n4;
+                    const R ph = (n1 + n2 + n3 + n4) * inv;
+                    // rows count with the wave-uniform weight rw[k] (1 or 0: a scalar operand, no
+                    // per-node select); the column mask ownx is applied when the sums are parked
+                    double dd = (double)(ph - PH[k]);
+                    double pr = based ? (double)ph + (double)PB[k] : (double)ph;
+                    accd = __builtin_fma(dd * rw[k], dd, accd);
+                    accp = __builtin_fma(pr * rw[k], pr, accp);
+                    PH[k] = ph;
+                }
+                accs[(2 * mm) * NTH + threadIdx.x] = ownx ? accd : 0.0;
+                accs[(2 * mm + 1) * NTH + threadIdx.x] = ownx ? accp : 0.0;
+                // the parking is full and more sweeps follow: sum it (the next sweep's barrier
+                // orders these reads before its stores)
+                if constexpr (M > PK)
+                    if (mm == PK - 1 && m + 1 < a.nsw) park_sums(c0);
             }
-            accs[(2 * m) * NTH + threadIdx.x] = ownx ? accd : 0.0;
-            accs[(2 * m + 1) * NTH + threadIdx.x] = ownx ? accp : 0.0;
         }
         R* ld = s.l[a.dst];
         R* pd = s.phi[a.dst];
@@ -1183,20 +1252,7 @@ __device__ __forceinline__ void b_sweep_tb(const Dev& d, const State<R>& s, cons
                 pd[n] = based ? PB[k] + PH[k] : PH[k];
             }
         }
-        // block sums of the 2M parked values: G threads per value, each adding a fixed
-        // strided subset, then a butterfly over the G lanes (a fixed order: reproducible)
-        double* pw = s.partials + part_sweep(part_nb(d), nbt, a.slot);
-        constexpr int G0 = NTH / (2 * M), G = G0 < 64 ? G0 : 64;
-        __syncthreads();
-        const int t = threadIdx.x;
-        if (t < 2 * M * G) {
-            const int v = t / G, p = t % G;
-            double sum = 0.0;
-            for (int q = p; q < NTH; q += G) sum += accs[v * NTH + q];
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-            if (p == 0 && v / 2 < a.nsw) pw[((int64_t)(v / 2) * nbt + tile) * 2 + (v & 1)] = sum;
-        }
+        park_sums(((a.nsw - 1) / PK) * PK);
     }
 }
 
@@ -1359,10 +1415,14 @@ __global__ void __launch_bounds__(NT) k_sweep_prep(Dev d, State<R> s, int gate) 
 // every tile itself).  256 threads a block: a 1024-thread block spent about 10 us on the
 // reduction itself, at any tile count.
 constexpr int TEST_NT = 256;
+// LDS doubles of a test workgroup: the parked sums (M <= 8), else the range sums of
+// k_sweep_test, which outnumber the per-wave sums of block_sums_waves
+template <int M>
+constexpr int TEST_SHM = M > 8 ? 2 * M * TEST_RANGES : 2 * M * TEST_NT + 2 * M;
 __host__ __device__ constexpr int64_t part_test(int nb, int nbt) { return part_total(nb, nbt); }
 template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) k_sweep_test_part(Dev d, State<R> s, SweepLaunch a) {
-    __shared__ double sh[2 * M * TEST_NT + 2 * M];
+    __shared__ double sh[TEST_SHM<M>];
     if (s.ctl->done) return;
     const int nbt = d.tbx * d.tby, parts = gridDim.x;
     const int b0 = (int)((int64_t)nbt * blockIdx.x / parts), b1 = (int)((int64_t)nbt * (blockIdx.x + 1) / parts);
@@ -1375,13 +1435,13 @@ __global__ void __launch_bounds__(TEST_NT) k_sweep_test_part(Dev d, State<R> s, 
 }
 // The outcome is published to host memory the caller polls: two 64-bit words, each carrying
 // the sequence number `seq` in its upper half (the host waits for both), written with
-// system-scope atomic stores: word 0 = count, word 1 = fix_launch << 6 | fix_n << 2 |
+// system-scope atomic stores: word 0 = count, word 1 = fix_launch << 7 | fix_n << 2 |
 // conv << 1 | done.
 template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, SweepLaunch a, int parts,
                                                         unsigned long long* word, unsigned seq) {
-    static_assert(TEST_RANGES <= TEST_NT, "the range sums fit the block's shared array");
-    __shared__ double sh[2 * M * TEST_NT + 2 * M];
+    static_assert(2 * M * TEST_RANGES <= TEST_SHM<M>, "the range sums fit the block's shared array");
+    __shared__ double sh[TEST_SHM<M>];
     if (!s.ctl->done) {
         if (parts > 0) {
             // range sums in block order: every thread stages a share of them in LDS (one
@@ -1417,7 +1477,7 @@ __global__ void __launch_bounds__(TEST_NT) k_sweep_test(Dev d, State<R> s, Sweep
     const Ctl* c = s.ctl;
     const unsigned long long hi = (unsigned long long)seq << 32;
     const unsigned long long w0 = hi | (unsigned)c->count;
-    const unsigned long long w1 = hi | ((unsigned)c->fix_launch << 6 | (unsigned)c->fix_n << 2 |
+    const unsigned long long w1 = hi | ((unsigned)c->fix_launch << 7 | (unsigned)c->fix_n << 2 |
                                         (unsigned)c->conv << 1 | (unsigned)c->done);
     __hip_atomic_store(&word[0], w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&word[1], w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -2312,7 +2372,7 @@ template <int M, typename R>
 __global__ void __launch_bounds__(TEST_NT) kb_sweep_test(const BatchCase<R>* __restrict__ cases,
                                                          const int* __restrict__ lcur0, int t,
                                                          const int* __restrict__ idx) {
-    __shared__ double sh[2 * M * TEST_NT + 2 * M];
+    __shared__ double sh[TEST_SHM<M>];
     const int c = idx[blockIdx.x];
     const BatchCase<R>& bc = cases[c];
     if (bc.s.ctl->done) return;

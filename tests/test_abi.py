@@ -54,7 +54,8 @@ def test_workspace_size_and_validation(liblbm):
     for bad in (dict(c, nx=1), dict(c, ny=2), dict(c, M=0.0), dict(c, sig_l=-1.0),
                 dict(c, poisson_max_sweeps=0), dict(c, shape=3), dict(c, sweep_block=3),
                 dict(c, sweep_waves=2), dict(c, stage_rows=-4), dict(c, stage_rows=6),
-                dict(c, stage_rows=516)):
+                dict(c, stage_rows=516), dict(c, sweep_block=16), dict(c, sweep_block=16, sweep_waves=4),
+                dict(c, sweep_block=32, sweep_waves=8)):
         with pytest.raises(liblbm.LbmError) as e:
             liblbm.workspace_bytes(bad)
         assert e.value.code == liblbm.LBM_EINVAL
@@ -67,6 +68,7 @@ def test_workspace_size_and_validation(liblbm):
     assert liblbm.launch_shapes(c)["stage_rows"] == 4  # 3 strips x 16 segments at 128 x 64
     assert liblbm.launch_shapes(dict(c, stage_rows=16, sweep_block=4)) == {
         "sweep_block": 4, "sweep_waves": 4, "stage_rows": 16}
+    assert liblbm.launch_shapes(dict(c, sweep_block=16, sweep_waves=8))["sweep_block"] == 16
 
 
 def test_time_copy_argument_checks(liblbm):

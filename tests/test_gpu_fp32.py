@@ -133,7 +133,7 @@ def test_fp32_population_round_trip():
 def test_fp32_sweep_block_invariance():
     c = inputs.scaled(inputs.drop_128x64(1), 96, 48)
     ref = None
-    for m, w in ((1, 4), (2, 4), (4, 4), (8, 4), (2, 8), (8, 8)):
+    for m, w in ((1, 4), (2, 4), (4, 4), (8, 4), (2, 8), (8, 8), (16, 8)):
         g = solver32(dict(c, sweep_block=m, sweep_waves=w))
         g.step(8)
         st = {k: g.field(k) for k in ("psi", "ux", "p", "T", "phi")}
