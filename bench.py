@@ -90,6 +90,10 @@ def shape_key(shapes):
     return (int(shapes["sweep_block"]), int(shapes["sweep_waves"]), int(shapes["stage_rows"]))
 
 
+# the autotuner's timings by (nx, ny, precision), for the report
+TUNE_TIMINGS = {}
+
+
 def launch_shapes(case, precision, tune=True):
     """Launch shapes for a grid and precision: the library's autotuner (timed here, not taken
     from a file), or the library's defaults with tune=False."""
@@ -98,6 +102,10 @@ def launch_shapes(case, precision, tune=True):
         return defaults(case, precision)
     from paper_2410_06657_amd.lbm import autotune
     r = autotune(dict(case, poisson_max_sweeps=2000), precision, launches=10, persist=False)
+    TUNE_TIMINGS[(case["nx"], case["ny"], precision)] = {
+        "us_per_sweep": {f"{k['sweep_block']}x{k['sweep_waves']}": round(k["us_per_sweep"], 3)
+                         for k in r["candidates"]},
+        "us_per_step_stages": {str(k["stage_rows"]): round(k["us_per_step"], 2) for k in r["stage_candidates"]}}
     return {"sweep_block": r["sweep_block"], "sweep_waves": r["sweep_waves"], "stage_rows": r["stage_rows"]}
 
 
@@ -287,6 +295,7 @@ def run_form(case, precision, steps, warmup, sweep_launches, workload_name, net,
         "initial_solve": {"sweeps": int(k_init), "seconds": round(init_s, 2), "start": "learned warm start",
                           "converged": True},
         "launch_shapes": shapes,
+        "autotune_timings": TUNE_TIMINGS.get((case["nx"], case["ny"], precision)),
         "roofline": rooflines[dominant], "rooflines": rooflines,
         "state": {"step": d["step"], "V_s": d["V_s"], "height": d["height"], "nonfinite": d["nonfinite"],
                   "op_resid_over_ramp": d["op_resid"] / d["op_resid_ramp"] if d["op_resid_ramp"] else None},
@@ -538,7 +547,8 @@ def run_time_to_freeze(nbatch=8, max_steps=1000000, grid="128x64", tune=True):
         sweep[p] = {"sweep_block": sh["sweep_block"], "sweep_waves": sh["sweep_waves"]}
     mk = lambda sd, p="fp32": dict(base(sd), **sweep[p])
     out = {"workload": f"{grid} sessile drop, R0={r0:g}, theta=90, R=3, S=1, Ca_E=0.1, Ste=0.1, seed 0",
-           "sweep_shapes": sweep}
+           "sweep_shapes": sweep,
+           "autotune_us_per_sweep": {p: (TUNE_TIMINGS.get((nx, ny, p)) or {}).get("us_per_sweep") for p in sweep}}
     t64, f64, k64 = one(mk(0, "fp64"), "fp64")
     print(f"[bench] time to freeze {grid}: fp64 {t64:.2f}s ({k64} steps)", file=sys.stderr, flush=True)
     t32, f32, _ = one(mk(0, "fp32"), "fp32")
