@@ -1233,9 +1233,11 @@ struct TuneKey {
 std::mutex tune_mu;
 std::map<TuneKey, lbm_tune> tune_cache;
 
-// Sweep shapes (sweeps per launch, waves per workgroup) worth timing: 16 sweeps need the
-// 64-row tile.  Fewer launches pay where the grid is small and a launch is mostly fixed cost.
-constexpr int TUNE_MW[][2] = {{2, 4}, {2, 8}, {4, 4}, {4, 8}, {8, 4}, {8, 8}, {16, 8}};
+// Sweep shapes (sweeps per launch, waves per workgroup) worth timing.  Not 16 x 8: it is
+// cheaper per sweep in back-to-back launches on small grids, which is what the tuner times,
+// but a solve of a few sweeps loses with it (a coarser stopping launch, longer
+// recomputations): 512 x 256 froze 14% slower with it.
+constexpr int TUNE_MW[][2] = {{2, 4}, {2, 8}, {4, 4}, {4, 8}, {8, 4}, {8, 8}};
 constexpr int TUNE_ROWS[] = {8, 16, 32, 64, 128};
 // A candidate replaces the default shape only when the default is slower by more than this
 // factor (the spread of repeated timings is about 1-2%): the choice then does not flip from

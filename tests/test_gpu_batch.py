@@ -26,7 +26,7 @@ def mixed_cases():
 
 
 @pytest.mark.parametrize("precision,shape", [("fp64", (8, 4)), ("fp32", (8, 4)), ("fp32", (4, 8)),
-                                             ("fp16store", (8, 4)), ("fp64", (16, 8))])
+                                             ("fp16store", (8, 4)), ("fp64", (16, 8)), ("fp32", (16, 8))])
 def test_batch_equals_single_runs(precision, shape):
     from paper_2410_06657_amd.lbm import Batch, Solver
     cases = [dict(c, sweep_block=shape[0], sweep_waves=shape[1]) for c in mixed_cases()]

@@ -105,17 +105,20 @@ def test_thousand_steps_128x64():
     assert dg["V_s"] > 10  # the drop is freezing
 
 
+@pytest.mark.parametrize("shape", [(0, 0), (16, 8)], ids=["default", "m16"])
 @pytest.mark.parametrize("nx,ny", [(100, 37), (70, 45), (64, 3), (2, 16)])
-def test_ragged_and_degenerate_grids(nx, ny):
+def test_ragged_and_degenerate_grids(nx, ny, shape):
     """Grids that leave partial tiles (x not a multiple of 64, y not of 4), the smallest
-    height the walls allow (ny = 3) and the narrowest periodic width (nx = 2)."""
+    height the walls allow (ny = 3) and the narrowest periodic width (nx = 2), with the default
+    sweep shape and with 16-sweep launches (a 64 x 64 region writing 32 x 32: the x wrap and
+    the walls fall inside one region)."""
     if nx >= 32 and ny >= 16:
         c = inputs.sessile_drop(nx, ny, min(nx, ny) / 3, 60.0, 3.0, 1.0, 0.2, 0.2, seed=7)
     else:
         c = inputs.stefan_strip(nx, ny, h0=ny / 2, Ste=0.2, rho_ratio_sl=0.9)
         inputs.set_electric(c, 2.0, 3.0, 0.0, 1.0)
     c.update(poisson_tol=1e-10)
-    g, o = solver(c), ob.Oracle(c)
+    g, o = solver(dict(c, sweep_block=shape[0], sweep_waves=shape[1])), ob.Oracle(c)
     g.step(25)
     o.step(25)
     assert list(g.sweep_log()) == list(o.sweep_log())

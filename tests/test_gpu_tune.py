@@ -19,7 +19,7 @@ def test_autotune_choice_cache_and_invariance(precision, tmp_path, monkeypatch):
     r = lbm.autotune(c, precision, launches=10, force=True)
     print(r)
     cands = {(k["sweep_block"], k["sweep_waves"]): k["us_per_sweep"] for k in r["candidates"]}
-    assert len(cands) == 7 and (16, 8) in cands and all(v > 0 for v in cands.values())
+    assert len(cands) == 6 and all(v > 0 for v in cands.values())
     best = (r["sweep_block"], r["sweep_waves"])
     # the fastest, or the default when it is within 3% of the fastest
     assert cands[best] == min(cands.values()) or (best == (8, 4) and cands[best] <= 1.03 * min(cands.values()))
