@@ -57,9 +57,11 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2410_06657_amd", "csrc", "lbm_kernels.
 
 
 def kernel_source_digest():
-    """SHA-256 of the kernel source the counters must have been taken from."""
+    """SHA-256 of the kernel source and the compiler flags the counters must have been taken
+    with (a flag such as -ffp-contract changes the code without touching the source)."""
+    from paper_2410_06657_amd.build import HIPFLAGS
     with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        return hashlib.sha256(f.read() + "\n".join(HIPFLAGS).encode()).hexdigest()
 
 
 def measured_traffic(kernel, precision, workload_name, shapes=None):

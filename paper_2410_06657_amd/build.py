@@ -8,9 +8,10 @@ LIB = os.path.join(HERE, "liblbm.so")
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # no implicit fused multiply-adds: every instantiation of a stage body (single case,
-    # batched) rounds identically; the kernels write the fused operations they want
-    "-ffp-contract=off",
+    # fused multiply-adds only within one source expression (decided by the front end, so
+    # every instantiation of a stage body, single case or batched, rounds identically); code
+    # that needs a product rounded on its own says so with `#pragma clang fp contract(off)`
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
