@@ -113,3 +113,70 @@ def test_untuned_launch_shapes_are_the_library_defaults():
     shapes = bench.launch_shapes(inputs.drop_4096x2048(), "fp64", tune=False)
     assert shapes == {"sweep_block": 8, "sweep_waves": 4, "stage_rows": 32}
     assert bench.shape_key(shapes) == (8, 4, 32)
+
+
+@pytest.mark.parametrize("grid", ["128x64", "1024x512"])
+def test_time_to_freeze_legs(monkeypatch, grid):
+    """run_time_to_freeze with stand-in solvers: every form runs the drop of the chosen grid with
+    its precision's sweep shape; the 1024 x 512 drop runs the three precision forms only, the
+    smaller ones also the warm start and the two batches; speedups are wall-time ratios."""
+    import types
+
+    import paper_2410_06657_amd
+    from paper_2410_06657_amd import lbm
+
+    made = []
+
+    class FakeSolver:
+        def __init__(self, case, precision="fp64"):
+            made.append((case["nx"], case["ny"], precision, case["sweep_block"], case["sweep_waves"]))
+            self.t = {"fp64": 100.0, "fp32": 100.01, "fp16store": 100.02}[precision]
+
+        def warm_start(self, net, factor):
+            pass
+
+        def solve_potential(self, tol, cap):
+            pass
+
+        def run_until_frozen(self, max_steps, every):
+            return 1234
+
+        def diag(self):
+            return {"t_fre": self.t}
+
+    class FakeBatch:
+        def __init__(self, cases, precision="fp32"):
+            self.n, self.t = len(cases), {"fp32": 100.01, "fp16store": 100.02}[precision]
+
+        def run_until_frozen(self, max_steps):
+            pass
+
+        def diag(self):
+            return [{"t_fre": self.t}] * self.n
+
+    shapes = {"fp64": (8, 4), "fp32": (16, 8), "fp16store": (8, 8)}
+    monkeypatch.setattr(bench, "launch_shapes", lambda case, p, tune=True: {
+        "sweep_block": shapes[p][0], "sweep_waves": shapes[p][1], "stage_rows": 32})
+    monkeypatch.setattr(lbm, "Solver", FakeSolver)
+    monkeypatch.setattr(lbm, "Batch", FakeBatch)
+    import torch
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    fake_warm = types.SimpleNamespace(factor_for=lambda ny: 4, load=lambda px: None)
+    monkeypatch.setitem(sys.modules, "paper_2410_06657_amd.warm", fake_warm)
+    monkeypatch.setattr(paper_2410_06657_amd, "warm", fake_warm, raising=False)
+    out = bench.run_time_to_freeze(nbatch=3, grid=grid)
+    nx, ny, _ = bench.TTF_GRIDS[grid]
+    assert all((c[0], c[1]) == (nx, ny) for c in made)
+    assert all((c[3], c[4]) == shapes[c[2]] for c in made)
+    assert out["sweep_shapes"]["fp32"] == {"sweep_block": 16, "sweep_waves": 8}
+    assert out["fp64"]["steps"] == 1234
+    assert out["fp32"]["t_fre_rel_diff"] == pytest.approx(1e-4)
+    assert out["fp32"]["speedup_vs_fp64"] > 0
+    if grid == "1024x512":
+        assert set(out) == {"workload", "sweep_shapes", "autotune_us_per_sweep", "fp64", "fp32", "fp16store"}
+        assert len(made) == 3
+    else:
+        assert {"warm_fp64", "batched_fp32", "batched_fp16store"} <= set(out)
+        assert out["batched_fp32"]["t_fre_equal_to_single_runs"] is True
+        assert out["batched_fp16store"]["seed0_t_fre_equal_to_single_run"] is True
+        assert len(made) == 4 + 3  # three forms, the warm start, the seeds one at a time
