@@ -512,8 +512,9 @@ def run_validation():
 
 
 TTF_GRIDS = {"128x64": (128, 64, 24.0), "512x256": (512, 256, 96.0), "1024x512": (1024, 512, 192.0)}
-# grids whose time to freeze is measured for the single-case precision forms only (a batch of 8
-# such drops, and the same seeds one at a time, would take about 25 minutes)
+# grids whose time to freeze is measured for the single-case precision forms only (at 50-70 s
+# per drop, the warm start, the two batches of 8 and the 8 seeds one at a time would add some
+# 15-20 minutes)
 TTF_FORMS_ONLY = {"1024x512"}
 
 
